@@ -1,0 +1,228 @@
+/*
+ * zxpar: exact GPU evaluation of parametric ZX scalars on MI355X (gfx950).
+ *
+ * The method (Sutcliffe & Kissinger, "Fast Classical Simulation of Quantum Circuits via
+ * Parametric Rewriting in the ZX-Calculus", QPL 2024): a Clifford+T diagram whose
+ * decomposition terms differ only by pi phases is simplified once with Boolean parameters
+ * (Section 3.1, Eq. 1), giving a parametric scalar (Section 3.2, Eq. 2-3) that is then
+ * evaluated for every assignment of its p parameters on the GPU and summed (Section 3.3,
+ * Appendix E).  Here that scalar is a "term program":
+ *
+ *     S = sqrt2^e * c * sum_{x in {0,1}^p} w^{phi(x)} * prod_j F_j(x),     w = e^{i pi/4},
+ *
+ * with F2-affine forms l(x) = const XOR parity(mask & x), node factors 1 + w^{a + b l(x)},
+ * phase-pair factors (Eq. 3), and phi a Z/8 phase polynomial.  Every step is exact: values
+ * live in Z[w] (four integer coefficients in the basis 1, w, w^2, w^3) with a shared power
+ * of sqrt2; there is no floating point anywhere on the evaluation path.
+ *
+ * Conventions for every entry point:
+ *   - return value: SIM_OK (0) or a negative SIM_E* code; no exception crosses the ABI;
+ *   - on error, sim_last_error() returns a message for the calling thread and the output
+ *     arguments are left untouched;
+ *   - pointers are host pointers unless named dev_*; "stream" is a hipStream_t passed as
+ *     void* (NULL = the null stream of the current device); outputs are caller-owned host
+ *     memory; the call returns when the output is valid;
+ *   - a sim_program is immutable after creation and owned by the library until
+ *     sim_program_free; its device image lives on the device that was current when it was
+ *     created, and it must be evaluated on that device;
+ *   - evaluations on one device are serialised by the library (a per-device lock guards
+ *     its scratch memory); programs may be created and freed from any thread.
+ */
+#ifndef ZXPAR_H
+#define ZXPAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,  /* bad argument, malformed IR or circuit text (message has the line) */
+    SIM_ERANGE = -2,  /* p above the cap, or a static bound says int128 could overflow */
+    SIM_ENOMEM = -3,  /* host or device allocation failed */
+    SIM_EDEVICE = -4, /* a HIP call failed (message names it) */
+    SIM_EBUSY = -5    /* admission refused: a memory budget would be exceeded */
+};
+
+typedef struct sim_program sim_program;
+
+/* two's complement 128-bit integer */
+typedef struct {
+    uint64_t lo;
+    int64_t hi;
+} sim_i128;
+
+/* value = (c[0] + c[1] w + c[2] w^2 + c[3] w^3) * sqrt2^sqrt2_exp.  Final results are in
+ * canonical form: zero is all-zero with exponent 0; otherwise the coefficients are not all
+ * divisible by sqrt2 (c1 = c3 and c0 = c2 mod 2 fails).  flags bit 0 = RAW: a partial sum
+ * over assignments without the program's constant c and sqrt2^e (sim_eval_range). */
+typedef struct {
+    sim_i128 c[4];
+    int32_t sqrt2_exp;
+    uint32_t flags;
+} sim_zomega;
+
+#define SIM_ZOMEGA_RAW 1u
+
+/* A query on a Clifford+T circuit (Section 2.2).  AMPLITUDE: <y|C|0^n> with y_i =
+ * out_bits[i] (0/1 bytes, n_qubits of them).  MARGINAL: P(qubit = value) =
+ * <0^n| C^dag (|value><value|_qubit (x) I) C |0^n>, the doubled diagram of Fig. 3. */
+enum { SIM_QUERY_AMPLITUDE = 0, SIM_QUERY_MARGINAL = 1 };
+typedef struct {
+    uint32_t kind;
+    uint32_t n_qubits;
+    const uint8_t *out_bits;
+    uint32_t qubit;
+    uint32_t value;
+} sim_query;
+
+/* p_cap: refuse (SIM_ERANGE) programs with more parameters (0 = 48).
+ * eliminate_constraints: 1 (default when opts is NULL) substitutes away every parameter
+ * fixed by a parity constraint of the simplified diagram (a factor that is 0 or 2), so the
+ * program has p' <= p parameters and 2^p' terms; 0 keeps them as 0/2-valued factors. */
+typedef struct {
+    uint32_t p_cap;
+    uint32_t eliminate_constraints;
+    uint32_t reserved[6];
+} sim_compile_opts;
+
+typedef struct {
+    uint32_t n_params;      /* p: terms of the program = 2^p */
+    uint32_t n_forms;
+    uint32_t n_factors;     /* node + pair factors after constant folding */
+    uint32_t n_monomials;   /* variable monomials of phi */
+    int32_t sqrt2_exp;      /* e of the program's constant */
+    uint32_t walk_bits;     /* parameters enumerated inside one slice (2^walk_bits terms) */
+    uint64_t n_slices;      /* 2^(p - walk_bits): the unit of sim_eval_range */
+    uint64_t image_bytes;   /* device memory held by the program */
+    double log2_terms;      /* p */
+    uint32_t n_eval_params; /* parameters the kernel enumerates (p plus one per pair factor) */
+    uint32_t is_zero;       /* the program is identically zero (a constant factor vanished) */
+    double compile_seconds; /* host time spent in sim_compile (0 for IR programs) */
+    uint32_t t_count;       /* T-like spiders before parameterisation (sim_compile only) */
+    uint32_t n_constraints; /* parameters removed by constraint elimination */
+    double ops_per_term;    /* int32 lane operations per term of the evaluation algorithm,
+                               counted from the packed program (the roofline's work unit) */
+} sim_info;
+
+/* launch shape of the evaluation kernels; zero fields take the library's choice */
+typedef struct {
+    uint32_t block_threads;   /* 64..1024, multiple of 64 */
+    uint32_t blocks_per_cu;   /* resident blocks per compute unit in the persistent grid */
+    uint32_t walk_bits;       /* upper bound on the Gray-walk length log2 */
+    uint32_t chunk_log2;      /* batch: log2 of terms per work item */
+} sim_tuning;
+
+/* Selects the device (hipSetDevice) and creates the library's state for it.  Optional:
+ * every entry point initialises the current device on first use. */
+int sim_init(int device);
+
+/* Parses a "zxir 1" term program and uploads its packed image to the current device.
+ * Text layout (whitespace-separated, '#' starts a comment, sections in this order):
+ *     zxir 1
+ *     p <p>
+ *     forms <F>   then F lines  f <const 0|1> <mask, hex; bit i = parameter x_i>
+ *     nodes <N>   then N lines  n <form> <a> <b>            1 + w^{a + b l(x)}
+ *     pairs <Q>   then Q lines  q <form1> <form2> <a> <b>   Eq. 3 with Psi = a pi/4 + pi l1,
+ *                                                           Phi = b pi/4 + pi l2
+ *     lin <K>     then K lines  l <c> <form>                phi += c l(x)
+ *     mono <M>    then M lines  m <c> <d> <v_1> .. <v_d>    phi += c x_v1 .. x_vd
+ *     scalar <c0> <c1> <c2> <c3> <e>                        c = c0 + c1 w + c2 w^2 + c3 w^3
+ *     end
+ * The text need not be NUL-terminated.  SIM_EINVAL on a malformed text (message names the
+ * line), SIM_ERANGE when p > 62 or the static bound (sum of |term| over all terms) could
+ * exceed int128. */
+int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out);
+
+/* Host-side compiler (Section 3): circuit text -> ZX diagram closed with |0^n> and the
+ * query's effect -> parametric Clifford simplification with one Boolean parameter per
+ * remaining T-like spider -> term program, uploaded like sim_program_from_ir.  opts may be
+ * NULL.  SIM_EINVAL on a circuit or query error, SIM_ERANGE when p exceeds the cap. */
+int sim_compile(const char *circuit_text, size_t len, const sim_query *q,
+                const sim_compile_opts *opts, sim_program **out);
+
+int sim_program_info(const sim_program *prog, sim_info *out);
+
+/* Host only (no device needed): parses and packs an IR text and reports what
+ * sim_program_from_ir would create, without uploading anything.  Same errors. */
+int sim_ir_info(const char *ir_text, size_t len, sim_info *out);
+
+/* Host only: runs the compiler of sim_compile and writes the resulting IR text into buf
+ * (cap bytes, NUL-terminated; *len_out receives the full length, SIM_ERANGE if it does not
+ * fit).  info (may be NULL) receives what sim_program_info would report. */
+int sim_compile_to_ir(const char *circuit_text, size_t len, const sim_query *q,
+                      const sim_compile_opts *opts, char *buf, size_t cap, size_t *len_out,
+                      sim_info *info);
+
+/* Writes the program's IR text (as parsed or as compiled, before packing) into buf (cap
+ * bytes, NUL-terminated when it fits); *len_out receives the full length.  SIM_ERANGE
+ * when cap is too small (nothing written). */
+int sim_program_ir(const sim_program *prog, char *buf, size_t cap, size_t *len_out);
+
+/* Assignment order of slices: slice s covers the 2^walk_bits assignments whose index, read
+ * in the order perm[0..p-1] (bit j of the index is parameter perm[j]), lies in
+ * [s << walk_bits, (s + 1) << walk_bits).  perm must hold p entries. */
+int sim_program_layout(const sim_program *prog, int32_t *perm, uint32_t cap);
+
+/* The whole hot path for one program: sum over all 2^p assignments on the GPU, times the
+ * constant, in canonical form. */
+int sim_eval_amplitude(const sim_program *prog, void *stream, sim_zomega *out);
+
+/* As sim_eval_amplitude, and *kernel_ms receives the duration of the evaluation kernel
+ * alone, measured with HIP events recorded on `stream` right before and after its launch
+ * (the finaliser and the result copy are outside the bracket). */
+int sim_eval_timed(const sim_program *prog, void *stream, sim_zomega *out, float *kernel_ms);
+
+/* Raw partial sum over slices [first_slice, first_slice + n_slices) (flags = RAW): for
+ * checkpoint/resume and sharding.  Partials over disjoint slices add exactly; finish with
+ * sim_finalize. */
+int sim_eval_range(const sim_program *prog, uint64_t first_slice, uint64_t n_slices,
+                   void *stream, sim_zomega *raw);
+
+/* Applies the program's constant and sqrt2 power to a raw sum and canonicalises it (on
+ * the device). */
+int sim_finalize(const sim_program *prog, const sim_zomega *raw, void *stream, sim_zomega *out);
+
+/* Many programs of uneven size in one persistent launch: work items of 2^chunk_log2 terms
+ * are pulled from a device queue; per-item partials are summed per program in a fixed
+ * order, so each result is bit-identical to sim_eval_amplitude.  t may be NULL. */
+int sim_eval_batch(const sim_program *const *progs, size_t n, void *stream,
+                   const sim_tuning *t, sim_zomega *out);
+
+/* Same as sim_eval_batch, but the launch sequence (queue reset, persistent kernel,
+ * finaliser, result copy) is captured once into a hipGraph held by the plan and replayed
+ * by sim_batch_plan_run.  The plan keeps the programs' device images referenced; the
+ * programs must outlive the plan. */
+typedef struct sim_batch_plan sim_batch_plan;
+int sim_batch_plan_create(const sim_program *const *progs, size_t n, const sim_tuning *t,
+                          void *stream, sim_batch_plan **out);
+int sim_batch_plan_run(sim_batch_plan *plan, void *stream, sim_zomega *out);
+void sim_batch_plan_free(sim_batch_plan *plan);
+
+/* Continuous batching primitive: evaluates, in one launch, the next slice range of each
+ * active request.  first_slice[i] and n_slices[i] select the range of progs[i]; the raw
+ * partials are written to raw[i].  Used by the serving loop, which adds partials exactly
+ * and finalises a request when its slices are done. */
+int sim_eval_ranges(const sim_program *const *progs, const uint64_t *first_slice,
+                    const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
+                    sim_zomega *raw);
+
+/* Adds two raw partials of the same program exactly (host, int128 with overflow check). */
+int sim_raw_add(const sim_zomega *a, const sim_zomega *b, sim_zomega *out);
+
+void sim_program_free(sim_program *prog);
+
+/* thread-local message of the last failing call on this thread ("" if none) */
+const char *sim_last_error(void);
+
+/* number of compute units of the current device (0 if unknown) */
+int sim_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZXPAR_H */

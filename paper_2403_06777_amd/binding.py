@@ -1,0 +1,352 @@
+"""ctypes binding of libzxpar.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does nothing but convert
+Python values to C arguments and back; all evaluation happens in the library's HIP kernels.
+The library is loaded from this package directory; if it has not been built, importing a
+function raises instead of falling back to anything else.
+
+Scalars are returned as ``((c0, c1, c2, c3), e)`` meaning (c0 + c1 w + c2 w^2 + c3 w^3) *
+sqrt2^e with w = e^{i pi/4}; raw partial sums as ``(c0, c1, c2, c3)``.
+"""
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzxpar.so")
+
+SIM_OK = 0
+SIM_EINVAL = -1
+SIM_ERANGE = -2
+SIM_ENOMEM = -3
+SIM_EDEVICE = -4
+SIM_EBUSY = -5
+SIM_ZOMEGA_RAW = 1
+SIM_QUERY_AMPLITUDE = 0
+SIM_QUERY_MARGINAL = 1
+
+_CODES = {SIM_EINVAL: "SIM_EINVAL", SIM_ERANGE: "SIM_ERANGE", SIM_ENOMEM: "SIM_ENOMEM",
+          SIM_EDEVICE: "SIM_EDEVICE", SIM_EBUSY: "SIM_EBUSY"}
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_CODES.get(code, code)}: {message}")
+        self.code = code
+
+
+class sim_i128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_int64)]
+
+    def value(self) -> int:
+        return (self.hi << 64) | self.lo
+
+    @classmethod
+    def of(cls, v: int) -> "sim_i128":
+        if not -(1 << 127) <= v < (1 << 127):
+            raise OverflowError("value does not fit int128")
+        return cls(v & ((1 << 64) - 1), v >> 64)
+
+
+class sim_zomega(ctypes.Structure):
+    _fields_ = [("c", sim_i128 * 4), ("sqrt2_exp", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+    def coeffs(self) -> Tuple[int, int, int, int]:
+        return tuple(self.c[k].value() for k in range(4))
+
+
+class sim_query(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("n_qubits", ctypes.c_uint32),
+                ("out_bits", ctypes.POINTER(ctypes.c_uint8)), ("qubit", ctypes.c_uint32),
+                ("value", ctypes.c_uint32)]
+
+
+class sim_compile_opts(ctypes.Structure):
+    _fields_ = [("p_cap", ctypes.c_uint32), ("eliminate_constraints", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
+
+
+class sim_info(ctypes.Structure):
+    _fields_ = [("n_params", ctypes.c_uint32), ("n_forms", ctypes.c_uint32),
+                ("n_factors", ctypes.c_uint32), ("n_monomials", ctypes.c_uint32),
+                ("sqrt2_exp", ctypes.c_int32), ("walk_bits", ctypes.c_uint32),
+                ("n_slices", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64),
+                ("log2_terms", ctypes.c_double), ("n_eval_params", ctypes.c_uint32),
+                ("is_zero", ctypes.c_uint32), ("compile_seconds", ctypes.c_double),
+                ("t_count", ctypes.c_uint32), ("n_constraints", ctypes.c_uint32),
+                ("ops_per_term", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class sim_tuning(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("walk_bits", ctypes.c_uint32), ("chunk_log2", ctypes.c_uint32)]
+
+
+_P = ctypes.c_void_p
+_lib = None
+
+# (name, restype, argtypes) of every entry point in include/zxpar.h
+SIGNATURES = [
+    ("sim_init", ctypes.c_int, [ctypes.c_int]),
+    ("sim_program_from_ir", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    ("sim_compile", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(sim_query),
+                                   ctypes.POINTER(sim_compile_opts), ctypes.POINTER(_P)]),
+    ("sim_program_info", ctypes.c_int, [_P, ctypes.POINTER(sim_info)]),
+    ("sim_ir_info", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(sim_info)]),
+    ("sim_compile_to_ir", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(sim_query),
+                                         ctypes.POINTER(sim_compile_opts), ctypes.c_char_p, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(sim_info)]),
+    ("sim_program_ir", ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sim_program_layout", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32]),
+    ("sim_eval_amplitude", ctypes.c_int, [_P, _P, ctypes.POINTER(sim_zomega)]),
+    ("sim_eval_timed", ctypes.c_int, [_P, _P, ctypes.POINTER(sim_zomega), ctypes.POINTER(ctypes.c_float)]),
+    ("sim_eval_range", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, _P, ctypes.POINTER(sim_zomega)]),
+    ("sim_finalize", ctypes.c_int, [_P, ctypes.POINTER(sim_zomega), _P, ctypes.POINTER(sim_zomega)]),
+    ("sim_eval_batch", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, _P, ctypes.POINTER(sim_tuning),
+                                      ctypes.POINTER(sim_zomega)]),
+    ("sim_batch_plan_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(sim_tuning), _P,
+                                             ctypes.POINTER(_P)]),
+    ("sim_batch_plan_run", ctypes.c_int, [_P, _P, ctypes.POINTER(sim_zomega)]),
+    ("sim_batch_plan_free", None, [_P]),
+    ("sim_eval_ranges", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
+                                       ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_raw_add", ctypes.c_int, [ctypes.POINTER(sim_zomega), ctypes.POINTER(sim_zomega),
+                                   ctypes.POINTER(sim_zomega)]),
+    ("sim_program_free", None, [_P]),
+    ("sim_last_error", ctypes.c_char_p, []),
+    ("sim_device_cus", ctypes.c_int, []),
+]
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SIM_OK:
+        raise SimError(rc, lib().sim_last_error().decode(errors="replace"))
+
+
+def _stream(stream) -> Optional[int]:
+    """hipStream_t from None (null stream), an int handle or a torch stream"""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    handle = getattr(stream, "cuda_stream", None)
+    if handle is None:
+        raise TypeError("stream must be None, an int handle or a torch.cuda.Stream")
+    return handle
+
+
+def _scalar(z: sim_zomega):
+    return z.coeffs(), z.sqrt2_exp
+
+
+def _query(kind: int, n_qubits: int, out_bits: Optional[Sequence[int]] = None, qubit: int = 0,
+           value: int = 0):
+    q = sim_query()
+    q.kind = kind
+    q.n_qubits = n_qubits
+    keep = None
+    if out_bits is not None:
+        keep = (ctypes.c_uint8 * max(1, n_qubits))(*[int(b) for b in out_bits])
+        q.out_bits = ctypes.cast(keep, ctypes.POINTER(ctypes.c_uint8))
+    q.qubit = qubit
+    q.value = value
+    return q, keep
+
+
+def amplitude_query(out_bits: str):
+    return _query(SIM_QUERY_AMPLITUDE, len(out_bits), [1 if ch == "1" else 0 for ch in out_bits])
+
+
+def marginal_query(n_qubits: int, qubit: int, value: int):
+    return _query(SIM_QUERY_MARGINAL, n_qubits, None, qubit, value)
+
+
+def _opts(p_cap: int = 0, eliminate_constraints: bool = True):
+    o = sim_compile_opts()
+    o.p_cap = p_cap
+    o.eliminate_constraints = 1 if eliminate_constraints else 0
+    return o
+
+
+def _tuning(t: Optional[dict]):
+    if not t:
+        return None
+    s = sim_tuning()
+    for k, v in t.items():
+        setattr(s, k, int(v))
+    return ctypes.byref(s)
+
+
+# ------------------------------------------------------------------ entry points
+
+def sim_init(device: int = 0):
+    _check(lib().sim_init(device))
+
+
+def sim_program_from_ir(ir_text: str) -> int:
+    data = ir_text.encode()
+    h = _P()
+    _check(lib().sim_program_from_ir(data, len(data), ctypes.byref(h)))
+    return h.value
+
+
+def sim_compile(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True) -> int:
+    q, _keep = query
+    data = circuit_text.encode()
+    h = _P()
+    o = _opts(p_cap, eliminate_constraints)
+    _check(lib().sim_compile(data, len(data), ctypes.byref(q), ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def sim_program_info(prog: int) -> dict:
+    out = sim_info()
+    _check(lib().sim_program_info(prog, ctypes.byref(out)))
+    return out.as_dict()
+
+
+def sim_ir_info(ir_text: str) -> dict:
+    data = ir_text.encode()
+    out = sim_info()
+    _check(lib().sim_ir_info(data, len(data), ctypes.byref(out)))
+    return out.as_dict()
+
+
+def sim_compile_to_ir(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True):
+    q, _keep = query
+    data = circuit_text.encode()
+    o = _opts(p_cap, eliminate_constraints)
+    n = ctypes.c_size_t()
+    info = sim_info()
+    _check(lib().sim_compile_to_ir(data, len(data), ctypes.byref(q), ctypes.byref(o), None, 0,
+                                   ctypes.byref(n), ctypes.byref(info)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().sim_compile_to_ir(data, len(data), ctypes.byref(q), ctypes.byref(o), buf, n.value + 1,
+                                   ctypes.byref(n), None))
+    return buf.value.decode(), info.as_dict()
+
+
+def sim_program_ir(prog: int) -> str:
+    n = ctypes.c_size_t()
+    _check(lib().sim_program_ir(prog, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().sim_program_ir(prog, buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def sim_program_layout(prog: int) -> List[int]:
+    p = sim_program_info(prog)["n_params"]
+    arr = (ctypes.c_int32 * max(1, p))()
+    _check(lib().sim_program_layout(prog, arr, p))
+    return list(arr[:p])
+
+
+def sim_eval_amplitude(prog: int, stream=None):
+    out = sim_zomega()
+    _check(lib().sim_eval_amplitude(prog, _stream(stream), ctypes.byref(out)))
+    return _scalar(out)
+
+
+def sim_eval_timed(prog: int, stream=None):
+    """returns (scalar, kernel_ms)"""
+    out = sim_zomega()
+    ms = ctypes.c_float()
+    _check(lib().sim_eval_timed(prog, _stream(stream), ctypes.byref(out), ctypes.byref(ms)))
+    return _scalar(out), ms.value
+
+
+def sim_eval_range(prog: int, first_slice: int, n_slices: int, stream=None):
+    out = sim_zomega()
+    _check(lib().sim_eval_range(prog, first_slice, n_slices, _stream(stream), ctypes.byref(out)))
+    return out.coeffs()
+
+
+def _raw(coeffs) -> sim_zomega:
+    z = sim_zomega()
+    for k in range(4):
+        z.c[k] = sim_i128.of(int(coeffs[k]))
+    z.flags = SIM_ZOMEGA_RAW
+    return z
+
+
+def sim_finalize(prog: int, raw_coeffs, stream=None):
+    raw = _raw(raw_coeffs)
+    out = sim_zomega()
+    _check(lib().sim_finalize(prog, ctypes.byref(raw), _stream(stream), ctypes.byref(out)))
+    return _scalar(out)
+
+
+def sim_raw_add(a, b):
+    za, zb, out = _raw(a), _raw(b), sim_zomega()
+    _check(lib().sim_raw_add(ctypes.byref(za), ctypes.byref(zb), ctypes.byref(out)))
+    return out.coeffs()
+
+
+def _prog_array(progs):
+    return (_P * max(1, len(progs)))(*progs)
+
+
+def sim_eval_batch(progs: Sequence[int], stream=None, tuning: Optional[dict] = None):
+    n = len(progs)
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_eval_batch(_prog_array(progs), n, _stream(stream), _tuning(tuning), outs))
+    return [_scalar(outs[i]) for i in range(n)]
+
+
+def sim_eval_ranges(progs: Sequence[int], first_slices: Sequence[int], n_slices: Sequence[int], stream=None,
+                    tuning: Optional[dict] = None):
+    n = len(progs)
+    firsts = (ctypes.c_uint64 * max(1, n))(*first_slices)
+    counts = (ctypes.c_uint64 * max(1, n))(*n_slices)
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_eval_ranges(_prog_array(progs), firsts, counts, n, _stream(stream), _tuning(tuning), outs))
+    return [outs[i].coeffs() for i in range(n)]
+
+
+def sim_batch_plan_create(progs: Sequence[int], tuning: Optional[dict] = None, stream=None) -> int:
+    h = _P()
+    _check(lib().sim_batch_plan_create(_prog_array(progs), len(progs), _tuning(tuning), _stream(stream),
+                                       ctypes.byref(h)))
+    return h.value
+
+
+def sim_batch_plan_run(plan: int, n: int, stream=None):
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_batch_plan_run(plan, _stream(stream), outs))
+    return [_scalar(outs[i]) for i in range(n)]
+
+
+def sim_batch_plan_free(plan: int):
+    lib().sim_batch_plan_free(plan)
+
+
+def sim_program_free(prog: int):
+    lib().sim_program_free(prog)
+
+
+def sim_last_error() -> str:
+    return lib().sim_last_error().decode(errors="replace")
+
+
+def sim_device_cus() -> int:
+    return lib().sim_device_cus()

@@ -1,0 +1,769 @@
+// C-ABI of the library: programs, single-program evaluation, ranges, batches and plans.
+//
+// Device memory: a program's packed image is uploaded once at creation.  Per-block partial
+// sums, batch work lists and result slots live in per-device scratch buffers owned by the
+// library (grown on demand, kept until the process ends) and guarded by a per-device lock.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/zxpar.h"
+#include "compiler.h"
+#include "kernels.h"
+#include "program.h"
+
+struct sim_program {
+    int device = 0;
+    IrProgram ir;
+    PackedProgram pk;
+    void *dimg = nullptr;
+    double compile_seconds = 0.0;
+    uint32_t t_count = 0;
+    uint32_t n_constraints = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(SIM_EDEVICE, std::string(#call) + " failed: " + hipGetErrorString(_e)); \
+    } while (0)
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct DeviceState {
+    bool ready = false;
+    int cus = 0;
+    std::mutex mu;
+    DevBuf partials, result, items, hdrs, imgs, firsts, counts, args, queue;
+    void *host_result = nullptr;  // pinned
+    size_t host_cap = 0;
+};
+
+constexpr int kMaxDevices = 64;
+DeviceState g_dev[kMaxDevices];
+std::mutex g_init_mu;
+
+int ensure(DevBuf &b, size_t need) {
+    if (b.cap >= need) return SIM_OK;
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.cap = 0;
+    size_t cap = std::max<size_t>(need, 4096);
+    hipError_t e = hipMalloc(&b.ptr, cap);
+    if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    b.cap = cap;
+    return SIM_OK;
+}
+
+int ensure_host(DeviceState &D, size_t need) {
+    if (D.host_cap >= need) return SIM_OK;
+    if (D.host_result) (void)hipHostFree(D.host_result);
+    D.host_result = nullptr;
+    D.host_cap = 0;
+    size_t cap = std::max<size_t>(need, 4096);
+    hipError_t e = hipHostMalloc(&D.host_result, cap, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+    D.host_cap = cap;
+    return SIM_OK;
+}
+
+int init_device(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(SIM_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    DeviceState &D = g_dev[dev];
+    if (D.ready) return SIM_OK;
+    HIP_TRY(hipSetDevice(dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    D.cus = prop.multiProcessorCount;
+    D.ready = true;
+    return SIM_OK;
+}
+
+int current_device(int *dev) {
+    HIP_TRY(hipGetDevice(dev));
+    return init_device(*dev);
+}
+
+FinalArgs final_args(const PackedProgram &pk, bool raw) {
+    FinalArgs a;
+    memset(&a, 0, sizeof a);
+    for (int k = 0; k < 4; ++k) {
+        a.c0[2 * k] = (uint64_t)pk.c0.c[k];
+        a.c0[2 * k + 1] = (uint64_t)((unsigned __int128)pk.c0.c[k] >> 64);
+    }
+    a.e = pk.e;
+    a.raw = raw ? 1u : 0u;
+    a.zero = pk.zero ? 1u : 0u;
+    return a;
+}
+
+int to_zomega(const DevResult &r, sim_zomega *out) {
+    if (r.flags & RESULT_FLAG_OVERFLOW)
+        return fail(SIM_ERANGE, "int128 overflow while applying the program constant");
+    for (int k = 0; k < 4; ++k) {
+        out->c[k].lo = r.w[2 * k];
+        out->c[k].hi = (int64_t)r.w[2 * k + 1];
+    }
+    out->sqrt2_exp = r.e;
+    out->flags = r.flags & RESULT_FLAG_RAW ? SIM_ZOMEGA_RAW : 0u;
+    return SIM_OK;
+}
+
+void zero_result(sim_zomega *out, bool raw) {
+    memset(out, 0, sizeof *out);
+    if (raw) out->flags = SIM_ZOMEGA_RAW;
+}
+
+uint32_t pick_threads(const sim_tuning *t) {
+    uint32_t th = t && t->block_threads ? t->block_threads : 256u;
+    th = std::min<uint32_t>(256u, std::max<uint32_t>(64u, th / 64 * 64));
+    return th;
+}
+
+// one evaluation of a slice range: kernel + finaliser + readback (device lock held)
+int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint64_t count, bool raw,
+                      hipStream_t stream, const sim_tuning *t, sim_zomega *out, float *kernel_ms = nullptr) {
+    const PackedProgram &pk = P->pk;
+    const uint32_t threads = pick_threads(t);
+    const uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 8u;
+    uint64_t want = (count + threads - 1) / threads;
+    uint64_t cap = (uint64_t)std::max(1, D.cus) * bpc;
+    uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+    int rc;
+    if ((rc = ensure(D.partials, (size_t)blocks * sizeof(Partial)))) return rc;
+    if ((rc = ensure(D.result, sizeof(DevResult)))) return rc;
+    if ((rc = ensure_host(D, sizeof(DevResult)))) return rc;
+    Partial *parts = (Partial *)D.partials.ptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (kernel_ms) {
+        HIP_TRY(hipEventCreate(&ev0));
+        HIP_TRY(hipEventCreate(&ev1));
+        HIP_TRY(hipEventRecord(ev0, stream));
+    }
+    HIP_TRY(launch_eval(pk.hdr, P->dimg, first, count, parts, blocks, threads, stream));
+    if (kernel_ms) HIP_TRY(hipEventRecord(ev1, stream));
+    FinalArgs fa = final_args(pk, raw);
+    HIP_TRY(launch_finalize(parts, blocks, fa, (DevResult *)D.result.ptr, stream));
+    HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (kernel_ms) {
+        HIP_TRY(hipEventElapsedTime(kernel_ms, ev0, ev1));
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    DevResult r;
+    memcpy(&r, D.host_result, sizeof r);
+    return to_zomega(r, out);
+}
+
+int finish_program(std::unique_ptr<sim_program> &P, sim_program **out) {
+    std::string err;
+    int rc = pack_program(P->ir, 12, &P->pk, &err);
+    if (rc) return fail(rc, err);
+    int dev;
+    if ((rc = current_device(&dev))) return rc;
+    P->device = dev;
+    hipError_t e = hipMalloc(&P->dimg, P->pk.blob.size());
+    if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    e = hipMemcpy(P->dimg, P->pk.blob.data(), P->pk.blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(P->dimg);
+        P->dimg = nullptr;
+        return fail(SIM_EDEVICE, std::string("hipMemcpy failed: ") + hipGetErrorString(e));
+    }
+    *out = P.release();
+    return SIM_OK;
+}
+
+int enter_device(const sim_program *P, DeviceState **D) {
+    int rc = init_device(P->device);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(P->device));
+    *D = &g_dev[P->device];
+    return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sim_last_error(void) { return g_err.c_str(); }
+
+int sim_init(int device) {
+    int rc = init_device(device);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(device));
+    return SIM_OK;
+}
+
+int sim_device_cus(void) {
+    int dev;
+    if (current_device(&dev)) return 0;
+    return g_dev[dev].cus;
+}
+
+int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out) {
+    if (!ir_text || !out) return fail(SIM_EINVAL, "null argument");
+    std::unique_ptr<sim_program> P(new (std::nothrow) sim_program());
+    if (!P) return fail(SIM_ENOMEM, "out of host memory");
+    std::string err;
+    if (!ir_parse(ir_text, len, &P->ir, &err)) return fail(SIM_EINVAL, err);
+    return finish_program(P, out);
+}
+
+int sim_compile(const char *circuit_text, size_t len, const sim_query *q, const sim_compile_opts *opts,
+                sim_program **out) {
+    if (!circuit_text || !q || !out) return fail(SIM_EINVAL, "null argument");
+    std::unique_ptr<sim_program> P(new (std::nothrow) sim_program());
+    if (!P) return fail(SIM_ENOMEM, "out of host memory");
+    CompileOptions co;
+    if (opts) {
+        if (opts->p_cap) co.p_cap = (int)opts->p_cap;
+        co.eliminate_constraints = opts->eliminate_constraints != 0;
+    }
+    CompileStats cs;
+    std::string err;
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = compile_circuit(circuit_text, len, *q, co, &P->ir, &cs, &err);
+    auto t1 = std::chrono::steady_clock::now();
+    if (rc) return fail(rc, err);
+    P->compile_seconds = std::chrono::duration<double>(t1 - t0).count();
+    P->t_count = (uint32_t)cs.t_count;
+    P->n_constraints = (uint32_t)cs.n_constraints;
+    return finish_program(P, out);
+}
+
+
+}  // extern "C"
+
+namespace {
+void fill_info(const PackedProgram &pk, double compile_seconds, uint32_t t_count, uint32_t n_constraints,
+               sim_info *out) {
+    memset(out, 0, sizeof *out);
+    out->n_params = (uint32_t)pk.p;
+    out->n_forms = (uint32_t)pk.n_forms;
+    out->n_factors = (uint32_t)pk.n_factors;
+    out->n_monomials = (uint32_t)pk.n_mono;
+    out->sqrt2_exp = pk.e;
+    out->walk_bits = (uint32_t)pk.walk_bits;
+    out->n_slices = pk.n_slices;
+    out->image_bytes = pk.blob.size();
+    out->log2_terms = (double)pk.p;
+    out->n_eval_params = pk.hdr.pe;
+    out->is_zero = pk.zero ? 1u : 0u;
+    out->compile_seconds = compile_seconds;
+    out->t_count = t_count;
+    out->n_constraints = n_constraints;
+    out->ops_per_term = pk.ops_per_term;
+}
+}  // namespace
+
+extern "C" int sim_ir_info(const char *ir_text, size_t len, sim_info *out) {
+    if (!ir_text || !out) return fail(SIM_EINVAL, "null argument");
+    IrProgram ir;
+    std::string err;
+    if (!ir_parse(ir_text, len, &ir, &err)) return fail(SIM_EINVAL, err);
+    PackedProgram pk;
+    int rc = pack_program(ir, 12, &pk, &err);
+    if (rc) return fail(rc, err);
+    fill_info(pk, 0.0, 0, 0, out);
+    return SIM_OK;
+}
+
+extern "C" int sim_compile_to_ir(const char *circuit_text, size_t len, const sim_query *q,
+                                 const sim_compile_opts *opts, char *buf, size_t cap, size_t *len_out,
+                                 sim_info *info) {
+    if (!circuit_text || !q) return fail(SIM_EINVAL, "null argument");
+    CompileOptions co;
+    if (opts) {
+        if (opts->p_cap) co.p_cap = (int)opts->p_cap;
+        co.eliminate_constraints = opts->eliminate_constraints != 0;
+    }
+    CompileStats cs;
+    std::string err;
+    IrProgram ir;
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = compile_circuit(circuit_text, len, *q, co, &ir, &cs, &err);
+    auto t1 = std::chrono::steady_clock::now();
+    if (rc) return fail(rc, err);
+    std::string s = ir_print(ir);
+    if (len_out) *len_out = s.size();
+    if (info) {
+        PackedProgram pk;
+        rc = pack_program(ir, 12, &pk, &err);
+        if (rc) return fail(rc, err);
+        fill_info(pk, std::chrono::duration<double>(t1 - t0).count(), (uint32_t)cs.t_count,
+                  (uint32_t)cs.n_constraints, info);
+    }
+    if (buf) {
+        if (cap < s.size() + 1) return fail(SIM_ERANGE, "buffer too small for the IR text");
+        memcpy(buf, s.c_str(), s.size() + 1);
+    }
+    return SIM_OK;
+}
+
+extern "C" {
+
+int sim_program_info(const sim_program *P, sim_info *out) {
+    if (!P || !out) return fail(SIM_EINVAL, "null argument");
+    fill_info(P->pk, P->compile_seconds, P->t_count, P->n_constraints, out);
+    return SIM_OK;
+}
+
+int sim_program_ir(const sim_program *P, char *buf, size_t cap, size_t *len_out) {
+    if (!P) return fail(SIM_EINVAL, "null argument");
+    std::string s = ir_print(P->ir);
+    if (len_out) *len_out = s.size();
+    if (!buf) return SIM_OK;
+    if (cap < s.size() + 1) return fail(SIM_ERANGE, "buffer too small for the IR text");
+    memcpy(buf, s.c_str(), s.size() + 1);
+    return SIM_OK;
+}
+
+int sim_program_layout(const sim_program *P, int32_t *perm, uint32_t cap) {
+    if (!P || (!perm && P->pk.p)) return fail(SIM_EINVAL, "null argument");
+    if (cap < (uint32_t)P->pk.p) return fail(SIM_ERANGE, "perm buffer shorter than p");
+    for (int j = 0; j < P->pk.p; ++j) perm[j] = P->pk.perm[j];
+    return SIM_OK;
+}
+
+int sim_eval_amplitude(const sim_program *P, void *stream, sim_zomega *out) {
+    if (!P || !out) return fail(SIM_EINVAL, "null argument");
+    if (P->pk.zero) {
+        zero_result(out, false);
+        return SIM_OK;
+    }
+    DeviceState *D;
+    int rc = enter_device(P, &D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(D->mu);
+    return eval_range_locked(*D, P, 0, P->pk.n_slices, false, (hipStream_t)stream, nullptr, out);
+}
+
+int sim_eval_timed(const sim_program *P, void *stream, sim_zomega *out, float *kernel_ms) {
+    if (!P || !out || !kernel_ms) return fail(SIM_EINVAL, "null argument");
+    if (P->pk.zero) {
+        zero_result(out, false);
+        *kernel_ms = 0.f;
+        return SIM_OK;
+    }
+    DeviceState *D;
+    int rc = enter_device(P, &D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(D->mu);
+    return eval_range_locked(*D, P, 0, P->pk.n_slices, false, (hipStream_t)stream, nullptr, out, kernel_ms);
+}
+
+int sim_eval_range(const sim_program *P, uint64_t first_slice, uint64_t n_slices, void *stream, sim_zomega *raw) {
+    if (!P || !raw) return fail(SIM_EINVAL, "null argument");
+    if (first_slice > P->pk.n_slices || n_slices > P->pk.n_slices - first_slice)
+        return fail(SIM_EINVAL, "slice range outside the program");
+    if (P->pk.zero || n_slices == 0) {
+        zero_result(raw, true);
+        return SIM_OK;
+    }
+    DeviceState *D;
+    int rc = enter_device(P, &D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(D->mu);
+    return eval_range_locked(*D, P, first_slice, n_slices, true, (hipStream_t)stream, nullptr, raw);
+}
+
+int sim_raw_add(const sim_zomega *a, const sim_zomega *b, sim_zomega *out) {
+    if (!a || !b || !out) return fail(SIM_EINVAL, "null argument");
+    sim_zomega r;
+    memset(&r, 0, sizeof r);
+    for (int k = 0; k < 4; ++k) {
+        i128 x = (i128)((unsigned __int128)a->c[k].lo | ((unsigned __int128)(uint64_t)a->c[k].hi << 64));
+        i128 y = (i128)((unsigned __int128)b->c[k].lo | ((unsigned __int128)(uint64_t)b->c[k].hi << 64));
+        i128 s;
+        if (__builtin_add_overflow(x, y, &s)) return fail(SIM_ERANGE, "int128 overflow adding partials");
+        r.c[k].lo = (uint64_t)s;
+        r.c[k].hi = (int64_t)((unsigned __int128)s >> 64);
+    }
+    r.flags = SIM_ZOMEGA_RAW;
+    *out = r;
+    return SIM_OK;
+}
+
+int sim_finalize(const sim_program *P, const sim_zomega *raw, void *stream, sim_zomega *out) {
+    if (!P || !raw || !out) return fail(SIM_EINVAL, "null argument");
+    if (P->pk.zero) {
+        zero_result(out, false);
+        return SIM_OK;
+    }
+    DeviceState *D;
+    int rc = enter_device(P, &D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(D->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = ensure(D->partials, sizeof(Partial)))) return rc;
+    if ((rc = ensure(D->result, sizeof(DevResult)))) return rc;
+    if ((rc = ensure_host(*D, sizeof(DevResult)))) return rc;
+    Partial part;
+    for (int k = 0; k < 4; ++k) {
+        part.w[2 * k] = raw->c[k].lo;
+        part.w[2 * k + 1] = (uint64_t)raw->c[k].hi;
+    }
+    HIP_TRY(hipMemcpyAsync(D->partials.ptr, &part, sizeof part, hipMemcpyHostToDevice, st));
+    FinalArgs fa = final_args(P->pk, false);
+    HIP_TRY(launch_finalize((Partial *)D->partials.ptr, 1, fa, (DevResult *)D->result.ptr, st));
+    HIP_TRY(hipMemcpyAsync(D->host_result, D->result.ptr, sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    DevResult r;
+    memcpy(&r, D->host_result, sizeof r);
+    return to_zomega(r, out);
+}
+
+void sim_program_free(sim_program *P) {
+    if (!P) return;
+    if (P->dimg) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(P->device);
+        (void)hipFree(P->dimg);
+        (void)hipSetDevice(cur);
+    }
+    delete P;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+// work list of a batch: programs grouped by kernel variant (W, monomials), each program's
+// slices cut into items of about 2^chunk_log2 terms
+struct BatchLayout {
+    struct Group {
+        uint32_t W = 1, mono = 0;
+        uint32_t item_first = 0, n_items = 0;
+        uint32_t table_bytes = 0;
+        ImgHeader h0;
+    };
+    std::vector<Group> groups;
+    std::vector<WorkItem> items;
+    std::vector<ImgHeader> hdrs;
+    std::vector<uint64_t> imgs;
+    std::vector<uint32_t> firsts, counts;  // per program: its items
+    std::vector<FinalArgs> args;
+    std::vector<uint32_t> live;  // indices of programs that need the GPU
+};
+
+int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_slice, const uint64_t *n_slices,
+                 bool raw, const sim_tuning *t, BatchLayout *L) {
+    const uint32_t chunk_log2 = t && t->chunk_log2 ? t->chunk_log2 : 22u;
+    L->hdrs.resize(n);
+    L->imgs.resize(n);
+    L->firsts.assign(n, 0);
+    L->counts.assign(n, 0);
+    L->args.resize(n);
+    std::vector<uint32_t> order;
+    for (size_t i = 0; i < n; ++i) {
+        const sim_program *P = ps[i];
+        L->hdrs[i] = P->pk.hdr;
+        L->imgs[i] = (uint64_t)(uintptr_t)P->dimg;
+        L->args[i] = final_args(P->pk, raw);
+        uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;
+        if (!P->pk.zero && cnt) order.push_back((uint32_t)i);
+    }
+    // group by kernel variant, keep program order inside a group
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        uint32_t ka = ps[a]->pk.hdr.W * 2 + ps[a]->pk.hdr.has_mono;
+        uint32_t kb = ps[b]->pk.hdr.W * 2 + ps[b]->pk.hdr.has_mono;
+        return ka < kb;
+    });
+    for (uint32_t i : order) {
+        const sim_program *P = ps[i];
+        const ImgHeader &H = P->pk.hdr;
+        if (L->groups.empty() || L->groups.back().W != H.W || L->groups.back().mono != H.has_mono) {
+            BatchLayout::Group g;
+            g.W = H.W;
+            g.mono = H.has_mono;
+            g.item_first = (uint32_t)L->items.size();
+            g.h0 = H;
+            L->groups.push_back(g);
+        }
+        BatchLayout::Group &g = L->groups.back();
+        g.table_bytes = std::max<uint32_t>(g.table_bytes, H.table_n * 32);
+        uint64_t s0 = first_slice ? first_slice[i] : 0;
+        uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;
+        // slices per item: 2^chunk_log2 terms, at least 1 slice
+        int terms_per_slice_log2 = (int)H.g;
+        uint64_t per = chunk_log2 > (uint32_t)terms_per_slice_log2
+                           ? ((uint64_t)1 << std::min<uint32_t>(62, chunk_log2 - terms_per_slice_log2))
+                           : 1;
+        L->firsts[i] = (uint32_t)L->items.size();
+        for (uint64_t s = 0; s < cnt; s += per) {
+            WorkItem wi;
+            wi.prog = i;
+            wi.out_slot = (uint32_t)L->items.size();
+            wi.s_begin = s0 + s;
+            wi.s_end = s0 + std::min(cnt, s + per);
+            L->items.push_back(wi);
+        }
+        L->counts[i] = (uint32_t)L->items.size() - L->firsts[i];
+        g.n_items = (uint32_t)L->items.size() - g.item_first;
+        L->live.push_back(i);
+    }
+    if (L->items.size() > 0xffffffffu) return fail(SIM_ERANGE, "too many work items");
+    return SIM_OK;
+}
+
+// enqueues the batch on `stream` (no host synchronisation); buffers must be uploaded
+int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuning *t, hipStream_t stream,
+                  const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items, uint32_t *d_queue,
+                  Partial *d_parts, const uint32_t *d_firsts, const uint32_t *d_counts, const FinalArgs *d_args,
+                  DevResult *d_out) {
+    const uint32_t threads = pick_threads(t);
+    const uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 8u;
+    uint32_t gi = 0;
+    for (const auto &g : L.groups) {
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g.n_items, (uint64_t)std::max(1, D.cus) * bpc));
+        HIP_TRY(launch_reset_queue(d_queue + gi, stream));
+        HIP_TRY(launch_eval_batch(g.h0, d_hdrs, d_imgs, d_items + g.item_first, g.n_items, d_queue + gi, d_parts,
+                                  blocks, threads, g.table_bytes, stream));
+        ++gi;
+    }
+    HIP_TRY(launch_finalize_batch(d_parts, d_firsts, d_counts, d_args, (uint32_t)n, d_out, stream));
+    return SIM_OK;
+}
+
+int upload_layout(DeviceState &D, const BatchLayout &L, size_t n, hipStream_t st) {
+    int rc;
+    if ((rc = ensure(D.hdrs, std::max<size_t>(1, n) * sizeof(ImgHeader)))) return rc;
+    if ((rc = ensure(D.imgs, std::max<size_t>(1, n) * 8))) return rc;
+    if ((rc = ensure(D.items, std::max<size_t>(1, L.items.size()) * sizeof(WorkItem)))) return rc;
+    if ((rc = ensure(D.partials, std::max<size_t>(1, L.items.size()) * sizeof(Partial)))) return rc;
+    if ((rc = ensure(D.firsts, std::max<size_t>(1, n) * 4))) return rc;
+    if ((rc = ensure(D.counts, std::max<size_t>(1, n) * 4))) return rc;
+    if ((rc = ensure(D.args, std::max<size_t>(1, n) * sizeof(FinalArgs)))) return rc;
+    if ((rc = ensure(D.result, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
+    if ((rc = ensure(D.queue, std::max<size_t>(1, L.groups.size()) * 4))) return rc;
+    if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(D.hdrs.ptr, L.hdrs.data(), n * sizeof(ImgHeader), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(D.imgs.ptr, L.imgs.data(), n * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(D.firsts.ptr, L.firsts.data(), n * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(D.counts.ptr, L.counts.data(), n * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(D.args.ptr, L.args.data(), n * sizeof(FinalArgs), hipMemcpyHostToDevice, st));
+    }
+    if (!L.items.empty())
+        HIP_TRY(hipMemcpyAsync(D.items.ptr, L.items.data(), L.items.size() * sizeof(WorkItem),
+                               hipMemcpyHostToDevice, st));
+    return SIM_OK;
+}
+
+int check_batch_args(const sim_program *const *ps, size_t n, int *dev) {
+    if (n && !ps) return fail(SIM_EINVAL, "null program list");
+    for (size_t i = 0; i < n; ++i)
+        if (!ps[i]) return fail(SIM_EINVAL, "null program in batch");
+    if (n) {
+        *dev = ps[0]->device;
+        for (size_t i = 1; i < n; ++i)
+            if (ps[i]->device != *dev) return fail(SIM_EINVAL, "programs of one batch must share a device");
+    } else {
+        HIP_TRY(hipGetDevice(dev));
+    }
+    return init_device(*dev);
+}
+
+int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, const uint64_t *count, bool raw,
+              void *stream, const sim_tuning *t, sim_zomega *out) {
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    if (first && count)
+        for (size_t i = 0; i < n; ++i)
+            if (first[i] > ps[i]->pk.n_slices || count[i] > ps[i]->pk.n_slices - first[i])
+                return fail(SIM_EINVAL, "slice range outside a program");
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    BatchLayout L;
+    if ((rc = build_layout(ps, n, first, count, raw, t, &L))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_layout(D, L, n, st))) return rc;
+    if (!L.live.empty()) {
+        if ((rc = enqueue_batch(D, L, n, t, st, (const ImgHeader *)D.hdrs.ptr, (const uint64_t *)D.imgs.ptr,
+                                (const WorkItem *)D.items.ptr, (uint32_t *)D.queue.ptr, (Partial *)D.partials.ptr,
+                                (const uint32_t *)D.firsts.ptr, (const uint32_t *)D.counts.ptr,
+                                (const FinalArgs *)D.args.ptr, (DevResult *)D.result.ptr)))
+            return rc;
+        HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<sim_zomega> res(n);
+    for (size_t i = 0; i < n; ++i) {
+        const sim_program *P = ps[i];
+        uint64_t cnt = count ? count[i] : P->pk.n_slices;
+        if (P->pk.zero || cnt == 0) {
+            zero_result(&res[i], raw);
+            continue;
+        }
+        DevResult r;
+        memcpy(&r, (const char *)D.host_result + i * sizeof(DevResult), sizeof r);
+        if ((rc = to_zomega(r, &res[i]))) return rc;
+    }
+    for (size_t i = 0; i < n; ++i) out[i] = res[i];
+    return SIM_OK;
+}
+
+}  // namespace
+
+struct sim_batch_plan {
+    int device = 0;
+    size_t n = 0;
+    std::vector<const sim_program *> progs;
+    BatchLayout L;
+    sim_tuning tuning;
+    bool has_tuning = false;
+    DevBuf hdrs, imgs, items, parts, firsts, counts, args, result, queue;
+    void *host_result = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int sim_eval_batch(const sim_program *const *ps, size_t n, void *stream, const sim_tuning *t, sim_zomega *out) {
+    if (n && !out) return fail(SIM_EINVAL, "null output");
+    return run_batch(ps, n, nullptr, nullptr, false, stream, t, out);
+}
+
+int sim_eval_ranges(const sim_program *const *ps, const uint64_t *first_slice, const uint64_t *n_slices, size_t n,
+                    void *stream, const sim_tuning *t, sim_zomega *raw) {
+    if (n && (!raw || !first_slice || !n_slices)) return fail(SIM_EINVAL, "null argument");
+    return run_batch(ps, n, first_slice, n_slices, true, stream, t, raw);
+}
+
+void sim_batch_plan_free(sim_batch_plan *plan) {
+    if (!plan) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(plan->device);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    for (DevBuf *b : {&plan->hdrs, &plan->imgs, &plan->items, &plan->parts, &plan->firsts, &plan->counts,
+                      &plan->args, &plan->result, &plan->queue})
+        if (b->ptr) (void)hipFree(b->ptr);
+    if (plan->host_result) (void)hipHostFree(plan->host_result);
+    (void)hipSetDevice(cur);
+    delete plan;
+}
+
+int sim_batch_plan_create(const sim_program *const *ps, size_t n, const sim_tuning *t, void *stream,
+                          sim_batch_plan **out) {
+    if (!out) return fail(SIM_EINVAL, "null output");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    std::unique_ptr<sim_batch_plan, void (*)(sim_batch_plan *)> plan(new sim_batch_plan(), sim_batch_plan_free);
+    plan->device = dev;
+    plan->n = n;
+    plan->progs.assign(ps, ps + n);
+    if (t) {
+        plan->tuning = *t;
+        plan->has_tuning = true;
+    }
+    if ((rc = build_layout(ps, n, nullptr, nullptr, false, t, &plan->L))) return rc;
+    const BatchLayout &L = plan->L;
+    hipStream_t st = (hipStream_t)stream;
+    auto alloc = [&](DevBuf &b, size_t bytes) { return ensure(b, std::max<size_t>(bytes, 64)); };
+    if ((rc = alloc(plan->hdrs, n * sizeof(ImgHeader))) || (rc = alloc(plan->imgs, n * 8)) ||
+        (rc = alloc(plan->items, L.items.size() * sizeof(WorkItem))) ||
+        (rc = alloc(plan->parts, L.items.size() * sizeof(Partial))) || (rc = alloc(plan->firsts, n * 4)) ||
+        (rc = alloc(plan->counts, n * 4)) || (rc = alloc(plan->args, n * sizeof(FinalArgs))) ||
+        (rc = alloc(plan->result, n * sizeof(DevResult))) || (rc = alloc(plan->queue, L.groups.size() * 4 + 4)))
+        return rc;
+    HIP_TRY(hipHostMalloc(&plan->host_result, std::max<size_t>(1, n) * sizeof(DevResult), hipHostMallocDefault));
+    if (n) {
+        HIP_TRY(hipMemcpy(plan->hdrs.ptr, L.hdrs.data(), n * sizeof(ImgHeader), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(plan->imgs.ptr, L.imgs.data(), n * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(plan->firsts.ptr, L.firsts.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(plan->counts.ptr, L.counts.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(plan->args.ptr, L.args.data(), n * sizeof(FinalArgs), hipMemcpyHostToDevice));
+    }
+    if (!L.items.empty())
+        HIP_TRY(hipMemcpy(plan->items.ptr, L.items.data(), L.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    if (!L.live.empty()) {
+        // capture the launch sequence once on a private stream
+        hipStream_t cap;
+        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        DeviceState &D = g_dev[dev];
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = enqueue_batch(D, L, n, plan->has_tuning ? &plan->tuning : nullptr, cap,
+                               (const ImgHeader *)plan->hdrs.ptr, (const uint64_t *)plan->imgs.ptr,
+                               (const WorkItem *)plan->items.ptr, (uint32_t *)plan->queue.ptr,
+                               (Partial *)plan->parts.ptr, (const uint32_t *)plan->firsts.ptr,
+                               (const uint32_t *)plan->counts.ptr, (const FinalArgs *)plan->args.ptr,
+                               (DevResult *)plan->result.ptr);
+            if (rc == SIM_OK) {
+                e = hipMemcpyAsync(plan->host_result, plan->result.ptr, n * sizeof(DevResult), hipMemcpyDeviceToHost,
+                                   cap);
+                if (e != hipSuccess) rc = fail(SIM_EDEVICE, std::string("hipMemcpyAsync failed: ") + hipGetErrorString(e));
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cap, &graph);
+            plan->graph = graph;
+            if (rc == SIM_OK && e2 != hipSuccess)
+                rc = fail(SIM_EDEVICE, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e2));
+        } else {
+            rc = fail(SIM_EDEVICE, std::string("hipStreamBeginCapture failed: ") + hipGetErrorString(e));
+        }
+        (void)hipStreamDestroy(cap);
+        if (rc) return rc;
+        HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+    }
+    (void)st;
+    *out = plan.release();
+    return SIM_OK;
+}
+
+int sim_batch_plan_run(sim_batch_plan *plan, void *stream, sim_zomega *out) {
+    if (!plan || (plan->n && !out)) return fail(SIM_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(plan->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (plan->exec) {
+        HIP_TRY(hipGraphLaunch(plan->exec, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    std::vector<sim_zomega> res(plan->n);
+    for (size_t i = 0; i < plan->n; ++i) {
+        const sim_program *P = plan->progs[i];
+        if (P->pk.zero) {
+            zero_result(&res[i], false);
+            continue;
+        }
+        DevResult r;
+        memcpy(&r, (const char *)plan->host_result + i * sizeof(DevResult), sizeof r);
+        int rc = to_zomega(r, &res[i]);
+        if (rc) return rc;
+    }
+    for (size_t i = 0; i < plan->n; ++i) out[i] = res[i];
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,48 @@
+// Launch wrappers of the HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "image.h"
+
+// arguments of the finaliser: constant c (four int128 as lo/hi pairs), exponent, mode
+struct FinalArgs {
+    uint64_t c0[8];
+    int32_t e;
+    uint32_t raw;   // 1: write the raw sum (no constant, no canonical form)
+    uint32_t zero;  // 1: the program is identically zero
+    uint32_t pad;
+};
+
+// device result, laid out exactly like sim_zomega
+struct DevResult {
+    uint64_t w[8];
+    int32_t e;
+    uint32_t flags;  // bit 0 raw, bit 1 int128 overflow while applying the constant
+};
+
+#define RESULT_FLAG_RAW 1u
+#define RESULT_FLAG_OVERFLOW 2u
+
+// largest dynamic LDS a value table may take
+#define MAX_TABLE_BYTES (64 * 1024)
+
+hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
+                       Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
+
+hipError_t launch_finalize(const Partial *partials, uint32_t n, const FinalArgs &args, DevResult *out,
+                           hipStream_t stream);
+
+// persistent multi-program launch; all programs share W and the monomial flag of `H0`
+hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
+                             const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue,
+                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t table_bytes,
+                             hipStream_t stream);
+
+hipError_t launch_reset_queue(uint32_t *d_queue, hipStream_t stream);
+
+// per-program finaliser: program k sums partials [item_first[k], item_first[k] + item_count[k])
+hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item_first,
+                                 const uint32_t *d_item_count, const FinalArgs *d_args, uint32_t n_progs,
+                                 DevResult *d_out, hipStream_t stream);

@@ -1,0 +1,654 @@
+// Parser, printer and packer of term programs.
+//
+// Packing strategy (what the kernels rely on):
+//
+//  * Every node factor takes one of two values 1 + w^{v0} (form = 0) and 1 + w^{v1}
+//    (form = 1).  The product of all factors therefore depends only on how many factors
+//    currently sit in each value class k (value 1 + w^k).  With n_k those counts:
+//        prod_k (1 + w^k)^{n_k} = w^R * sqrt2^E * Q(A - B)      if n_4 = 0, else 0,
+//    because 1 + w^2 = sqrt2 w, 1 + w^6 = sqrt2 w^-1, 1 + w^7 = w^-1 (1 + w),
+//    1 + w^5 = w^-3 (1 + w^3) and (1 + w)(1 + w^3) = sqrt2 w^2, where
+//        A = n1 + n7,  B = n3 + n5,  m = min(A, B),
+//        E = 2 n0 + n2 + n6 + m,     R = n2 - n6 - n7 - 3 n5 + 2 m   (mod 8),
+//        Q(d) = (1 + w)^d for d >= 0 and (1 + w^3)^(-d) for d < 0.
+//    Each of A, B, E, R is affine in the form bits, so it is a base value plus weighted
+//    popcounts of L(x) against a few masks.  A small table holds w^r sqrt2^e Q(d) exactly.
+//  * Linear phase terms c * l(x) are added to R the same way.
+//  * A phase-pair factor (Eq. 3) is the sum over one extra Boolean z of
+//        w^{z (b + 4 l2)} (1 + w^{a + 4 (l1 xor z)}),
+//    and 4 z l2 = 2 z + 2 l2 - 2 (z xor l2) (mod 8), so it becomes a node factor and three
+//    linear phase terms in one more parameter; those extra parameters are always walked
+//    inside a slice, so slices still partition the original 2^p assignments.
+//  * Factors on constant forms, and factors whose two values coincide, are multiplied
+//    into the constant c at pack time (exactly, with overflow checks).
+//  * Variable monomials are kept for a Gray-code walk: the parameters with the fewest
+//    monomials are walked inside each slice, and each walk step adds only the change of
+//    the monomials that contain the flipped parameter.
+
+#include "program.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <sstream>
+
+#include "../../include/zxpar.h"
+
+// ------------------------------------------------------------------ IR text
+
+namespace {
+
+struct Lexer {
+    std::vector<std::pair<std::string, int>> toks;  // token, line
+    size_t pos = 0;
+};
+
+void lex(const char *text, size_t len, Lexer *lx) {
+    int line = 1;
+    size_t i = 0;
+    while (i < len) {
+        char ch = text[i];
+        if (ch == '#') {
+            while (i < len && text[i] != '\n') ++i;
+        } else if (ch == '\n') {
+            ++line;
+            ++i;
+        } else if (ch == ' ' || ch == '\t' || ch == '\r' || ch == '\f' || ch == '\v' || ch == '\0') {
+            ++i;
+        } else {
+            size_t j = i;
+            while (j < len && !strchr(" \t\r\n\f\v#", text[j]) && text[j] != '\0') ++j;
+            lx->toks.emplace_back(std::string(text + i, j - i), line);
+            i = j;
+        }
+    }
+}
+
+struct ParseError {
+    std::string msg;
+};
+
+const std::pair<std::string, int> &next(Lexer *lx) {
+    if (lx->pos >= lx->toks.size()) throw ParseError{"unexpected end of program text"};
+    return lx->toks[lx->pos++];
+}
+
+void expect(Lexer *lx, const char *w) {
+    const auto &t = next(lx);
+    if (t.first != w)
+        throw ParseError{"line " + std::to_string(t.second) + ": expected '" + w + "', got '" + t.first + "'"};
+}
+
+long long get_int(Lexer *lx, long long lo, long long hi) {
+    const auto &t = next(lx);
+    char *end = nullptr;
+    errno = 0;
+    long long v = strtoll(t.first.c_str(), &end, 10);
+    if (*end || errno || t.first.empty())
+        throw ParseError{"line " + std::to_string(t.second) + ": bad integer '" + t.first + "'"};
+    if (v < lo || v > hi)
+        throw ParseError{"line " + std::to_string(t.second) + ": value " + t.first + " out of range"};
+    return v;
+}
+
+i128 get_i128(Lexer *lx) {
+    const auto &t = next(lx);
+    const char *s = t.first.c_str();
+    bool neg = false;
+    if (*s == '-') {
+        neg = true;
+        ++s;
+    }
+    if (!*s) throw ParseError{"line " + std::to_string(t.second) + ": bad integer"};
+    i128 v = 0;
+    for (; *s; ++s) {
+        if (*s < '0' || *s > '9') throw ParseError{"line " + std::to_string(t.second) + ": bad integer"};
+        if (__builtin_mul_overflow(v, (i128)10, &v) || __builtin_add_overflow(v, (i128)(*s - '0'), &v))
+            throw ParseError{"line " + std::to_string(t.second) + ": constant exceeds int128"};
+    }
+    return neg ? -v : v;
+}
+
+uint64_t get_hex(Lexer *lx) {
+    const auto &t = next(lx);
+    char *end = nullptr;
+    errno = 0;
+    unsigned long long v = strtoull(t.first.c_str(), &end, 16);
+    if (*end || errno || t.first.empty() || t.first[0] == '-')
+        throw ParseError{"line " + std::to_string(t.second) + ": bad hex mask '" + t.first + "'"};
+    return (uint64_t)v;
+}
+
+std::string i128_str(i128 v) {
+    if (v == 0) return "0";
+    bool neg = v < 0;
+    unsigned __int128 u = neg ? (unsigned __int128)(-(v + 1)) + 1 : (unsigned __int128)v;
+    std::string s;
+    while (u) {
+        s.push_back((char)('0' + (int)(u % 10)));
+        u /= 10;
+    }
+    if (neg) s.push_back('-');
+    std::reverse(s.begin(), s.end());
+    return s;
+}
+
+}  // namespace
+
+bool ir_parse(const char *text, size_t len, IrProgram *out, std::string *err) {
+    Lexer lx;
+    lex(text, len, &lx);
+    IrProgram P;
+    try {
+        expect(&lx, "zxir");
+        if (get_int(&lx, 1, 1) != 1) throw ParseError{"unsupported IR version"};
+        expect(&lx, "p");
+        P.p = (int)get_int(&lx, 0, 62);
+        expect(&lx, "forms");
+        long long nf = get_int(&lx, 0, 1 << 20);
+        for (long long i = 0; i < nf; ++i) {
+            expect(&lx, "f");
+            IrForm f;
+            f.cst = (int)get_int(&lx, 0, 1);
+            f.mask = get_hex(&lx);
+            if (P.p < 64 && (f.mask >> P.p)) throw ParseError{"form " + std::to_string(i) + " names a parameter >= p"};
+            P.forms.push_back(f);
+        }
+        auto form_idx = [&](void) { return (int)get_int(&lx, 0, (long long)P.forms.size() - 1); };
+        expect(&lx, "nodes");
+        long long nn = get_int(&lx, 0, 1 << 20);
+        for (long long i = 0; i < nn; ++i) {
+            expect(&lx, "n");
+            IrNode n;
+            n.form = form_idx();
+            n.a = (int)get_int(&lx, -(1LL << 30), 1LL << 30);
+            n.b = (int)get_int(&lx, -(1LL << 30), 1LL << 30);
+            P.nodes.push_back(n);
+        }
+        expect(&lx, "pairs");
+        long long nq = get_int(&lx, 0, 1 << 20);
+        for (long long i = 0; i < nq; ++i) {
+            expect(&lx, "q");
+            IrPair q;
+            q.f1 = form_idx();
+            q.f2 = form_idx();
+            q.a = (int)get_int(&lx, -(1LL << 30), 1LL << 30);
+            q.b = (int)get_int(&lx, -(1LL << 30), 1LL << 30);
+            P.pairs.push_back(q);
+        }
+        expect(&lx, "lin");
+        long long nl = get_int(&lx, 0, 1 << 20);
+        for (long long i = 0; i < nl; ++i) {
+            expect(&lx, "l");
+            IrLin l;
+            l.c = (int)get_int(&lx, -(1LL << 30), 1LL << 30);
+            l.form = form_idx();
+            P.lin.push_back(l);
+        }
+        expect(&lx, "mono");
+        long long nm = get_int(&lx, 0, 1 << 20);
+        for (long long i = 0; i < nm; ++i) {
+            expect(&lx, "m");
+            IrMono m;
+            m.c = (int)get_int(&lx, -(1LL << 30), 1LL << 30);
+            int d = (int)get_int(&lx, 1, 16);
+            for (int k = 0; k < d; ++k) m.vars.push_back((int)get_int(&lx, 0, P.p - 1));
+            P.mono.push_back(m);
+        }
+        expect(&lx, "scalar");
+        for (int k = 0; k < 4; ++k) P.scalar.c[k] = get_i128(&lx);
+        P.e = (int32_t)get_int(&lx, -(1LL << 30), 1LL << 30);
+        expect(&lx, "end");
+        if (lx.pos != lx.toks.size())
+            throw ParseError{"line " + std::to_string(lx.toks[lx.pos].second) + ": text after 'end'"};
+    } catch (const ParseError &pe) {
+        if (err) *err = "IR: " + pe.msg;
+        return false;
+    }
+    *out = std::move(P);
+    return true;
+}
+
+std::string ir_print(const IrProgram &P) {
+    std::ostringstream os;
+    os << "zxir 1\np " << P.p << "\nforms " << P.forms.size() << "\n";
+    for (const auto &f : P.forms) os << "f " << f.cst << " " << std::hex << f.mask << std::dec << "\n";
+    os << "nodes " << P.nodes.size() << "\n";
+    for (const auto &n : P.nodes) os << "n " << n.form << " " << n.a << " " << n.b << "\n";
+    os << "pairs " << P.pairs.size() << "\n";
+    for (const auto &q : P.pairs) os << "q " << q.f1 << " " << q.f2 << " " << q.a << " " << q.b << "\n";
+    os << "lin " << P.lin.size() << "\n";
+    for (const auto &l : P.lin) os << "l " << l.c << " " << l.form << "\n";
+    os << "mono " << P.mono.size() << "\n";
+    for (const auto &m : P.mono) {
+        os << "m " << m.c << " " << m.vars.size();
+        for (int v : m.vars) os << " " << v;
+        os << "\n";
+    }
+    os << "scalar";
+    for (int k = 0; k < 4; ++k) os << " " << i128_str(P.scalar.c[k]);
+    os << " " << P.e << "\nend\n";
+    return os.str();
+}
+
+// ------------------------------------------------------------------ value table
+
+Zw table_value(int d, int r, int e) {
+    Zw z = zw_one();
+    if (d >= 0) {
+        for (int i = 0; i < d; ++i) z = zw_add(z, zw_rot(z, 1));  // times (1 + w)
+    } else {
+        for (int i = 0; i < -d; ++i) z = zw_add(z, zw_rot(z, 3));  // times (1 + w^3)
+    }
+    z = zw_rot(z, r);
+    if (e) z = zw_times_sqrt2(z);
+    return z;
+}
+
+// ------------------------------------------------------------------ packer
+
+namespace {
+
+// per value class k of a factor (value 1 + w^k): its contribution to A, B, E and R
+int cls_A(int k) { return (k == 1 || k == 7) ? 1 : 0; }
+int cls_B(int k) { return (k == 3 || k == 5) ? 1 : 0; }
+int cls_E(int k) { return k == 0 ? 2 : ((k == 2 || k == 6) ? 1 : 0); }
+int cls_R(int k) {
+    switch (k) {
+        case 2: return 1;
+        case 6: return -1;
+        case 7: return -1;
+        case 5: return -3;
+        default: return 0;
+    }
+}
+
+int mod8(long long v) { return (int)(((v % 8) + 8) % 8); }
+
+struct Work {
+    int pe = 0;
+    std::vector<IrForm> forms;  // masks over eval variables (pair variables first)
+    std::vector<std::pair<int, std::pair<int, int>>> nodes;  // form, (v0, v1)
+    std::vector<std::pair<int, int>> lin;                    // (c mod 8, form)
+    std::map<std::vector<int>, int> mono;                    // sorted vars -> c mod 8
+    Zw c0;
+    int32_t e = 0;
+    bool zero = false;
+};
+
+bool mul_const(Work *w, const Zw &f, std::string *err) {
+    Zw r;
+    if (!zw_mul_checked(w->c0, f, &r)) {
+        *err = "constant factor exceeds int128";
+        return false;
+    }
+    w->c0 = r;
+    zw_canonicalise(&w->c0, &w->e);
+    if (zw_is_zero(w->c0)) w->zero = true;
+    return true;
+}
+
+Zw one_plus_w(int k) {
+    Zw z = zw_rot(zw_one(), k);
+    z.c[0] += 1;
+    return z;
+}
+
+}  // namespace
+
+int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err) {
+    PackedProgram &P = *out;
+    P = PackedProgram();
+    P.p = ir.p;
+    P.q = (int)ir.pairs.size();
+    Work w;
+    w.pe = ir.p + P.q;
+    if (w.pe > 62) {
+        *err = "too many parameters (p plus pair factors must be <= 62)";
+        return SIM_ERANGE;
+    }
+    w.c0 = ir.scalar;
+    w.e = ir.e;
+    zw_canonicalise(&w.c0, &w.e);
+    if (zw_is_zero(w.c0)) w.zero = true;
+    const int q = P.q;
+
+    // forms over eval variables: pair variable k is bit k, original parameter i is bit q + i
+    for (const auto &f : ir.forms) w.forms.push_back(IrForm{f.cst, f.mask << q});
+    int const_phase = 0;
+    for (const auto &n : ir.nodes) {
+        const IrForm &f = w.forms[n.form];
+        int v0 = mod8(n.a), v1 = mod8((long long)n.a + n.b);
+        if (f.mask == 0 || v0 == v1) {
+            if (!mul_const(&w, one_plus_w(f.cst ? v1 : v0), err)) return SIM_ERANGE;
+        } else {
+            w.nodes.push_back({n.form, {v0, v1}});
+        }
+    }
+    for (int k = 0; k < q; ++k) {
+        const IrPair &pr = ir.pairs[k];
+        uint64_t zbit = (uint64_t)1 << k;
+        const IrForm f1 = w.forms[pr.f1], f2 = w.forms[pr.f2];
+        int fz1 = (int)w.forms.size();
+        w.forms.push_back(IrForm{f1.cst, f1.mask ^ zbit});
+        int fz = (int)w.forms.size();
+        w.forms.push_back(IrForm{0, zbit});
+        int fz2 = (int)w.forms.size();
+        w.forms.push_back(IrForm{f2.cst, f2.mask ^ zbit});
+        int v0 = mod8(pr.a), v1 = mod8((long long)pr.a + 4);
+        w.nodes.push_back({fz1, {v0, v1}});
+        w.lin.push_back({mod8((long long)pr.b + 2), fz});  // (b + 2) z
+        if (f2.mask == 0) const_phase += 2 * f2.cst;        // 2 l2
+        else w.lin.push_back({2, pr.f2});
+        w.lin.push_back({6, fz2});                          // -2 (z xor l2)
+    }
+    for (const auto &l : ir.lin) {
+        int c = mod8(l.c);
+        if (!c) continue;
+        const IrForm &f = w.forms[l.form];
+        if (f.mask == 0) const_phase += c * f.cst;
+        else w.lin.push_back({c, l.form});
+    }
+    for (const auto &m : ir.mono) {
+        std::vector<int> vs;
+        for (int v : m.vars) vs.push_back(v + q);
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        int &c = w.mono[vs];
+        c = mod8((long long)c + m.c);
+    }
+    for (auto it = w.mono.begin(); it != w.mono.end();) {
+        if (it->second == 0) it = w.mono.erase(it);
+        else ++it;
+    }
+    if (mod8(const_phase)) w.c0 = zw_rot(w.c0, mod8(const_phase));
+    if (w.zero) {
+        w.c0 = zw_zero();
+        w.e = 0;
+    }
+
+    // ---- packed order of the eval variables
+    const int p = ir.p;
+    std::vector<int> inc(p, 0);  // monomial incidences per original parameter
+    for (const auto &m : w.mono)
+        for (int v : m.first) inc[v - q]++;
+    int g_orig = std::max(0, std::min(max_walk_bits, p - 20));
+    if (p <= 20) g_orig = std::min(p, std::max(0, std::min(max_walk_bits, p / 2)));
+    if (p - g_orig > 62) g_orig = p - 62;
+    // walked parameters: fewest monomials first (they flip most often); high: index order
+    std::vector<int> order(p);
+    for (int i = 0; i < p; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return inc[a] < inc[b]; });
+    std::vector<int> walked(order.begin(), order.begin() + g_orig);
+    std::sort(walked.begin(), walked.end(), [&](int a, int b) {
+        return inc[a] != inc[b] ? inc[a] < inc[b] : a < b;
+    });
+    std::vector<char> is_walked(p, 0);
+    for (int v : walked) is_walked[v] = 1;
+    std::vector<int> pos_of(w.pe, -1);  // eval variable -> packed position
+    for (int k = 0; k < q; ++k) pos_of[k] = k;
+    int pos = q;
+    P.perm.clear();
+    for (int v : walked) {
+        pos_of[v + q] = pos++;
+        P.perm.push_back(v);
+    }
+    for (int i = 0; i < p; ++i)
+        if (!is_walked[i]) {
+            pos_of[i + q] = pos++;
+            P.perm.push_back(i);
+        }
+    const int g = q + g_orig;
+    if (g > 30) {
+        *err = "too many pair factors for one Gray walk (at most 30)";
+        return SIM_ERANGE;
+    }
+    P.walk_bits = g_orig;
+    P.n_slices = (uint64_t)1 << (w.pe - g);
+    auto permute = [&](uint64_t m) {
+        uint64_t r = 0;
+        for (int v = 0; v < w.pe; ++v)
+            if (m >> v & 1) r |= (uint64_t)1 << pos_of[v];
+        return r;
+    };
+
+    // ---- forms actually used, in packed positions
+    std::vector<int> form_slot(w.forms.size(), -1);
+    std::vector<IrForm> used;
+    auto use_form = [&](int f) {
+        if (form_slot[f] < 0) {
+            form_slot[f] = (int)used.size();
+            used.push_back(IrForm{w.forms[f].cst, permute(w.forms[f].mask)});
+        }
+        return form_slot[f];
+    };
+    for (auto &n : w.nodes) n.first = use_form(n.first);
+    for (auto &l : w.lin) l.second = use_form(l.second);
+    const int F = (int)used.size();
+    int W = 1;
+    while (W * 32 < F) W *= 2;
+    if (W > 16) {
+        *err = "too many distinct forms (at most 512)";
+        return SIM_ERANGE;
+    }
+    P.W = W;
+    P.n_forms = F;
+    P.n_factors = (int)w.nodes.size();
+    P.n_mono = (int)w.mono.size();
+
+    // ---- static bound: every node factor has |sigma(F)| <= 2 in every embedding, so each
+    // coefficient of a term is <= 2^nodes and the sum over 2^pe terms is <= 2^(nodes + pe)
+    if (!w.zero && (long long)w.nodes.size() + w.pe > 125) {
+        *err = "static bound exceeds int128 (factors + parameters > 125)";
+        return SIM_ERANGE;
+    }
+
+    // ---- statistics
+    std::vector<long long> wt[N_STATS];
+    for (int s = 0; s < N_STATS; ++s) wt[s].assign(F, 0);
+    long long base[N_STATS] = {0, 0, 0, 0};
+    std::vector<uint32_t> z0(W, 0), z1(W, 0);
+    bool has_zero = false;
+    typedef int (*ClsFn)(int);
+    ClsFn fns[N_STATS] = {cls_A, cls_B, cls_E, cls_R};
+    long long amax = 0, amin = 0, bmax = 0, bmin = 0;
+    for (const auto &n : w.nodes) {
+        int f = n.first, v0 = n.second.first, v1 = n.second.second;
+        for (int s = 0; s < N_STATS; ++s) {
+            base[s] += fns[s](v0);
+            wt[s][f] += fns[s](v1) - fns[s](v0);
+        }
+        if (v0 == 4) {
+            z0[f / 32] |= 1u << (f % 32);
+            has_zero = true;
+        }
+        if (v1 == 4) {
+            z1[f / 32] |= 1u << (f % 32);
+            has_zero = true;
+        }
+    }
+    for (const auto &l : w.lin) wt[STAT_R][l.second] += l.first;
+    for (int f = 0; f < F; ++f) {
+        if (wt[STAT_A][f] > 0) amax += wt[STAT_A][f]; else amin += wt[STAT_A][f];
+        if (wt[STAT_B][f] > 0) bmax += wt[STAT_B][f]; else bmin += wt[STAT_B][f];
+    }
+    amax += base[STAT_A];
+    amin += base[STAT_A];
+    bmax += base[STAT_B];
+    bmin += base[STAT_B];
+    amin = std::max(0LL, amin);
+    bmin = std::max(0LL, bmin);
+    long long dmin = amin - bmax, dmax = amax - bmin;
+    if (dmax > 63 || dmin < -63) {
+        *err = "more than 63 odd-class factors (table range)";
+        return SIM_ERANGE;
+    }
+    if (dmin > dmax) dmin = dmax = 0;
+
+    // ---- image words
+    std::vector<uint32_t> img;
+    ImgHeader &H = P.hdr;
+    memset(&H, 0, sizeof H);
+    H.pe = (uint32_t)w.pe;
+    H.g = (uint32_t)g;
+    H.W = (uint32_t)W;
+    H.has_zero = has_zero ? 1u : 0u;
+    H.has_mono = w.mono.empty() ? 0u : 1u;
+    H.n_slices_lo = (uint32_t)P.n_slices;
+    H.n_slices_hi = (uint32_t)(P.n_slices >> 32);
+    H.off_col = (uint32_t)img.size();
+    for (int j = 0; j < w.pe; ++j) {
+        std::vector<uint32_t> col(W, 0);
+        for (int f = 0; f < F; ++f)
+            if (used[f].mask >> j & 1) col[f / 32] |= 1u << (f % 32);
+        img.insert(img.end(), col.begin(), col.end());
+    }
+    H.off_cvec = (uint32_t)img.size();
+    {
+        std::vector<uint32_t> cv(W, 0);
+        for (int f = 0; f < F; ++f)
+            if (used[f].cst) cv[f / 32] |= 1u << (f % 32);
+        img.insert(img.end(), cv.begin(), cv.end());
+    }
+    H.off_z0 = (uint32_t)img.size();
+    img.insert(img.end(), z0.begin(), z0.end());
+    H.off_z1 = (uint32_t)img.size();
+    img.insert(img.end(), z1.begin(), z1.end());
+    for (int s = 0; s < N_STATS; ++s) {
+        H.stat_off[s] = (uint32_t)img.size();
+        H.stat_base[s] = (int32_t)(s == STAT_R ? mod8(base[s]) : base[s]);
+        uint32_t cnt = 0;
+        auto emit = [&](long long weight, const std::vector<uint32_t> &mask) {
+            bool any = false;
+            for (uint32_t v : mask) any |= v != 0;
+            if (!any) return;
+            img.push_back((uint32_t)(int32_t)weight);
+            img.insert(img.end(), mask.begin(), mask.end());
+            ++cnt;
+        };
+        if (s == STAT_R) {
+            for (int bit = 0; bit < 3; ++bit) {
+                std::vector<uint32_t> mask(W, 0);
+                for (int f = 0; f < F; ++f)
+                    if (mod8(wt[s][f]) >> bit & 1) mask[f / 32] |= 1u << (f % 32);
+                emit(1LL << bit, mask);
+            }
+        } else {
+            long long mx = 0;
+            for (int f = 0; f < F; ++f) mx = std::max(mx, std::llabs(wt[s][f]));
+            for (int bit = 0; (1LL << bit) <= mx; ++bit) {
+                std::vector<uint32_t> pm(W, 0), nm(W, 0);
+                for (int f = 0; f < F; ++f) {
+                    long long v = wt[s][f];
+                    if (v > 0 && (v >> bit & 1)) pm[f / 32] |= 1u << (f % 32);
+                    if (v < 0 && ((-v) >> bit & 1)) nm[f / 32] |= 1u << (f % 32);
+                }
+                emit(1LL << bit, pm);
+                emit(-(1LL << bit), nm);
+            }
+        }
+        H.stat_n[s] = cnt;
+    }
+    // monomials in packed positions
+    const uint64_t walk_mask = g >= 64 ? ~0ull : (((uint64_t)1 << g) - 1);
+    std::vector<std::pair<int, uint64_t>> monos;
+    for (const auto &m : w.mono) {
+        uint64_t pm = 0;
+        for (int v : m.first) pm |= (uint64_t)1 << pos_of[v];
+        monos.push_back({m.second, pm});
+    }
+    H.off_monohi = (uint32_t)img.size();
+    for (const auto &m : monos) {
+        if (m.second & walk_mask) continue;
+        uint64_t hm = m.second >> g;
+        img.push_back((uint32_t)m.first);
+        img.push_back((uint32_t)hm);
+        img.push_back((uint32_t)(hm >> 32));
+        H.n_monohi++;
+    }
+    H.off_didx = (uint32_t)img.size();
+    std::vector<std::vector<uint32_t>> per(g);
+    for (int i = 0; i < g; ++i) {
+        for (const auto &m : monos) {
+            if (!(m.second >> i & 1)) continue;
+            uint64_t others = m.second & ~((uint64_t)1 << i);
+            uint32_t wm = (uint32_t)(others & walk_mask);
+            uint64_t hm = others >> g;
+            per[i].push_back((uint32_t)m.first);
+            per[i].push_back(wm);
+            per[i].push_back((uint32_t)hm);
+            per[i].push_back((uint32_t)(hm >> 32));
+        }
+    }
+    uint32_t acc = 0;
+    for (int i = 0; i <= g; ++i) {
+        img.push_back(acc);
+        if (i < g) acc += (uint32_t)(per[i].size() / 4);
+    }
+    H.off_delta = (uint32_t)img.size();
+    for (int i = 0; i < g; ++i) img.insert(img.end(), per[i].begin(), per[i].end());
+
+    // ---- value table
+    const int nd = (int)(dmax - dmin + 1);
+    H.d_off = (int32_t)(-dmin);
+    H.table_n = (uint32_t)(nd * 16 + 1);
+    H.zero_entry = (uint32_t)(nd * 16);
+    std::vector<int64_t> table((size_t)H.table_n * 4, 0);
+    for (int d = (int)dmin; d <= (int)dmax; ++d)
+        for (int r = 0; r < 8; ++r)
+            for (int e = 0; e < 2; ++e) {
+                Zw z = table_value(d, r, e);
+                size_t idx = ((size_t)(d - dmin) * 8 + r) * 2 + e;
+                for (int k = 0; k < 4; ++k) {
+                    if (z.c[k] > (i128)INT64_MAX || z.c[k] < (i128)INT64_MIN) {
+                        *err = "table entry exceeds int64";
+                        return SIM_ERANGE;
+                    }
+                    table[idx * 4 + k] = (int64_t)z.c[k];
+                }
+            }
+    size_t word_bytes = img.size() * 4;
+    size_t tab_off = (word_bytes + 7) & ~(size_t)7;
+    H.table_byte_off = (uint32_t)tab_off;
+    H.image_bytes = (uint32_t)(tab_off + table.size() * 8);
+    P.blob.assign(H.image_bytes, 0);
+    if (!img.empty()) memcpy(P.blob.data(), img.data(), word_bytes);
+    memcpy(P.blob.data() + tab_off, table.data(), table.size() * 8);
+
+    // ---- algorithmic work per term, counted in int32 lane operations from the packed
+    // program: Gray-step XOR of one column (W), each statistic mask (W ANDs, W popcounts,
+    // one multiply-add), the zero test (3W + 1), combining the statistics into the table
+    // index and shift (10), shifting and adding four int128 coefficients (4 x 10), and per
+    // walk step the slice-dependent monomial updates whose walk part holds (5 each, +2),
+    // plus the per-slice set-up spread over the 2^g terms of a slice.
+    {
+        double ops = W + 10 + 40;
+        for (int s = 0; s < N_STATS; ++s) ops += H.stat_n[s] * (2.0 * W + 1);
+        if (has_zero) ops += 3.0 * W + 1;
+        double setup = (double)(w.pe - g) * 2.0 * W + 5.0 * H.n_monohi;
+        double steps = (double)((uint64_t)1 << g);
+        double mono_ops = 0;
+        if (!w.mono.empty() && g > 0) {
+            // exact count over one walk: step t flips position ctz(t) with Gray state gray(t)
+            const uint32_t *didx = img.data() + H.off_didx;
+            const uint32_t *de = img.data() + H.off_delta;
+            for (uint64_t t = 1; t < ((uint64_t)1 << g); ++t) {
+                int i = __builtin_ctzll(t);
+                uint32_t gray = (uint32_t)(t ^ (t >> 1));
+                mono_ops += 2;
+                for (uint32_t e = didx[i]; e < didx[i + 1]; ++e) {
+                    uint32_t wm = de[4 * e + 1];
+                    bool hi = de[4 * e + 2] || de[4 * e + 3];
+                    if ((gray & wm) == wm && hi) mono_ops += 5;
+                }
+            }
+        }
+        P.ops_per_term = ops + (setup + mono_ops) / steps;
+    }
+
+    P.c0 = w.c0;
+    P.e = w.e;
+    P.zero = w.zero;
+    zw_canonicalise(&P.c0, &P.e);
+    return SIM_OK;
+}

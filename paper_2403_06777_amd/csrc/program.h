@@ -1,0 +1,65 @@
+// Term programs: the IR text, its parser and printer, and the packer that turns a program
+// into the device image evaluated by the kernels.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "image.h"
+#include "zw.h"
+
+// A program denotes S = sqrt2^e * c * sum_x w^{phi(x)} prod_j F_j(x) (the parametric scalar
+// of Eq. 2, one decomposition term per assignment x of the p Boolean parameters).
+struct IrForm {
+    int cst;        // constant bit
+    uint64_t mask;  // bit i = parameter x_i enters the parity
+};
+struct IrNode {
+    int form, a, b;  // 1 + w^{a + b l(x)}   (the node subterm; b = 4 for 1 + e^{i(alpha + pi l)})
+};
+struct IrPair {
+    int f1, f2, a, b;  // 1 + w^{a + 4 l1} + w^{b + 4 l2} - w^{a + b + 4(l1 xor l2)}   (Eq. 3)
+};
+struct IrLin {
+    int c, form;  // phi += c l(x)
+};
+struct IrMono {
+    int c;
+    std::vector<int> vars;  // phi += c prod x_v
+};
+
+struct IrProgram {
+    int p = 0;
+    std::vector<IrForm> forms;
+    std::vector<IrNode> nodes;
+    std::vector<IrPair> pairs;
+    std::vector<IrLin> lin;
+    std::vector<IrMono> mono;
+    Zw scalar = zw_one();
+    int32_t e = 0;
+};
+
+bool ir_parse(const char *text, size_t len, IrProgram *out, std::string *err);
+std::string ir_print(const IrProgram &prog);
+
+struct PackedProgram {
+    ImgHeader hdr;
+    std::vector<uint8_t> blob;  // image words, padding, int64 value table
+    std::vector<int32_t> perm;  // bit j of a slice-ordered index is parameter perm[j]
+    int p = 0;                  // parameters of the program (terms = 2^p)
+    int q = 0;                  // pair factors turned into walk parameters
+    int walk_bits = 0;          // original parameters enumerated inside a slice
+    uint64_t n_slices = 1;
+    Zw c0 = zw_one();           // constant, canonical
+    int32_t e = 0;
+    bool zero = false;          // a constant factor vanished
+    int n_factors = 0, n_mono = 0, n_forms = 0;
+    int W = 1;
+    double ops_per_term = 0.0;  // algorithmic int32 lane-ops per term (see pack_program)
+};
+
+// Returns 0 or a negative SIM_E* code with *err set.  max_walk_bits caps the Gray walk.
+int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err);
+
+// exact value of one table entry: w^r * sqrt2^e * (1 + w)^d (d >= 0) or (1 + w^3)^(-d)
+Zw table_value(int d, int r, int e);

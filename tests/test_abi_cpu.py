@@ -1,0 +1,106 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-only paths
+(IR parsing, packing, error reporting) behave as documented.  No GPU needed."""
+
+import ctypes
+
+import pytest
+
+import paper_2403_06777_amd as zx
+import workloads as wl
+from paper_2403_06777_amd import binding
+from tests.helpers import header_functions
+
+
+def test_library_exports_every_declared_function():
+    lib = binding.lib()
+    declared = header_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    bound = {name for name, _, _ in binding.SIGNATURES}
+    assert set(declared) == bound
+
+
+def test_binding_exposes_c_names():
+    for name in header_functions():
+        assert hasattr(zx, name) or name in ("sim_last_error",), name
+
+
+def test_ir_info_kernel_sized():
+    prog = wl.kernel_sized_program(0)
+    info = zx.sim_ir_info(prog.to_text())
+    assert info["n_params"] == 32
+    assert info["n_factors"] == 64
+    assert info["n_monomials"] == len(prog.mono)
+    assert info["n_slices"] << info["walk_bits"] == 1 << 32
+
+
+@pytest.mark.parametrize("text,frag", [
+    ("zxir 2\n", "range"),
+    ("zxir 1\np 3\nforms 1\nf 0 ff\n", "parameter >= p"),
+    ("zxir 1\np 3\nforms 1\nf 0 1\nnodes 1\nn 4 0 1\n", "out of range"),
+    ("zxir 1\np 3\nforms 0\nnodes 0\npairs 0\nlin 0\nmono 0\nscalar 1 0 0 0 0\n", "end of program"),
+    ("zxir 1\np 3\nforms 0\nnodes 0\npairs 0\nlin 0\nmono 0\nscalar 1 0 0 0 0\nend\nextra\n", "after 'end'"),
+    ("zxir 1\np 70\n", "out of range"),
+    ("zxir 1\np 2\nforms 0\nnodes 0\npairs 0\nlin 0\nmono 1\nm 1 1 5\nscalar 1 0 0 0 0\nend\n", "out of range"),
+])
+def test_ir_errors_are_reported(text, frag):
+    with pytest.raises(zx.SimError) as ei:
+        zx.sim_ir_info(text)
+    assert ei.value.code == binding.SIM_EINVAL
+    assert frag in str(ei.value)
+
+
+def test_error_names_line():
+    text = "zxir 1\np 3\nforms 1\nf 0 1\nnodes 1\nn 0 x 1\n"
+    with pytest.raises(zx.SimError) as ei:
+        zx.sim_ir_info(text)
+    assert "line 6" in str(ei.value)
+
+
+def test_static_bound_refuses_overflow():
+    prog = wl.random_program(0, 60, n_nodes=80, general_ab=False)
+    with pytest.raises(zx.SimError) as ei:
+        zx.sim_ir_info(prog.to_text())
+    assert ei.value.code == binding.SIM_ERANGE
+
+
+def test_constant_factors_fold_and_zero_program():
+    prog = wl.ProgramSpec(3)
+    f = prog.add_form(1, 0)   # constant 1
+    prog.nodes = [(f, 0, 4)]  # 1 + w^4 = 0
+    info = zx.sim_ir_info(prog.to_text())
+    assert info["is_zero"] == 1
+    prog.nodes = [(f, 0, 2)]  # 1 + w^2, folded into the constant
+    info = zx.sim_ir_info(prog.to_text())
+    assert info["is_zero"] == 0 and info["n_factors"] == 0
+
+
+def test_pairs_add_walk_parameters():
+    t = wl.appendix_d_terms()[1]
+    info = zx.sim_ir_info(t.to_text())
+    assert info["n_params"] == 4
+    assert info["n_eval_params"] == 4 + len(t.pairs)
+
+
+def test_many_forms_pick_wider_vectors():
+    prog = wl.random_program(1, 20, n_nodes=40, n_lin=300)
+    info = zx.sim_ir_info(prog.to_text())
+    assert info["n_forms"] > 128
+
+
+def test_raw_add_is_exact_and_checks_overflow():
+    a = (2 ** 100, -5, 3, -(2 ** 90))
+    b = (2 ** 100, 7, -3, 2 ** 90 + 1)
+    assert zx.sim_raw_add(a, b) == (2 ** 101, 2, 0, 1)
+    with pytest.raises(zx.SimError):
+        zx.sim_raw_add((2 ** 126, 0, 0, 0), (2 ** 126, 0, 0, 0))
+
+
+def test_null_arguments_are_rejected():
+    lib = binding.lib()
+    assert lib.sim_ir_info(None, 0, None) == binding.SIM_EINVAL
+    assert lib.sim_program_info(None, None) == binding.SIM_EINVAL
+    out = binding.sim_zomega()
+    assert lib.sim_eval_amplitude(None, None, ctypes.byref(out)) == binding.SIM_EINVAL
+    assert b"null" in lib.sim_last_error()

@@ -1,0 +1,218 @@
+"""Parity of the HIP path with the oracle, through the C-ABI (needs an MI355X).
+
+Every expected value comes from the oracle (term-by-term evaluator) or from a closed form
+built from oracle results; the comparison is exact equality of canonical Z[w] scalars.
+"""
+
+import sys
+
+import pytest
+
+import paper_2403_06777_amd as zx
+import workloads as wl
+from oracle import zomega as zw
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_value(text):
+    h = zx.sim_program_from_ir(text)
+    try:
+        return zx.sim_eval_amplitude(h)
+    finally:
+        zx.sim_program_free(h)
+
+
+def oracle_value(o2, text):
+    return o2.evaluate(text)["canonical"]
+
+
+@pytest.mark.parametrize("p,factors,monos", [(4, 8, 10), (9, 16, 30), (13, 32, 60), (17, 64, 120), (20, 64, 200)])
+def test_kernel_sized_family_exhaustive(o2, p, factors, monos):
+    for seed in range(2):
+        prog = wl.kernel_sized_program(seed, p=p, n_factors=factors, n_monomials=monos)
+        text = prog.to_text()
+        say("kernel-sized family", p, factors, monos, seed)
+        assert gpu_value(text) == oracle_value(o2, text)
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 5, 8, 11, 14, 18])
+def test_random_programs_exhaustive(o2, p):
+    for seed in range(3):
+        prog = wl.random_program(seed, p, n_nodes=12, n_pairs=2 if p else 0, n_lin=6, n_mono=3 * p,
+                                 scalar_range=3, shared_forms=bool(seed % 2))
+        text = prog.to_text()
+        say("random program", p, seed)
+        assert gpu_value(text) == oracle_value(o2, text)
+
+
+@pytest.mark.parametrize("n_lin,p", [(80, 12), (200, 14), (420, 10)])
+def test_wide_form_vectors(o2, n_lin, p):
+    # more than 64, 128 and 256 forms: W = 4, 8 and 16 words per lane
+    prog = wl.random_program(7, p, n_nodes=30, n_lin=n_lin, n_mono=10, scalar_range=2)
+    text = prog.to_text()
+    info = zx.sim_ir_info(text)
+    say("wide forms", info["n_forms"])
+    assert gpu_value(text) == oracle_value(o2, text)
+
+
+def test_appendix_d_example_total():
+    total = None
+    for t in wl.appendix_d_terms():
+        (c, e) = gpu_value(t.to_text())
+        total = (c, e) if total is None else zw.add_scalar(*total, c, e)
+    assert total == zw.canonical((80, 0, 16, 0), 0)
+
+
+def test_zero_and_constant_programs(o2):
+    prog = wl.ProgramSpec(5)
+    f = prog.add_form(0, 0)
+    prog.nodes = [(f, 4, 0)]
+    assert gpu_value(prog.to_text()) == ((0, 0, 0, 0), 0)
+    prog = wl.ProgramSpec(0)
+    prog.scalar = (3, -1, 2, 0)
+    prog.sqrt2_exp = -3
+    text = prog.to_text()
+    assert gpu_value(text) == oracle_value(o2, text)
+
+
+@pytest.mark.parametrize("p,fpb", [(24, 3), (32, 4), (36, 6)])
+def test_closed_form_block_programs(o2, p, fpb):
+    # scrambled block-separable programs: the sum is the product of the block sums
+    full, blocks = wl.block_separable_program(p, p, factors_per_block=fpb, lin_per_block=2,
+                                              pairs_per_block=1 if p < 36 else 0, scramble=True)
+    expect = zw.ONE
+    for blk in blocks:
+        expect = zw.mul(expect, o2.evaluate(blk.to_text(), threads=1)["raw"])
+    say("closed form", p, fpb, "log2|expect|", max(abs(v) for v in expect).bit_length())
+    assert gpu_value(full.to_text()) == zw.canonical(expect, 0)
+
+
+def test_closed_form_with_monomials(o2):
+    full, blocks = wl.block_separable_program(5, 32, factors_per_block=3, lin_per_block=1, mono_per_block=3,
+                                              scramble=False)
+    expect = zw.ONE
+    for blk in blocks:
+        expect = zw.mul(expect, o2.evaluate(blk.to_text(), threads=1)["raw"])
+    say("closed form with monomials")
+    assert gpu_value(full.to_text()) == zw.canonical(expect, 0)
+
+
+def test_kernel_sized_full_size_sampled_slices(o2):
+    # p = 32: the whole sum equals the sum of range partials, and sampled ranges equal the
+    # oracle on exactly the same assignments
+    prog = wl.kernel_sized_program(0)
+    text = prog.to_text()
+    h = zx.sim_program_from_ir(text)
+    try:
+        info = zx.sim_program_info(h)
+        perm = zx.sim_program_layout(h)
+        wb, ns = info["walk_bits"], info["n_slices"]
+        say("full size", info)
+        whole = zx.sim_eval_amplitude(h)
+        parts = (0, 0, 0, 0)
+        G = 8
+        for g in range(G):
+            a, b = g * ns // G, (g + 1) * ns // G
+            parts = zx.sim_raw_add(parts, zx.sim_eval_range(h, a, b - a))
+        assert zx.sim_finalize(h, parts) == whole
+        rng = wl.SplitMix64(77, 0)
+        for _ in range(4):
+            s0 = rng.randint(0, ns - 16)
+            raw = zx.sim_eval_range(h, s0, 16)
+            ref = o2.evaluate(text, first=s0 << wb, count=16 << wb, perm=perm)["raw"]
+            say("slices", s0, raw, ref)
+            assert raw == ref
+    finally:
+        zx.sim_program_free(h)
+
+
+def test_range_partials_match_oracle_ranges(o2):
+    prog = wl.random_program(3, 16, n_nodes=20, n_pairs=2, n_lin=5, n_mono=30, scalar_range=2)
+    text = prog.to_text()
+    h = zx.sim_program_from_ir(text)
+    try:
+        info = zx.sim_program_info(h)
+        perm = zx.sim_program_layout(h)
+        wb, ns = info["walk_bits"], info["n_slices"]
+        for s0, n in [(0, 1), (3, 5), (ns - 7, 7), (0, ns)]:
+            raw = zx.sim_eval_range(h, s0, n)
+            ref = o2.evaluate(text, first=s0 << wb, count=n << wb, perm=perm)["raw"]
+            assert raw == ref
+        assert zx.sim_eval_range(h, 5, 0) == (0, 0, 0, 0)
+        with pytest.raises(zx.SimError):
+            zx.sim_eval_range(h, ns, 1)
+    finally:
+        zx.sim_program_free(h)
+
+
+def _batch_programs():
+    progs = []
+    for i in range(10):
+        p = [3, 7, 12, 16, 18, 0, 9, 14, 20, 11][i]
+        progs.append(wl.random_program(40 + i, p, n_nodes=10 + i, n_pairs=i % 3, n_lin=3 + (60 if i == 4 else 0),
+                                       n_mono=(2 * p if i % 2 else 0), scalar_range=2))
+    z = wl.ProgramSpec(4)
+    f = z.add_form(1, 0)
+    z.nodes = [(f, 0, 4)]
+    progs.append(z)
+    return [p.to_text() for p in progs]
+
+
+def test_batch_equals_single_evaluations(o2):
+    texts = _batch_programs()
+    hs = [zx.sim_program_from_ir(t) for t in texts]
+    try:
+        single = [zx.sim_eval_amplitude(h) for h in hs]
+        for t, s in zip(texts, single):
+            assert s == oracle_value(o2, t)
+        for tuning in (None, {"chunk_log2": 10}, {"chunk_log2": 14, "block_threads": 128, "blocks_per_cu": 2}):
+            say("batch", tuning)
+            assert zx.sim_eval_batch(hs, tuning=tuning) == single
+        # batch of ranges
+        infos = [zx.sim_program_info(h) for h in hs]
+        firsts = [i["n_slices"] // 3 for i in infos]
+        counts = [i["n_slices"] - f for f, i in zip(firsts, infos)]
+        raws = zx.sim_eval_ranges(hs, firsts, counts)
+        for h, f, c, r in zip(hs, firsts, counts, raws):
+            assert r == zx.sim_eval_range(h, f, c)
+    finally:
+        for h in hs:
+            zx.sim_program_free(h)
+
+
+def test_batch_plan_graph_replays(o2):
+    texts = _batch_programs()
+    hs = [zx.sim_program_from_ir(t) for t in texts]
+    plan = None
+    try:
+        single = [zx.sim_eval_amplitude(h) for h in hs]
+        plan = zx.sim_batch_plan_create(hs, {"chunk_log2": 12})
+        for rep in range(4):
+            say("plan replay", rep)
+            assert zx.sim_batch_plan_run(plan, len(hs)) == single
+            # eager work between replays
+            assert zx.sim_eval_amplitude(hs[rep]) == single[rep]
+    finally:
+        if plan:
+            zx.sim_batch_plan_free(plan)
+        for h in hs:
+            zx.sim_program_free(h)
+
+
+def test_torch_stream_is_accepted():
+    import torch
+    s = torch.cuda.Stream()
+    prog = wl.kernel_sized_program(3, p=14, n_factors=20, n_monomials=30)
+    h = zx.sim_program_from_ir(prog.to_text())
+    try:
+        assert zx.sim_eval_amplitude(h, s) == zx.sim_eval_amplitude(h)
+        val, ms = zx.sim_eval_timed(h, s)
+        assert val == zx.sim_eval_amplitude(h) and ms > 0
+    finally:
+        zx.sim_program_free(h)
