@@ -34,6 +34,12 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define SIM_API __attribute__((visibility("default")))
+#else
+#define SIM_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -118,7 +124,7 @@ typedef struct {
 
 /* Selects the device (hipSetDevice) and creates the library's state for it.  Optional:
  * every entry point initialises the current device on first use. */
-int sim_init(int device);
+SIM_API int sim_init(int device);
 
 /* Parses a "zxir 1" term program and uploads its packed image to the current device.
  * Text layout (whitespace-separated, '#' starts a comment, sections in this order):
@@ -135,61 +141,61 @@ int sim_init(int device);
  * The text need not be NUL-terminated.  SIM_EINVAL on a malformed text (message names the
  * line), SIM_ERANGE when p > 62 or the static bound (sum of |term| over all terms) could
  * exceed int128. */
-int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out);
+SIM_API int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out);
 
 /* Host-side compiler (Section 3): circuit text -> ZX diagram closed with |0^n> and the
  * query's effect -> parametric Clifford simplification with one Boolean parameter per
  * remaining T-like spider -> term program, uploaded like sim_program_from_ir.  opts may be
  * NULL.  SIM_EINVAL on a circuit or query error, SIM_ERANGE when p exceeds the cap. */
-int sim_compile(const char *circuit_text, size_t len, const sim_query *q,
+SIM_API int sim_compile(const char *circuit_text, size_t len, const sim_query *q,
                 const sim_compile_opts *opts, sim_program **out);
 
-int sim_program_info(const sim_program *prog, sim_info *out);
+SIM_API int sim_program_info(const sim_program *prog, sim_info *out);
 
 /* Host only (no device needed): parses and packs an IR text and reports what
  * sim_program_from_ir would create, without uploading anything.  Same errors. */
-int sim_ir_info(const char *ir_text, size_t len, sim_info *out);
+SIM_API int sim_ir_info(const char *ir_text, size_t len, sim_info *out);
 
 /* Host only: runs the compiler of sim_compile and writes the resulting IR text into buf
  * (cap bytes, NUL-terminated; *len_out receives the full length, SIM_ERANGE if it does not
  * fit).  info (may be NULL) receives what sim_program_info would report. */
-int sim_compile_to_ir(const char *circuit_text, size_t len, const sim_query *q,
+SIM_API int sim_compile_to_ir(const char *circuit_text, size_t len, const sim_query *q,
                       const sim_compile_opts *opts, char *buf, size_t cap, size_t *len_out,
                       sim_info *info);
 
 /* Writes the program's IR text (as parsed or as compiled, before packing) into buf (cap
  * bytes, NUL-terminated when it fits); *len_out receives the full length.  SIM_ERANGE
  * when cap is too small (nothing written). */
-int sim_program_ir(const sim_program *prog, char *buf, size_t cap, size_t *len_out);
+SIM_API int sim_program_ir(const sim_program *prog, char *buf, size_t cap, size_t *len_out);
 
 /* Assignment order of slices: slice s covers the 2^walk_bits assignments whose index, read
  * in the order perm[0..p-1] (bit j of the index is parameter perm[j]), lies in
  * [s << walk_bits, (s + 1) << walk_bits).  perm must hold p entries. */
-int sim_program_layout(const sim_program *prog, int32_t *perm, uint32_t cap);
+SIM_API int sim_program_layout(const sim_program *prog, int32_t *perm, uint32_t cap);
 
 /* The whole hot path for one program: sum over all 2^p assignments on the GPU, times the
  * constant, in canonical form. */
-int sim_eval_amplitude(const sim_program *prog, void *stream, sim_zomega *out);
+SIM_API int sim_eval_amplitude(const sim_program *prog, void *stream, sim_zomega *out);
 
 /* As sim_eval_amplitude, and *kernel_ms receives the duration of the evaluation kernel
  * alone, measured with HIP events recorded on `stream` right before and after its launch
  * (the finaliser and the result copy are outside the bracket). */
-int sim_eval_timed(const sim_program *prog, void *stream, sim_zomega *out, float *kernel_ms);
+SIM_API int sim_eval_timed(const sim_program *prog, void *stream, sim_zomega *out, float *kernel_ms);
 
 /* Raw partial sum over slices [first_slice, first_slice + n_slices) (flags = RAW): for
  * checkpoint/resume and sharding.  Partials over disjoint slices add exactly; finish with
  * sim_finalize. */
-int sim_eval_range(const sim_program *prog, uint64_t first_slice, uint64_t n_slices,
+SIM_API int sim_eval_range(const sim_program *prog, uint64_t first_slice, uint64_t n_slices,
                    void *stream, sim_zomega *raw);
 
 /* Applies the program's constant and sqrt2 power to a raw sum and canonicalises it (on
  * the device). */
-int sim_finalize(const sim_program *prog, const sim_zomega *raw, void *stream, sim_zomega *out);
+SIM_API int sim_finalize(const sim_program *prog, const sim_zomega *raw, void *stream, sim_zomega *out);
 
 /* Many programs of uneven size in one persistent launch: work items of 2^chunk_log2 terms
  * are pulled from a device queue; per-item partials are summed per program in a fixed
  * order, so each result is bit-identical to sim_eval_amplitude.  t may be NULL. */
-int sim_eval_batch(const sim_program *const *progs, size_t n, void *stream,
+SIM_API int sim_eval_batch(const sim_program *const *progs, size_t n, void *stream,
                    const sim_tuning *t, sim_zomega *out);
 
 /* Same as sim_eval_batch, but the launch sequence (queue reset, persistent kernel,
@@ -197,29 +203,29 @@ int sim_eval_batch(const sim_program *const *progs, size_t n, void *stream,
  * by sim_batch_plan_run.  The plan keeps the programs' device images referenced; the
  * programs must outlive the plan. */
 typedef struct sim_batch_plan sim_batch_plan;
-int sim_batch_plan_create(const sim_program *const *progs, size_t n, const sim_tuning *t,
+SIM_API int sim_batch_plan_create(const sim_program *const *progs, size_t n, const sim_tuning *t,
                           void *stream, sim_batch_plan **out);
-int sim_batch_plan_run(sim_batch_plan *plan, void *stream, sim_zomega *out);
-void sim_batch_plan_free(sim_batch_plan *plan);
+SIM_API int sim_batch_plan_run(sim_batch_plan *plan, void *stream, sim_zomega *out);
+SIM_API void sim_batch_plan_free(sim_batch_plan *plan);
 
 /* Continuous batching primitive: evaluates, in one launch, the next slice range of each
  * active request.  first_slice[i] and n_slices[i] select the range of progs[i]; the raw
  * partials are written to raw[i].  Used by the serving loop, which adds partials exactly
  * and finalises a request when its slices are done. */
-int sim_eval_ranges(const sim_program *const *progs, const uint64_t *first_slice,
+SIM_API int sim_eval_ranges(const sim_program *const *progs, const uint64_t *first_slice,
                     const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
                     sim_zomega *raw);
 
 /* Adds two raw partials of the same program exactly (host, int128 with overflow check). */
-int sim_raw_add(const sim_zomega *a, const sim_zomega *b, sim_zomega *out);
+SIM_API int sim_raw_add(const sim_zomega *a, const sim_zomega *b, sim_zomega *out);
 
-void sim_program_free(sim_program *prog);
+SIM_API void sim_program_free(sim_program *prog);
 
 /* thread-local message of the last failing call on this thread ("" if none) */
-const char *sim_last_error(void);
+SIM_API const char *sim_last_error(void);
 
 /* number of compute units of the current device (0 if unknown) */
-int sim_device_cus(void);
+SIM_API int sim_device_cus(void);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ def header_functions():
     """names of the functions declared in include/zxpar.h"""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(sim_\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:SIM_API\s+)?(?:int|void|const char \*)\s*\*?\s*(sim_\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
