@@ -143,45 +143,51 @@ def exact_state(text: str) -> ExactState:
 
 
 def complex_state(text: str) -> np.ndarray:
-    """complex128 state vector, axis i of the reshaped tensor is qubit i"""
+    """complex128 state vector; axis n-1-q of the (2,)*n tensor is qubit q, so the flat
+    index of a basis state is sum_q y_q 2^q.  Gates update views of the tensor in place."""
+    import torch  # plain CPU tensor ops (multithreaded); no GPU involved
+
     n, gates = parse_circuit(text)
     if n > 26:
         raise ValueError("too many qubits for a dense complex state")
-    psi = np.zeros((2,) * n, dtype=np.complex128)
+    psi = torch.zeros((2,) * n, dtype=torch.complex128)
     psi[(0,) * n] = 1.0
     s = 1 / np.sqrt(2)
-    phases = {k: np.exp(1j * np.pi * v / 4) for k, v in DIAG_PHASE.items()}
+    phases = {k: complex(np.exp(1j * np.pi * v / 4)) for k, v in DIAG_PHASE.items()}
 
-    def ax(q):  # numpy axis of qubit q (index order is bit n-1 ... bit 0 in C order)
-        return n - 1 - q
+    def sl(**fixed):  # index tuple fixing some qubits to 0/1
+        idx = [slice(None)] * n
+        for q, v in fixed.items():
+            idx[n - 1 - int(q[1:])] = v
+        return tuple(idx)
 
     for g in gates:
         name = g[0]
         if name == "h":
-            a = ax(g[1])
-            x0 = np.take(psi, 0, axis=a)
-            x1 = np.take(psi, 1, axis=a)
-            psi = np.stack([(x0 + x1) * s, (x0 - x1) * s], axis=a)
+            x0 = psi[sl(**{f"q{g[1]}": 0})]
+            x1 = psi[sl(**{f"q{g[1]}": 1})]
+            tmp = x0.clone()
+            x0 += x1
+            x0 *= s
+            x1 -= tmp
+            x1 *= -s
         elif name in phases:
-            a = ax(g[1])
-            idx = [slice(None)] * n
-            idx[a] = 1
-            psi[tuple(idx)] *= phases[name]
+            psi[sl(**{f"q{g[1]}": 1})] *= phases[name]
         elif name == "x":
-            psi = np.flip(psi, axis=ax(g[1])).copy()
+            x0 = psi[sl(**{f"q{g[1]}": 0})]
+            x1 = psi[sl(**{f"q{g[1]}": 1})]
+            tmp = x0.clone()
+            x0.copy_(x1)
+            x1.copy_(tmp)
         elif name == "cx":
-            ac, at = ax(g[1]), ax(g[2])
-            idx = [slice(None)] * n
-            idx[ac] = 1
-            sub = psi[tuple(idx)]
-            at2 = at if at < ac else at - 1
-            psi[tuple(idx)] = np.flip(sub, axis=at2).copy()
+            a = psi[sl(**{f"q{g[1]}": 1, f"q{g[2]}": 0})]
+            b = psi[sl(**{f"q{g[1]}": 1, f"q{g[2]}": 1})]
+            tmp = a.clone()
+            a.copy_(b)
+            b.copy_(tmp)
         elif name == "cz":
-            idx = [slice(None)] * n
-            idx[ax(g[1])] = 1
-            idx[ax(g[2])] = 1
-            psi[tuple(idx)] *= -1
-    return psi.reshape(-1)
+            psi[sl(**{f"q{g[1]}": 1, f"q{g[2]}": 1})] *= -1
+    return psi.reshape(-1).numpy()
 
 
 def complex_amplitude(text: str, out_bits: str) -> complex:

@@ -1,0 +1,168 @@
+"""The host compiler (circuit -> term program), checked on the CPU: each compiled program is
+evaluated by the oracle's term-by-term evaluator and must equal the exact state-vector
+amplitude or marginal, bit for bit in canonical Z[w] form."""
+
+import time
+
+import numpy as np
+import pytest
+
+import paper_2403_06777_amd as zx
+import workloads as wl
+from oracle import statevector as sv
+from oracle import zomega as zw
+from workloads.circuits import Circuit
+
+
+def compiled_value(o2, text, query, **kw):
+    ir, info = zx.sim_compile_to_ir(text, query, **kw)
+    return o2.evaluate(ir)["canonical"], info
+
+
+def _rand_circuit(seed, n, ng, nt, extras=True):
+    rng = wl.SplitMix64(700, seed)
+    c = wl.random_clifford_t(rng, n, ng, nt)
+    if extras and n >= 2:
+        for _ in range(ng // 6):
+            g = ["x", "z", "sdg", "tdg", "cz"][rng.randint(0, 4)]
+            pos = rng.randint(0, len(c.gates))
+            if g == "cz":
+                a, b = rng.sample_distinct(n, 2)
+                c.gates.insert(pos, ("cz", a, b))
+            else:
+                c.gates.insert(pos, (g, rng.randint(0, n - 1)))
+    return c
+
+
+def _bits(rng, n):
+    return "".join("1" if rng.bernoulli(0.5) else "0" for _ in range(n))
+
+
+def test_tiny_configuration_all_seeds(o2):
+    # 6 qubits, 60 Clifford gates, 8 T gates, <0^6|C|0^6>, seeds 0..99
+    for seed in range(100):
+        c, y = wl.tiny_circuit(seed)
+        text = wl.circuit_text(c)
+        got, info = compiled_value(o2, text, zx.amplitude_query(y))
+        assert got == sv.exact_amplitude(text, y), seed
+        assert info["n_params"] <= 8
+
+
+@pytest.mark.parametrize("eliminate", [True, False])
+def test_random_circuits_amplitudes(o2, eliminate):
+    for seed in range(30):
+        n = 2 + seed % 9
+        c = _rand_circuit(seed, n, 15 + 4 * seed, seed % 11)
+        text = wl.circuit_text(c)
+        y = _bits(wl.SplitMix64(701, seed), n)
+        got, _ = compiled_value(o2, text, zx.amplitude_query(y), eliminate_constraints=eliminate)
+        assert got == sv.exact_amplitude(text, y), seed
+
+
+def test_random_circuits_marginals(o2):
+    for seed in range(30):
+        n = 2 + seed % 8
+        c = _rand_circuit(100 + seed, n, 20 + 3 * seed, seed % 9)
+        text = wl.circuit_text(c)
+        q, a = seed % n, (seed // 2) % 2
+        got, _ = compiled_value(o2, text, zx.marginal_query(n, q, a))
+        assert got == sv.exact_marginal(text, q, a), seed
+
+
+def test_clifford_circuits_need_no_parameters(o2):
+    for seed in range(15):
+        n = 3 + seed % 6
+        c = _rand_circuit(200 + seed, n, 60, 0)
+        c.gates = [g for g in c.gates if g[0] not in ("t", "tdg")]
+        text = wl.circuit_text(c)
+        y = _bits(wl.SplitMix64(702, seed), n)
+        got, info = compiled_value(o2, text, zx.amplitude_query(y))
+        assert info["n_params"] == 0
+        assert got == sv.exact_amplitude(text, y)
+
+
+def test_t_substitution_identities(o2):
+    # S -> T T, Z -> T^4 and inserting T^8 or T T^dag leave the amplitude unchanged
+    for seed in range(8):
+        n = 4
+        c = _rand_circuit(300 + seed, n, 40, 4, extras=False)
+        y = _bits(wl.SplitMix64(703, seed), n)
+        base, _ = compiled_value(o2, wl.circuit_text(c), zx.amplitude_query(y))
+        g2 = []
+        for g in c.gates:
+            if g[0] == "s":
+                g2 += [("t", g[1]), ("t", g[1])]
+            else:
+                g2.append(g)
+        g2[len(g2) // 2:len(g2) // 2] = [("t", 1)] * 8 + [("t", 2), ("tdg", 2)] + [("t", 3)] * 4 + [("z", 3)]
+        alt, _ = compiled_value(o2, wl.circuit_text(Circuit(n, g2)), zx.amplitude_query(y))
+        assert alt == base == sv.exact_amplitude(wl.circuit_text(c), y)
+
+
+def test_born_rule_sums(o2):
+    # sum_y |A(y)|^2 = 1 and P(0) + P(1) = 1 from compiled programs alone
+    n = 4
+    c = _rand_circuit(400, n, 40, 6)
+    text = wl.circuit_text(c)
+    tot = ((0, 0, 0, 0), 0)
+    for i in range(2 ** n):
+        y = "".join(str(i >> k & 1) for k in range(n))
+        z, e = compiled_value(o2, text, zx.amplitude_query(y))[0]
+        tot = zw.add_scalar(*tot, *zw.canonical(zw.mul(z, zw.conj(z)), 2 * e))
+    assert tot == ((1, 0, 0, 0), 0)
+    for q in range(n):
+        p0 = compiled_value(o2, text, zx.marginal_query(n, q, 0))[0]
+        p1 = compiled_value(o2, text, zx.marginal_query(n, q, 1))[0]
+        assert zw.add_scalar(*p0, *p1) == ((1, 0, 0, 0), 0)
+
+
+def test_circuit_then_inverse_is_identity(o2):
+    c = _rand_circuit(401, 5, 60, 8)
+    inv = sv.inverse_gates(c.gates)
+    text = wl.circuit_text(Circuit(5, c.gates + inv))
+    got, _ = compiled_value(o2, text, zx.amplitude_query("00000"))
+    assert got == ((1, 0, 0, 0), 0)
+
+
+@pytest.mark.slow
+def test_circuit_scale_against_complex_state_vector(o2):
+    # 24 qubits, 600 Clifford + 40 T: the compiled program (evaluated exactly by the
+    # oracle) agrees with a complex128 state vector within 1e-9 relative
+    c, y = wl.circuit_scale(0)
+    text = wl.circuit_text(c)
+    got, info = compiled_value(o2, text, zx.amplitude_query(y))
+    assert info["n_params"] <= 40
+    amp = sv.complex_amplitude(text, y)
+    val = zw.to_complex(*got)
+    assert abs(val - amp) <= 1e-9 * max(abs(amp), 1e-12)
+
+
+def test_circuit_errors():
+    q = zx.amplitude_query("00")
+    for text, frag in [("h 0\n", "before 'qubits'"), ("qubits 2\nh 5\n", "line 2"),
+                       ("qubits 2\nfoo 1\n", "unknown gate"), ("qubits 2\ncx 1 1\n", "one qubit"),
+                       ("qubits 2\nh 0\nqubits 3\n", "twice")]:
+        with pytest.raises(zx.SimError) as ei:
+            zx.sim_compile_to_ir(text, q)
+        assert frag in str(ei.value)
+    with pytest.raises(zx.SimError):
+        zx.sim_compile_to_ir("qubits 3\nh 0\n", q)  # query size mismatch
+
+
+def test_parameter_cap():
+    c, y = wl.circuit_scale(1)
+    text = wl.circuit_text(c)
+    _, info = zx.sim_compile_to_ir(text, zx.amplitude_query(y))
+    with pytest.raises(zx.SimError) as ei:
+        zx.sim_compile_to_ir(text, zx.amplitude_query(y), p_cap=info["n_params"] - 1)
+    assert ei.value.code == zx.binding.SIM_ERANGE
+
+
+def test_compile_is_fast_and_deterministic():
+    c, y = wl.circuit_scale(2)
+    text = wl.circuit_text(c)
+    t0 = time.time()
+    a = zx.sim_compile_to_ir(text, zx.amplitude_query(y))
+    b = zx.sim_compile_to_ir(text, zx.amplitude_query(y))
+    assert a[0] == b[0]
+    assert time.time() - t0 < 5
