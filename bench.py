@@ -44,6 +44,110 @@ def cpu_baseline(ir_text: str, p: int, target_s: float) -> dict:
             "sample": f"first {n} of the 2^{p} assignments (binary order), {dt:.1f} s on {cores} threads"}
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    return xs[min(len(xs) - 1, max(0, int(round(q * (len(xs) - 1)))))]
+
+
+def batch_section(stream, p_cap: int) -> dict:
+    """512 amplitude queries of uneven size: one autotuned, graph-captured persistent launch
+    versus one launch per query on the same stream; every result must agree exactly."""
+    import paper_2403_06777_amd as zx
+    from paper_2403_06777_amd import runtime
+    import workloads as wl
+
+    qs = wl.batch_queries(512)
+    handles, ps, rejected = [], [], 0
+    t0 = time.perf_counter()
+    for c, y in qs:
+        try:
+            h = zx.sim_compile(wl.circuit_text(c), zx.amplitude_query(y), p_cap=p_cap)
+        except zx.SimError:
+            rejected += 1
+            continue
+        handles.append(h)
+        ps.append(zx.sim_program_info(h)["n_params"])
+    compile_s = time.perf_counter() - t0
+    terms = sum(1 << p for p in ps)
+    try:
+        # one launch per query (same kernel, same stream); completion time of each query
+        for h in handles[:8]:
+            zx.sim_eval_amplitude(h, stream)
+        single, done_at, per_call = [], [], []
+        t0 = time.perf_counter()
+        for h in handles:
+            t1 = time.perf_counter()
+            single.append(zx.sim_eval_amplitude(h, stream))
+            t2 = time.perf_counter()
+            per_call.append(t2 - t1)
+            done_at.append(t2 - t0)
+        single_s = time.perf_counter() - t0
+        tuning = runtime.autotune(handles, reps=1, stream=stream)
+        plan = runtime.BatchPlan(handles, tuning, stream)
+        res = plan.run(stream)
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            res = plan.run(stream)
+            best = min(best, time.perf_counter() - t0)
+        plan.free()
+        t0 = time.perf_counter()
+        eager = zx.sim_eval_batch(handles, stream, tuning)
+        eager_s = time.perf_counter() - t0
+        if res != single or eager != single:
+            raise SystemExit("batched results differ from single-launch results")
+    finally:
+        for h in handles:
+            zx.sim_program_free(h)
+    return {
+        "workload": "512 amplitude queries: circuits of U{10..40} qubits, U{200..1000} Clifford gates, "
+                    "U{10..50} T gates, random output strings (seed = query index)",
+        "queries": len(qs), "rejected_p_cap": rejected, "p_cap": p_cap,
+        "p_min": min(ps), "p_median": sorted(ps)[len(ps) // 2], "p_max": max(ps),
+        "terms": terms, "compile_s": compile_s,
+        "batched_graph_s": best, "batched_eager_s": eager_s, "single_launch_s": single_s,
+        "batched_terms_per_s": terms / best, "single_launch_terms_per_s": terms / single_s,
+        "speedup": single_s / best,
+        "latency_batched_p50_s": best, "latency_batched_p99_s": best,
+        "latency_single_p50_s": percentile(done_at, 0.5), "latency_single_p99_s": percentile(done_at, 0.99),
+        "single_call_p50_s": percentile(per_call, 0.5), "single_call_p99_s": percentile(per_call, 0.99),
+        "tuning": tuning, "results_identical": True,
+    }
+
+
+def serve_section(stream, n_requests: int, p_cap: int) -> dict:
+    """Poisson stream of 70% amplitudes / 30% single-qubit marginals over a pool of 64
+    circuits, continuous batching versus one-launch-per-query FIFO, rate swept around the
+    measured single-query service rate."""
+    import paper_2403_06777_amd.serving as S
+    import workloads as wl
+
+    pool = wl.serving_pool(64)
+    backend = S.ZxBackend(stream=stream, p_cap=p_cap)
+    probe = S.make_stream(pool, 80, rate=1e6, seed=99)
+    st = S.run_fifo(backend, probe, realtime=False)
+    mu = st.done / st.wall if st.wall > 0 else 1.0
+    rows = []
+    for mult in (0.25, 0.5, 1.0, 2.0, 4.0):
+        rate = mult * mu
+        reqs = S.make_stream(pool, n_requests, rate=rate, seed=int(mult * 100))
+        srv = S.Server(backend, mem_budget=256 << 20, max_active=256, tick_terms=1 << 27, compile_workers=8)
+        try:
+            a = srv.run(reqs, realtime=True).summary()
+        finally:
+            srv.close()
+        fifo_reqs = S.make_stream(pool, n_requests, rate=rate, seed=int(mult * 100))
+        b = S.run_fifo(backend, fifo_reqs, realtime=True).summary()
+        same = all(x.result == y.result for x, y in zip(reqs, fifo_reqs) if x.status == y.status == "done")
+        rows.append({"rate_per_s": rate, "rate_x_service": mult, "continuous": a, "fifo": b,
+                     "results_identical": same})
+    return {"workload": "Poisson stream, 70% amplitudes / 30% marginals P(q=v) by doubled diagram, pool of "
+                        "64 circuits (U{20..50} qubits, U{20..80} T, U{200..1000} Clifford gates)",
+            "requests_per_rate": n_requests, "p_cap": p_cap, "service_rate_per_s": mu, "rates": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +156,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--p-cap", type=int, default=36)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -134,9 +242,13 @@ def main():
         },
         "result": {"coeffs": [str(c) for c in ref[0]], "sqrt2_exp": ref[1]},
     }
+    zx.sim_program_free(h)
+    if not args.no_batch:
+        out["batch"] = batch_section(stream, args.p_cap)
+    if not args.no_serve:
+        out["serving"] = serve_section(stream, args.serve_requests, min(args.p_cap, 32))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(text, p, args.cpu_seconds)
-    zx.sim_program_free(h)
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,378 @@
+"""Continuous-batching server for amplitude and marginal queries.
+
+Requests arrive over time (open loop).  Each is compiled on a host worker thread (the
+reduction of Section 3 runs once per query), then admitted when a slot is free and its
+program fits the device-memory budget; compiled programs stay resident in an LRU cache so
+repeated queries skip compilation.  Every tick runs ONE batched launch
+(sim_eval_ranges) that evaluates the next chunk of slices of every active request; the
+raw partial sums are added exactly, and a request whose slices are all done is finalised
+on the device and answered.  Requests that arrive while others are on the GPU therefore
+join the next tick: their work overlaps on the device with the requests already running.
+
+Because partial sums over disjoint slices add exactly in Z[w], a result does not depend
+on how its slices were chunked or which other requests shared its launches: it is
+bit-identical to a solo evaluation.
+
+The backend is injectable (tests drive the scheduling logic with a fake one on the CPU);
+ZxBackend is the real one over the C-ABI.
+"""
+
+import collections
+import concurrent.futures as cf
+import hashlib
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+from . import binding as B
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds after the start of the run
+    circuit: str
+    kind: str  # "amplitude" or "marginal"
+    bits: str = ""
+    n_qubits: int = 0
+    qubit: int = 0
+    value: int = 0
+    status: str = "pending"  # done | rejected
+    result: Optional[Tuple] = None
+    error: str = ""
+    t_admit: Optional[float] = None
+    t_done: Optional[float] = None
+    terms: int = 0
+    p: int = -1
+
+    def key(self) -> Tuple:
+        h = hashlib.sha1(self.circuit.encode()).hexdigest()
+        if self.kind == "amplitude":
+            return (h, "a", self.bits)
+        return (h, "m", self.n_qubits, self.qubit, self.value)
+
+    def latency(self) -> Optional[float]:
+        return None if self.t_done is None else self.t_done - self.arrival
+
+
+class ZxBackend:
+    """The library, through its C-ABI."""
+
+    def __init__(self, stream=None, tuning: Optional[dict] = None, p_cap: int = 40):
+        self.stream = stream
+        self.tuning = tuning
+        self.p_cap = p_cap
+
+    def compile(self, req: Request):
+        if req.kind == "amplitude":
+            q = B.amplitude_query(req.bits)
+        else:
+            q = B.marginal_query(req.n_qubits, req.qubit, req.value)
+        h = B.sim_compile(req.circuit, q, p_cap=self.p_cap)
+        return h, B.sim_program_info(h)
+
+    def eval_ranges(self, handles, firsts, counts):
+        return B.sim_eval_ranges(handles, firsts, counts, self.stream, self.tuning)
+
+    def raw_add(self, a, b):
+        return B.sim_raw_add(a, b)
+
+    def finalize(self, handle, raw):
+        return B.sim_finalize(handle, raw, self.stream)
+
+    def evaluate(self, handle):
+        return B.sim_eval_amplitude(handle, self.stream)
+
+    def free(self, handle):
+        B.sim_program_free(handle)
+
+
+@dataclass
+class _Entry:
+    handle: int
+    info: dict
+    bytes: int
+    users: int = 0
+
+
+@dataclass
+class _Active:
+    req: Request
+    entry: _Entry
+    next_slice: int = 0
+    raw: Tuple = (0, 0, 0, 0)
+
+
+@dataclass
+class ServeStats:
+    done: int = 0
+    rejected: int = 0
+    ticks: int = 0
+    held_for_memory: int = 0
+    cache_hits: int = 0
+    terms: int = 0
+    wall: float = 0.0
+    latencies: List[float] = field(default_factory=list)
+
+    def summary(self) -> dict:
+        lat = sorted(self.latencies)
+
+        def pct(q):
+            if not lat:
+                return None
+            i = min(len(lat) - 1, max(0, int(round(q * (len(lat) - 1)))))
+            return lat[i]
+
+        return {"done": self.done, "rejected": self.rejected, "ticks": self.ticks,
+                "held_for_memory": self.held_for_memory, "cache_hits": self.cache_hits,
+                "terms": self.terms, "wall_s": self.wall,
+                "terms_per_s": self.terms / self.wall if self.wall > 0 else None,
+                "p50_s": pct(0.5), "p99_s": pct(0.99)}
+
+
+class ProgramCache:
+    """Resident compiled programs, LRU, bounded by a device-memory budget."""
+
+    def __init__(self, backend, budget_bytes: int):
+        self.backend = backend
+        self.budget = budget_bytes
+        self.entries: "collections.OrderedDict[Tuple, _Entry]" = collections.OrderedDict()
+        self.used = 0
+
+    def get(self, key) -> Optional[_Entry]:
+        e = self.entries.get(key)
+        if e is not None:
+            self.entries.move_to_end(key)
+        return e
+
+    def make_room(self, need: int) -> bool:
+        if need > self.budget:
+            return False
+        for key in list(self.entries.keys()):
+            if self.used + need <= self.budget:
+                break
+            e = self.entries[key]
+            if e.users == 0:
+                self.backend.free(e.handle)
+                self.used -= e.bytes
+                del self.entries[key]
+        return self.used + need <= self.budget
+
+    def put(self, key, entry: _Entry):
+        self.entries[key] = entry
+        self.used += entry.bytes
+
+    def clear(self):
+        for e in self.entries.values():
+            self.backend.free(e.handle)
+        self.entries.clear()
+        self.used = 0
+
+
+class Server:
+    def __init__(self, backend, mem_budget: int = 64 << 20, max_active: int = 256, tick_terms: int = 1 << 27,
+                 compile_workers: int = 4, scratch_per_request: int = 4096):
+        self.backend = backend
+        self.cache = ProgramCache(backend, mem_budget)
+        self.max_active = max_active
+        self.tick_terms = tick_terms
+        self.pool = cf.ThreadPoolExecutor(max_workers=compile_workers)
+        self.scratch_per_request = scratch_per_request
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+        self.cache.clear()
+
+    def _compile(self, req: Request):
+        return self.backend.compile(req)
+
+    def run(self, requests: List[Request], realtime: bool = True) -> ServeStats:
+        stats = ServeStats()
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        compiling: Dict[int, Tuple[Request, cf.Future]] = {}
+        held: "collections.deque[Tuple[Request, int, dict]]" = collections.deque()  # compiled, no room yet
+        waiting: "collections.deque[Tuple[Request, _Entry]]" = collections.deque()  # resident, pinned
+        active: List[_Active] = []
+        inflight: Dict[Tuple, cf.Future] = {}
+        freed = set()  # handles of programs refused for size (shared by duplicate requests)
+        start = time.perf_counter()
+        now = lambda: time.perf_counter() - start  # noqa: E731
+
+        def reject(req, msg):
+            req.status, req.error, req.t_done = "rejected", msg, now()
+            stats.rejected += 1
+
+        def place(req, handle, info) -> bool:
+            """make the compiled program resident (pinned) if the budget allows"""
+            key = req.key()
+            ent = self.cache.get(key)
+            if ent is None:
+                need = int(info["image_bytes"]) + self.scratch_per_request
+                if need > self.cache.budget:
+                    if handle not in freed:
+                        self.backend.free(handle)
+                        freed.add(handle)
+                    inflight.pop(key, None)
+                    reject(req, "SIM_EBUSY: program exceeds the device-memory budget")
+                    return True
+                if not self.cache.make_room(need):
+                    return False
+                ent = _Entry(handle, info, need)
+                self.cache.put(key, ent)
+            inflight.pop(key, None)
+            ent.users += 1
+            waiting.append((req, ent))
+            return True
+
+        while pending or compiling or held or waiting or active:
+            t = now()
+            # arrivals: resident programs are pinned and wait for a slot, others compile
+            while pending and (pending[0].arrival <= t or not realtime):
+                req = pending.popleft()
+                key = req.key()
+                ent = self.cache.get(key)
+                if ent is not None:
+                    stats.cache_hits += 1
+                    ent.users += 1
+                    waiting.append((req, ent))
+                    continue
+                fut = inflight.get(key)
+                if fut is None:
+                    fut = self.pool.submit(self._compile, req)
+                    inflight[key] = fut
+                compiling[req.rid] = (req, fut)
+            # finished compilations become resident when the memory budget allows
+            for rid in list(compiling.keys()):
+                req, fut = compiling[rid]
+                if not fut.done():
+                    continue
+                del compiling[rid]
+                try:
+                    handle, info = fut.result()
+                except B.SimError as e:
+                    inflight.pop(req.key(), None)
+                    reject(req, str(e))
+                    continue
+                if not place(req, handle, info):
+                    stats.held_for_memory += 1
+                    held.append((req, handle, info))
+            for _ in range(len(held)):
+                req, handle, info = held.popleft()
+                if not place(req, handle, info):
+                    held.append((req, handle, info))
+            # admission to a slot
+            while waiting and len(active) < self.max_active:
+                req, ent = waiting.popleft()
+                req.t_admit = now()
+                req.p = ent.info["n_params"]
+                req.terms = 1 << req.p
+                if ent.info["is_zero"]:
+                    req.result = self.backend.finalize(ent.handle, (0, 0, 0, 0))
+                    self._finish(req, ent, stats, now())
+                    continue
+                active.append(_Active(req, ent))
+            if not active:
+                if compiling or held:
+                    time.sleep(0.0002)
+                elif pending and realtime and not waiting:
+                    wait = pending[0].arrival - now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                continue
+            # one tick: the next chunk of every active request in a single launch
+            share = max(1, self.tick_terms // len(active))
+            handles, firsts, counts = [], [], []
+            for a in active:
+                info = a.entry.info
+                per = max(1, share >> info["walk_bits"])
+                cnt = min(per, info["n_slices"] - a.next_slice)
+                handles.append(a.entry.handle)
+                firsts.append(a.next_slice)
+                counts.append(cnt)
+            raws = self.backend.eval_ranges(handles, firsts, counts)
+            stats.ticks += 1
+            still = []
+            for a, cnt, raw in zip(active, counts, raws):
+                a.raw = self.backend.raw_add(a.raw, raw)
+                a.next_slice += cnt
+                if a.next_slice >= a.entry.info["n_slices"]:
+                    a.req.result = self.backend.finalize(a.entry.handle, a.raw)
+                    self._finish(a.req, a.entry, stats, now())
+                else:
+                    still.append(a)
+            active = still
+        stats.wall = now()
+        return stats
+
+    def _finish(self, req: Request, ent: _Entry, stats: ServeStats, t: float):
+        ent.users -= 1
+        req.status = "done"
+        req.t_done = t
+        stats.done += 1
+        stats.terms += req.terms
+        stats.latencies.append(req.latency())
+
+
+def run_fifo(backend, requests: List[Request], realtime: bool = True, cache_budget: int = 64 << 20) -> ServeStats:
+    """Baseline: one request at a time in arrival order, compiled (with the same resident
+    program cache) and evaluated by one launch of its own."""
+    stats = ServeStats()
+    cache = ProgramCache(backend, cache_budget)
+    start = time.perf_counter()
+    now = lambda: time.perf_counter() - start  # noqa: E731
+    try:
+        for req in sorted(requests, key=lambda r: r.arrival):
+            if realtime:
+                wait = req.arrival - now()
+                if wait > 0:
+                    time.sleep(wait)
+            key = req.key()
+            ent = cache.get(key)
+            if ent is None:
+                try:
+                    handle, info = backend.compile(req)
+                except B.SimError as e:
+                    req.status, req.error, req.t_done = "rejected", str(e), now()
+                    stats.rejected += 1
+                    continue
+                ent = _Entry(handle, info, int(info["image_bytes"]))
+                cache.make_room(ent.bytes)
+                cache.put(key, ent)
+            else:
+                stats.cache_hits += 1
+            req.t_admit = now()
+            req.p = ent.info["n_params"]
+            req.terms = 1 << req.p
+            req.result = backend.evaluate(ent.handle)
+            req.status = "done"
+            req.t_done = now()
+            stats.done += 1
+            stats.terms += req.terms
+            stats.latencies.append(req.latency())
+    finally:
+        stats.wall = now()
+        cache.clear()
+    return stats
+
+
+def make_stream(pool, n_requests: int, rate: float, seed: int = 0, marginal_frac: float = 0.3) -> List[Request]:
+    """Poisson arrivals at `rate` per second; each request picks a pool circuit, and is a
+    marginal P(q = v) with probability marginal_frac, else an amplitude of a random string."""
+    import math
+    from workloads import SplitMix64, circuit_text
+
+    rng = SplitMix64(40, seed)
+    t = 0.0
+    out = []
+    texts = [circuit_text(c) for c in pool]
+    for i in range(n_requests):
+        t += -math.log(1.0 - rng.uniform()) / rate
+        ci = rng.randint(0, len(pool) - 1)
+        c = pool[ci]
+        if rng.uniform() < marginal_frac:
+            out.append(Request(i, t, texts[ci], "marginal", n_qubits=c.n_qubits,
+                               qubit=rng.randint(0, c.n_qubits - 1), value=rng.randint(0, 1)))
+        else:
+            bits = "".join("1" if rng.bernoulli(0.5) else "0" for _ in range(c.n_qubits))
+            out.append(Request(i, t, texts[ci], "amplitude", bits=bits, n_qubits=c.n_qubits))
+    return out
