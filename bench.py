@@ -44,6 +44,10 @@ def cpu_baseline(ir_text: str, p: int, target_s: float) -> dict:
             "sample": f"first {n} of the 2^{p} assignments (binary order), {dt:.1f} s on {cores} threads"}
 
 
+def progress(*args):
+    print("[bench]", *args, file=sys.stderr, flush=True)
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -71,6 +75,7 @@ def batch_section(stream, p_cap: int) -> dict:
         ps.append(zx.sim_program_info(h)["n_params"])
     compile_s = time.perf_counter() - t0
     terms = sum(1 << p for p in ps)
+    progress(f"batch: compiled {len(handles)} programs in {compile_s:.1f} s, {terms:.3e} terms")
     try:
         # one launch per query (same kernel, same stream); completion time of each query
         for h in handles[:8]:
@@ -84,6 +89,7 @@ def batch_section(stream, p_cap: int) -> dict:
             per_call.append(t2 - t1)
             done_at.append(t2 - t0)
         single_s = time.perf_counter() - t0
+        progress(f"batch: one launch per query {single_s:.3f} s; autotuning")
         tuning = runtime.autotune(handles, reps=1, stream=stream)
         plan = runtime.BatchPlan(handles, tuning, stream)
         res = plan.run(stream)
@@ -129,6 +135,7 @@ def serve_section(stream, n_requests: int, p_cap: int) -> dict:
     probe = S.make_stream(pool, 80, rate=1e6, seed=99)
     st = S.run_fifo(backend, probe, realtime=False)
     mu = st.done / st.wall if st.wall > 0 else 1.0
+    progress(f"serve: single-query service rate {mu:.1f}/s")
     rows = []
     for mult in (0.25, 0.5, 1.0, 2.0, 4.0):
         rate = mult * mu
@@ -143,6 +150,8 @@ def serve_section(stream, n_requests: int, p_cap: int) -> dict:
         same = all(x.result == y.result for x, y in zip(reqs, fifo_reqs) if x.status == y.status == "done")
         rows.append({"rate_per_s": rate, "rate_x_service": mult, "continuous": a, "fifo": b,
                      "results_identical": same})
+        progress(f"serve: rate {rate:.1f}/s continuous p50 {a['p50_s']} p99 {a['p99_s']} | "
+                 f"fifo p50 {b['p50_s']} p99 {b['p99_s']}")
     return {"workload": "Poisson stream, 70% amplitudes / 30% marginals P(q=v) by doubled diagram, pool of "
                         "64 circuits (U{20..50} qubits, U{20..80} T, U{200..1000} Clifford gates)",
             "requests_per_rate": n_requests, "p_cap": p_cap, "service_rate_per_s": mu, "rates": rows}

@@ -216,6 +216,10 @@ SIM_API int sim_eval_ranges(const sim_program *const *progs, const uint64_t *fir
                     const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
                     sim_zomega *raw);
 
+/* sim_finalize for n programs in one launch: out[i] = finalised raws[i] of progs[i]. */
+SIM_API int sim_finalize_batch(const sim_program *const *progs, const sim_zomega *raws, size_t n,
+                               void *stream, sim_zomega *out);
+
 /* Adds two raw partials of the same program exactly (host, int128 with overflow check). */
 SIM_API int sim_raw_add(const sim_zomega *a, const sim_zomega *b, sim_zomega *out);
 

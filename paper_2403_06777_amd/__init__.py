@@ -22,6 +22,7 @@ from .binding import (  # noqa: F401
     sim_eval_timed,
     sim_eval_ranges,
     sim_finalize,
+    sim_finalize_batch,
     sim_init,
     sim_ir_info,
     sim_last_error,

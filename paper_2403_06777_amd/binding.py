@@ -115,6 +115,8 @@ SIGNATURES = [
     ("sim_eval_ranges", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                        ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_finalize_batch", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(sim_zomega), ctypes.c_size_t, _P,
+                                          ctypes.POINTER(sim_zomega)]),
     ("sim_raw_add", ctypes.c_int, [ctypes.POINTER(sim_zomega), ctypes.POINTER(sim_zomega),
                                    ctypes.POINTER(sim_zomega)]),
     ("sim_program_free", None, [_P]),
@@ -300,6 +302,14 @@ def sim_finalize(prog: int, raw_coeffs, stream=None):
     out = sim_zomega()
     _check(lib().sim_finalize(prog, ctypes.byref(raw), _stream(stream), ctypes.byref(out)))
     return _scalar(out)
+
+
+def sim_finalize_batch(progs: Sequence[int], raws, stream=None):
+    n = len(progs)
+    zs = (sim_zomega * max(1, n))(*[_raw(r) for r in raws])
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_finalize_batch(_prog_array(progs), zs, n, _stream(stream), outs))
+    return [_scalar(outs[i]) for i in range(n)]
 
 
 def sim_raw_add(a, b):

@@ -54,9 +54,11 @@ struct DeviceState {
     bool ready = false;
     int cus = 0;
     std::mutex mu;
-    DevBuf partials, result, items, hdrs, imgs, firsts, counts, args, queue;
+    DevBuf partials, result, queue, stage;
     void *host_result = nullptr;  // pinned
     size_t host_cap = 0;
+    void *host_stage = nullptr;   // pinned staging of batch layouts
+    size_t host_stage_cap = 0;
 };
 
 constexpr int kMaxDevices = 64;
@@ -472,9 +474,10 @@ struct BatchLayout {
     std::vector<uint32_t> live;  // indices of programs that need the GPU
 };
 
+constexpr uint64_t kMaxItemsPerProgram = 4096;
+
 int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_slice, const uint64_t *n_slices,
                  bool raw, const sim_tuning *t, BatchLayout *L) {
-    const uint32_t chunk_log2 = t && t->chunk_log2 ? t->chunk_log2 : 22u;
     L->hdrs.resize(n);
     L->imgs.resize(n);
     L->firsts.assign(n, 0);
@@ -510,11 +513,14 @@ int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_s
         g.table_bytes = std::max<uint32_t>(g.table_bytes, H.table_n * 32);
         uint64_t s0 = first_slice ? first_slice[i] : 0;
         uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;
-        // slices per item: 2^chunk_log2 terms, at least 1 slice
-        int terms_per_slice_log2 = (int)H.g;
-        uint64_t per = chunk_log2 > (uint32_t)terms_per_slice_log2
-                           ? ((uint64_t)1 << std::min<uint32_t>(62, chunk_log2 - terms_per_slice_log2))
-                           : 1;
+        // slices per item: with an explicit chunk, 2^chunk_log2 terms; by default about one
+        // slice per thread of a workgroup, and at most kMaxItemsPerProgram items per program
+        uint64_t per;
+        if (t && t->chunk_log2) {
+            per = t->chunk_log2 > H.g ? ((uint64_t)1 << std::min<uint32_t>(62, t->chunk_log2 - H.g)) : 1;
+        } else {
+            per = std::max<uint64_t>(256, (cnt + kMaxItemsPerProgram - 1) / kMaxItemsPerProgram);
+        }
         L->firsts[i] = (uint32_t)L->items.size();
         for (uint64_t s = 0; s < cnt; s += per) {
             WorkItem wi;
@@ -551,28 +557,57 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
     return SIM_OK;
 }
 
-int upload_layout(DeviceState &D, const BatchLayout &L, size_t n, hipStream_t st) {
+// device addresses of the pieces of a batch layout inside one staging buffer
+struct LayoutPtrs {
+    const ImgHeader *hdrs;
+    const uint64_t *imgs;
+    const WorkItem *items;
+    const uint32_t *firsts, *counts;
+    const FinalArgs *args;
+};
+
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// packs the layout into pinned host memory and uploads it with one copy
+int upload_layout(DeviceState &D, const BatchLayout &L, size_t n, hipStream_t st, LayoutPtrs *P) {
+    const size_t o_hdrs = 0;
+    const size_t o_imgs = align16(o_hdrs + n * sizeof(ImgHeader));
+    const size_t o_firsts = align16(o_imgs + n * 8);
+    const size_t o_counts = align16(o_firsts + n * 4);
+    const size_t o_args = align16(o_counts + n * 4);
+    const size_t o_items = align16(o_args + n * sizeof(FinalArgs));
+    const size_t total = align16(o_items + L.items.size() * sizeof(WorkItem)) + 16;
     int rc;
-    if ((rc = ensure(D.hdrs, std::max<size_t>(1, n) * sizeof(ImgHeader)))) return rc;
-    if ((rc = ensure(D.imgs, std::max<size_t>(1, n) * 8))) return rc;
-    if ((rc = ensure(D.items, std::max<size_t>(1, L.items.size()) * sizeof(WorkItem)))) return rc;
+    if ((rc = ensure(D.stage, total))) return rc;
+    if (D.host_stage_cap < total) {
+        if (D.host_stage) (void)hipHostFree(D.host_stage);
+        D.host_stage = nullptr;
+        D.host_stage_cap = 0;
+        hipError_t e = hipHostMalloc(&D.host_stage, std::max<size_t>(total, 1 << 16), hipHostMallocDefault);
+        if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+        D.host_stage_cap = std::max<size_t>(total, 1 << 16);
+    }
+    char *h = (char *)D.host_stage;
+    if (n) {
+        memcpy(h + o_hdrs, L.hdrs.data(), n * sizeof(ImgHeader));
+        memcpy(h + o_imgs, L.imgs.data(), n * 8);
+        memcpy(h + o_firsts, L.firsts.data(), n * 4);
+        memcpy(h + o_counts, L.counts.data(), n * 4);
+        memcpy(h + o_args, L.args.data(), n * sizeof(FinalArgs));
+    }
+    if (!L.items.empty()) memcpy(h + o_items, L.items.data(), L.items.size() * sizeof(WorkItem));
     if ((rc = ensure(D.partials, std::max<size_t>(1, L.items.size()) * sizeof(Partial)))) return rc;
-    if ((rc = ensure(D.firsts, std::max<size_t>(1, n) * 4))) return rc;
-    if ((rc = ensure(D.counts, std::max<size_t>(1, n) * 4))) return rc;
-    if ((rc = ensure(D.args, std::max<size_t>(1, n) * sizeof(FinalArgs)))) return rc;
     if ((rc = ensure(D.result, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
     if ((rc = ensure(D.queue, std::max<size_t>(1, L.groups.size()) * 4))) return rc;
     if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
-    if (n) {
-        HIP_TRY(hipMemcpyAsync(D.hdrs.ptr, L.hdrs.data(), n * sizeof(ImgHeader), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(D.imgs.ptr, L.imgs.data(), n * 8, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(D.firsts.ptr, L.firsts.data(), n * 4, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(D.counts.ptr, L.counts.data(), n * 4, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(D.args.ptr, L.args.data(), n * sizeof(FinalArgs), hipMemcpyHostToDevice, st));
-    }
-    if (!L.items.empty())
-        HIP_TRY(hipMemcpyAsync(D.items.ptr, L.items.data(), L.items.size() * sizeof(WorkItem),
-                               hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(D.stage.ptr, h, total, hipMemcpyHostToDevice, st));
+    char *d = (char *)D.stage.ptr;
+    P->hdrs = (const ImgHeader *)(d + o_hdrs);
+    P->imgs = (const uint64_t *)(d + o_imgs);
+    P->firsts = (const uint32_t *)(d + o_firsts);
+    P->counts = (const uint32_t *)(d + o_counts);
+    P->args = (const FinalArgs *)(d + o_args);
+    P->items = (const WorkItem *)(d + o_items);
     return SIM_OK;
 }
 
@@ -604,12 +639,12 @@ int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, con
     BatchLayout L;
     if ((rc = build_layout(ps, n, first, count, raw, t, &L))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = upload_layout(D, L, n, st))) return rc;
+    LayoutPtrs LP;
+    if ((rc = upload_layout(D, L, n, st, &LP))) return rc;
     if (!L.live.empty()) {
-        if ((rc = enqueue_batch(D, L, n, t, st, (const ImgHeader *)D.hdrs.ptr, (const uint64_t *)D.imgs.ptr,
-                                (const WorkItem *)D.items.ptr, (uint32_t *)D.queue.ptr, (Partial *)D.partials.ptr,
-                                (const uint32_t *)D.firsts.ptr, (const uint32_t *)D.counts.ptr,
-                                (const FinalArgs *)D.args.ptr, (DevResult *)D.result.ptr)))
+        if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items, (uint32_t *)D.queue.ptr,
+                                (Partial *)D.partials.ptr, LP.firsts, LP.counts, LP.args,
+                                (DevResult *)D.result.ptr)))
             return rc;
         HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
     }
@@ -656,6 +691,52 @@ int sim_eval_ranges(const sim_program *const *ps, const uint64_t *first_slice, c
                     void *stream, const sim_tuning *t, sim_zomega *raw) {
     if (n && (!raw || !first_slice || !n_slices)) return fail(SIM_EINVAL, "null argument");
     return run_batch(ps, n, first_slice, n_slices, true, stream, t, raw);
+}
+
+int sim_finalize_batch(const sim_program *const *ps, const sim_zomega *raws, size_t n, void *stream,
+                       sim_zomega *out) {
+    if (n && (!raws || !out)) return fail(SIM_EINVAL, "null argument");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    if (!n) return SIM_OK;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    hipStream_t st = (hipStream_t)stream;
+    // one "item" per program whose partial is the raw sum given by the caller
+    BatchLayout L;
+    L.hdrs.resize(n);
+    L.imgs.assign(n, 0);
+    L.args.resize(n);
+    L.firsts.resize(n);
+    L.counts.assign(n, 1);
+    for (size_t i = 0; i < n; ++i) {
+        L.hdrs[i] = ps[i]->pk.hdr;
+        L.args[i] = final_args(ps[i]->pk, false);
+        L.firsts[i] = (uint32_t)i;
+    }
+    L.items.resize(n);
+    LayoutPtrs LP;
+    if ((rc = upload_layout(D, L, n, st, &LP))) return rc;
+    std::vector<Partial> parts(n);
+    for (size_t i = 0; i < n; ++i)
+        for (int k = 0; k < 4; ++k) {
+            parts[i].w[2 * k] = raws[i].c[k].lo;
+            parts[i].w[2 * k + 1] = (uint64_t)raws[i].c[k].hi;
+        }
+    HIP_TRY(hipMemcpyAsync(D.partials.ptr, parts.data(), n * sizeof(Partial), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_finalize_batch((Partial *)D.partials.ptr, LP.firsts, LP.counts, LP.args, (uint32_t)n,
+                                  (DevResult *)D.result.ptr, st));
+    HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<sim_zomega> res(n);
+    for (size_t i = 0; i < n; ++i) {
+        DevResult r;
+        memcpy(&r, (const char *)D.host_result + i * sizeof(DevResult), sizeof r);
+        if ((rc = to_zomega(r, &res[i]))) return rc;
+    }
+    for (size_t i = 0; i < n; ++i) out[i] = res[i];
+    return SIM_OK;
 }
 
 void sim_batch_plan_free(sim_batch_plan *plan) {

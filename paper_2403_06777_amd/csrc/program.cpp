@@ -372,8 +372,12 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     std::vector<int> inc(p, 0);  // monomial incidences per original parameter
     for (const auto &m : w.mono)
         for (int v : m.first) inc[v - q]++;
-    int g_orig = std::max(0, std::min(max_walk_bits, p - 20));
-    if (p <= 20) g_orig = std::min(p, std::max(0, std::min(max_walk_bits, p / 2)));
+    // Walk length: a slice costs a set-up (its high parameters into L, and with variable
+    // monomials a full evaluation of phi) that the 2^g walk steps amortise.  Without variable
+    // monomials the set-up is a few XORs per high parameter, so short walks (fine slices,
+    // more lanes for the same work) cost nothing; with monomials a longer walk pays off.
+    const int want = w.mono.empty() ? 6 : 12;
+    int g_orig = std::min(p, std::min(max_walk_bits, want));
     if (p - g_orig > 62) g_orig = p - 62;
     // walked parameters: fewest monomials first (they flip most often); high: index order
     std::vector<int> order(p);

@@ -95,12 +95,30 @@ ZW_HD inline bool zw_add_checked(const Zw &a, const Zw &b, Zw *out) {
 
 // Canonical form of z * sqrt2^e: zero has e = 0; otherwise divide out sqrt2 while the
 // quotient stays integral.
+// Dividing by 2 = sqrt2^2 removes the common trailing zero bits of the four coefficients;
+// after that at most one more sqrt2 divides z (two would mean z is even again).
+ZW_HD inline int zw_ctz128(i128 v) {
+    const uint64_t lo = (uint64_t)v, hi = (uint64_t)((unsigned __int128)v >> 64);
+    if (lo) return __builtin_ctzll(lo);
+    if (hi) return 64 + __builtin_ctzll(hi);
+    return 128;
+}
+
 ZW_HD inline void zw_canonicalise(Zw *z, int32_t *e) {
     if (zw_is_zero(*z)) {
         *e = 0;
         return;
     }
-    while (zw_div_sqrt2_ok(*z)) {
+    int k = 128;
+    for (int i = 0; i < 4; ++i) {
+        int t = zw_ctz128(z->c[i]);
+        k = t < k ? t : k;
+    }
+    if (k) {
+        for (int i = 0; i < 4; ++i) z->c[i] >>= k;
+        *e += 2 * k;
+    }
+    if (zw_div_sqrt2_ok(*z)) {
         *z = zw_div_sqrt2(*z);
         *e += 1;
     }

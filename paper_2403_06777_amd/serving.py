@@ -80,6 +80,9 @@ class ZxBackend:
     def finalize(self, handle, raw):
         return B.sim_finalize(handle, raw, self.stream)
 
+    def finalize_many(self, handles, raws):
+        return B.sim_finalize_batch(handles, raws, self.stream)
+
     def evaluate(self, handle):
         return B.sim_eval_amplitude(handle, self.stream)
 
@@ -291,15 +294,23 @@ class Server:
                 counts.append(cnt)
             raws = self.backend.eval_ranges(handles, firsts, counts)
             stats.ticks += 1
-            still = []
+            still, finished = [], []
             for a, cnt, raw in zip(active, counts, raws):
                 a.raw = self.backend.raw_add(a.raw, raw)
                 a.next_slice += cnt
                 if a.next_slice >= a.entry.info["n_slices"]:
-                    a.req.result = self.backend.finalize(a.entry.handle, a.raw)
-                    self._finish(a.req, a.entry, stats, now())
+                    finished.append(a)
                 else:
                     still.append(a)
+            if finished:
+                if hasattr(self.backend, "finalize_many"):
+                    vals = self.backend.finalize_many([a.entry.handle for a in finished], [a.raw for a in finished])
+                else:
+                    vals = [self.backend.finalize(a.entry.handle, a.raw) for a in finished]
+                t_done = now()
+                for a, v in zip(finished, vals):
+                    a.req.result = v
+                    self._finish(a.req, a.entry, stats, t_done)
             active = still
         stats.wall = now()
         return stats

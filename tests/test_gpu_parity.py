@@ -216,3 +216,15 @@ def test_torch_stream_is_accepted():
         assert val == zx.sim_eval_amplitude(h) and ms > 0
     finally:
         zx.sim_program_free(h)
+
+
+def test_finalize_batch_matches_single_finalize():
+    texts = _batch_programs()
+    hs = [zx.sim_program_from_ir(t) for t in texts]
+    try:
+        raws = [zx.sim_eval_range(h, 0, zx.sim_program_info(h)["n_slices"]) for h in hs]
+        assert zx.sim_finalize_batch(hs, raws) == [zx.sim_finalize(h, r) for h, r in zip(hs, raws)]
+        assert zx.sim_finalize_batch(hs, raws) == [zx.sim_eval_amplitude(h) for h in hs]
+    finally:
+        for h in hs:
+            zx.sim_program_free(h)
