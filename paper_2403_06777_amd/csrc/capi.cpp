@@ -59,7 +59,12 @@ struct DeviceState {
     size_t host_cap = 0;
     void *host_stage = nullptr;   // pinned staging of batch layouts
     size_t host_stage_cap = 0;
+    bool aux_ready = false;       // auxiliary streams (default priority) for concurrent batch groups
+    hipStream_t aux[4];
+    hipEvent_t ev_fork, ev_join[4];
 };
+
+constexpr int kAux = 4;
 
 constexpr int kMaxDevices = 64;
 DeviceState g_dev[kMaxDevices];
@@ -86,6 +91,17 @@ int ensure_host(DeviceState &D, size_t need) {
     hipError_t e = hipHostMalloc(&D.host_result, cap, hipHostMallocDefault);
     if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
     D.host_cap = cap;
+    return SIM_OK;
+}
+
+int ensure_aux(DeviceState &D) {
+    if (D.aux_ready) return SIM_OK;
+    for (int a = 0; a < kAux; ++a) {
+        HIP_TRY(hipStreamCreateWithFlags(&D.aux[a], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&D.ev_join[a], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&D.ev_fork, hipEventDisableTiming));
+    D.aux_ready = true;
     return SIM_OK;
 }
 
@@ -460,9 +476,9 @@ namespace {
 // slices cut into items of about 2^chunk_log2 terms
 struct BatchLayout {
     struct Group {
-        uint32_t W = 1, mono = 0;
+        uint32_t W = 1, mono = 0, acc = 0;
         uint32_t item_first = 0, n_items = 0;
-        uint32_t table_bytes = 0;
+        uint32_t lds_bytes = 0;
         ImgHeader h0;
     };
     std::vector<Group> groups;
@@ -493,24 +509,27 @@ int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_s
         if (!P->pk.zero && cnt) order.push_back((uint32_t)i);
     }
     // group by kernel variant, keep program order inside a group
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        uint32_t ka = ps[a]->pk.hdr.W * 2 + ps[a]->pk.hdr.has_mono;
-        uint32_t kb = ps[b]->pk.hdr.W * 2 + ps[b]->pk.hdr.has_mono;
-        return ka < kb;
-    });
+    auto variant = [&](uint32_t i) {
+        const ImgHeader &H = ps[i]->pk.hdr;
+        return (H.W * 2 + H.has_mono) * 4 + H.acc;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return variant(a) < variant(b); });
     for (uint32_t i : order) {
         const sim_program *P = ps[i];
         const ImgHeader &H = P->pk.hdr;
-        if (L->groups.empty() || L->groups.back().W != H.W || L->groups.back().mono != H.has_mono) {
+        if (L->groups.empty() || L->groups.back().W != H.W || L->groups.back().mono != H.has_mono ||
+            L->groups.back().acc != H.acc) {
             BatchLayout::Group g;
             g.W = H.W;
             g.mono = H.has_mono;
+            g.acc = H.acc;
             g.item_first = (uint32_t)L->items.size();
             g.h0 = H;
             L->groups.push_back(g);
         }
         BatchLayout::Group &g = L->groups.back();
-        g.table_bytes = std::max<uint32_t>(g.table_bytes, H.table_n * 32);
+        g.lds_bytes = std::max<uint32_t>(g.lds_bytes, (uint32_t)dyn_lds_bytes(H));
+        if (H.g > g.h0.g) g.h0.g = H.g;  // flush interval follows the longest walk of the group
         uint64_t s0 = first_slice ? first_slice[i] : 0;
         uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;
         // slices per item: with an explicit chunk, 2^chunk_log2 terms; by default about one
@@ -545,13 +564,32 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
                   DevResult *d_out) {
     const uint32_t threads = pick_threads(t);
     const uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 8u;
+    const size_t ng = L.groups.size();
+    // kernel variants run concurrently: group k on auxiliary stream k % kAux, forked from and
+    // joined back into `stream` with events (also valid under stream capture)
+    const bool fork = ng > 1;
+    if (fork) {
+        int rc = ensure_aux(D);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(D.ev_fork, stream));
+        for (int a = 0; a < kAux; ++a) HIP_TRY(hipStreamWaitEvent(D.aux[a], D.ev_fork, 0));
+    }
     uint32_t gi = 0;
     for (const auto &g : L.groups) {
-        uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g.n_items, (uint64_t)std::max(1, D.cus) * bpc));
-        HIP_TRY(launch_reset_queue(d_queue + gi, stream));
+        hipStream_t s = fork ? D.aux[gi % kAux] : stream;
+        uint32_t share = fork ? std::max<uint32_t>(1, (uint32_t)((uint64_t)std::max(1, D.cus) * bpc)) : 0;
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(g.n_items, share ? share : (uint64_t)std::max(1, D.cus) * bpc));
+        HIP_TRY(launch_reset_queue(d_queue + gi, s));
         HIP_TRY(launch_eval_batch(g.h0, d_hdrs, d_imgs, d_items + g.item_first, g.n_items, d_queue + gi, d_parts,
-                                  blocks, threads, g.table_bytes, stream));
+                                  blocks, threads, g.lds_bytes, s));
         ++gi;
+    }
+    if (fork) {
+        for (int a = 0; a < kAux && a < (int)ng; ++a) {
+            HIP_TRY(hipEventRecord(D.ev_join[a], D.aux[a]));
+            HIP_TRY(hipStreamWaitEvent(stream, D.ev_join[a], 0));
+        }
     }
     HIP_TRY(launch_finalize_batch(d_parts, d_firsts, d_counts, d_args, (uint32_t)n, d_out, stream));
     return SIM_OK;

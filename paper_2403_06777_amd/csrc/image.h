@@ -2,12 +2,12 @@
 //
 // The paper stores each subterm as a row (dummy flag, 4 alpha/pi, P^psi bits, 4 beta/pi,
 // P^phi bits) and lays the table out column-major for coalescing (Section 3.3, Appendix D).
-// Here the same information is re-laid for one lane per assignment: the affine forms of all
-// factors become a bit-vector L(x) of F bits (W 32-bit words), one column per parameter
-// holds the forms that contain it (so a Gray-code step updates L with W XORs), and the
-// factors are summarised by a few weighted popcount masks over L (value classes).  Every
-// offset below counts 32-bit words from the start of the image; the int64 value table sits
-// at a byte offset aligned to 8.
+// Here the same information is re-laid for one lane per slice of assignments: the affine
+// forms of all factors become a bit-vector L(x) of F bits (W 32-bit words), one column per
+// parameter holds the forms that contain it (so a Gray-code step updates L with W XORs), and
+// the factors are summarised by weighted popcount masks over L (value classes).  Every offset
+// below counts 32-bit words from the start of the image; the int64 value table sits at a
+// byte offset aligned to 8.
 #pragma once
 
 #include <stdint.h>
@@ -15,28 +15,50 @@
 // statistics computed per term from popcounts of L (see the packer for their meaning)
 enum { STAT_A = 0, STAT_B = 1, STAT_E = 2, STAT_R = 3, N_STATS = 4 };
 
+#ifdef __HIPCC__
+#define IMG_HD __host__ __device__
+#else
+#define IMG_HD
+#endif
+
+// fixed statistic slots: A+1, A-1, B+1, B-1, E+1, E+2, E-1, E-2, R*1, R*2, R*4
+constexpr int kSlots = 11;
+IMG_HD constexpr int slot_stat(int i) { return i < 2 ? STAT_A : i < 4 ? STAT_B : i < 8 ? STAT_E : STAT_R; }
+IMG_HD constexpr int slot_weight(int i) {
+    return i == 0 ? 1 : i == 1 ? -1 : i == 2 ? 1 : i == 3 ? -1 : i == 4 ? 1 : i == 5 ? 2 : i == 6 ? -1
+         : i == 7 ? -2 : i == 8 ? 1 : i == 9 ? 2 : 4;
+}
+
+// how the terms of a lane are summed
+enum {
+    ACC_I64 = 0,   // every partial sum fits int64 (static bound): four int64 registers
+    ACC_I128 = 1,  // four int128 registers, term shifted into them
+    ACC_CLASS = 2  // per-block LDS counters of sum 2^h per value class, times the table at flush
+};
+
 struct ImgHeader {
     uint32_t pe;        // parameters enumerated by the kernel (p plus one per pair factor)
     uint32_t g;         // Gray-walk bits: packed positions 0 .. g-1
     uint32_t W;         // 32-bit words per form vector
     uint32_t has_zero;  // some factor can vanish: test the zero masks
     uint32_t has_mono;  // variable monomials present
+    uint32_t acc;       // ACC_* mode
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j
     uint32_t off_cvec;  // W words: constant bits of the forms
     uint32_t off_z0;    // W words: forms whose factor vanishes when the form is 0
     uint32_t off_z1;    // W words: ... when the form is 1
-    uint32_t stat_off[N_STATS];  // entries of (W + 1) words: weight, mask[W]
-    uint32_t stat_n[N_STATS];
+    uint32_t off_slots; // kSlots entries of (W + 1) words: weight (0 = unused), mask[W]
     int32_t stat_base[N_STATS];
     uint32_t off_monohi;  // monomials over high positions only: c, mask_lo, mask_hi (slice bits)
     uint32_t n_monohi;
     uint32_t off_didx;    // g + 1 words: delta entries for walk position i are [didx[i], didx[i+1])
     uint32_t off_delta;   // entries of 4 words: c, walk mask, slice mask lo, slice mask hi
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
-    uint32_t table_n;         // entries
-    int32_t d_off;            // table index of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e
-    uint32_t zero_entry;      // index of the all-zero entry
+    uint32_t table_n;         // entries (value classes + one zero entry)
+    int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e
+    uint32_t zero_entry;      // index of the all-zero entry (= number of classes)
+    uint32_t q_limbs;         // ACC_CLASS: counters per class (2^h split as 2^(32 q) * 2^(h mod 32))
     uint32_t image_bytes;     // total bytes of the image
 };
 

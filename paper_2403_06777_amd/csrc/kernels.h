@@ -28,16 +28,22 @@ struct DevResult {
 // largest dynamic LDS a value table may take
 #define MAX_TABLE_BYTES (64 * 1024)
 
+// dynamic LDS of a program: value table (register modes) or class counters
+size_t dyn_lds_bytes(const ImgHeader &H);
+// rounds of `threads` slices between flushes of the class counters
+uint32_t flush_rounds_for(const ImgHeader &H, uint32_t threads);
+
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                        Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
 
 hipError_t launch_finalize(const Partial *partials, uint32_t n, const FinalArgs &args, DevResult *out,
                            hipStream_t stream);
 
-// persistent multi-program launch; all programs share W and the monomial flag of `H0`
+// persistent multi-program launch; all programs share W, the monomial flag and the
+// accumulation mode of `H0`; lds_bytes is the largest dyn_lds_bytes of the programs
 hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
                              const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue,
-                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t table_bytes,
+                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t lds_bytes,
                              hipStream_t stream);
 
 hipError_t launch_reset_queue(uint32_t *d_queue, hipStream_t stream);

@@ -2,15 +2,21 @@
 // terms exactly.
 //
 // Work decomposition.  The paper gives one GPU thread to each subterm row of one bitstring
-// and multiplies/sums with repeated pairwise launches (Section 3.3, Appendix E).  Here a
-// lane owns a whole slice of 2^g assignments instead: the high parameters are fixed by the
-// slice index, the low g parameters are enumerated in Gray-code order so that one step
-// flips one parameter, which XORs one wave-uniform column into the lane's form vector L.
-// The product of all factors of a term is read off popcounts of L (value classes, see the
-// packer) and one exact table entry w^r sqrt2^e Q(d) from LDS, shifted by sqrt2^(2h) = 2^h
-// and added to four int128 accumulators.  Partial sums go wave -> block through shuffles and
-// LDS, then a finaliser adds the per-block partials, applies the constant and reduces to
-// canonical form.  No floating point is used anywhere.
+// and multiplies/sums with repeated pairwise launches (Section 3.3, Appendix E).  Here a lane
+// owns a whole slice of 2^g assignments instead: the high parameters are fixed by the slice
+// index, the low g parameters are enumerated in Gray-code order so that one step flips one
+// parameter, which XORs one wave-uniform column into the lane's form vector L.  The product
+// of all factors of a term is read off popcounts of L (value classes, see the packer): a
+// value class (d, r, e) and a power 2^h such that the term is 2^h * w^r sqrt2^e Q(d), with
+// the exact Z[w] value of each class in a small int64 table.  Terms are summed per lane in
+// int64 or int128 registers (term = table entry shifted by h), or, when that would need the
+// wide int128 shift on every term, counted per class in LDS as sums of powers of two and
+// multiplied by the table only when the counters are flushed.  Partial sums go lane -> wave
+// -> block through shuffles and LDS; a finaliser adds the per-block partials, applies the
+// constant and reduces to canonical form.  No floating point is used anywhere.
+//
+// Image words are read through the constant address space so that every wave-uniform read
+// is a scalar load.
 
 #include <hip/hip_runtime.h>
 
@@ -21,56 +27,117 @@
 namespace {
 
 constexpr int kMaxThreads = 256;
+typedef const __attribute__((address_space(4))) uint32_t CU32;
 
 __device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__builtin_popcount(x); }
 
-// one term: value classes -> table entry -> accumulate
+__device__ __forceinline__ CU32 *const_words(const uint8_t *img) {
+    return (CU32 *)(uintptr_t)img;
+}
+
+// the per-program statistic masks, read once and kept in scalar registers
 template <int W>
-__device__ __forceinline__ void eval_term(const ImgHeader &H, const uint32_t *__restrict__ wd,
-                                          const int64_t *tab, const uint32_t (&L)[W], int phi,
-                                          i128 (&acc)[4]) {
+struct Slots {
+    int wgt[kSlots];
+    uint32_t m[kSlots][W];
+};
+
+template <int W>
+__device__ __forceinline__ void load_slots(const ImgHeader &H, CU32 *wd, Slots<W> &S) {
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+        CU32 *e = wd + H.off_slots + i * (W + 1);
+        S.wgt[i] = (int)e[0];
+#pragma unroll
+        for (int w = 0; w < W; ++w) S.m[i][w] = e[1 + w];
+    }
+}
+
+struct TermClass {
+    uint32_t cls;  // value class (d, r, e) or the zero entry
+    int h;         // the term is 2^h times the class value
+    bool zero;
+};
+
+template <int W>
+__device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W> &S, CU32 *wd,
+                                              const uint32_t (&L)[W], int phi) {
     int st[N_STATS];
 #pragma unroll
-    for (int s = 0; s < N_STATS; ++s) {
-        int v = H.stat_base[s];
-        const uint32_t *ent = wd + H.stat_off[s];
-        const uint32_t n = H.stat_n[s];
-        for (uint32_t e = 0; e < n; ++e, ent += W + 1) {
+    for (int s = 0; s < N_STATS; ++s) st[s] = H.stat_base[s];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+        if (S.wgt[i] != 0) {
             uint32_t c = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) c += popc(L[w] & ent[1 + w]);
-            v += (int)ent[0] * (int)c;
+            for (int w = 0; w < W; ++w) c += popc(L[w] & S.m[i][w]);
+            st[slot_stat(i)] += __mul24((int)c, S.wgt[i]);
         }
-        st[s] = v;
     }
-    bool zero = false;
+    TermClass t;
+    t.zero = false;
     if (H.has_zero) {
         uint32_t z = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) z |= (~L[w] & wd[H.off_z0 + w]) | (L[w] & wd[H.off_z1 + w]);
-        zero = z != 0u;
+        t.zero = z != 0u;
     }
     const int A = st[STAT_A], B = st[STAT_B];
     const int m = A < B ? A : B;
     const int E = st[STAT_E] + m;
     const int R = st[STAT_R] + 2 * m + phi;
-    uint32_t idx = ((uint32_t)(A - B + H.d_off) * 8u + (uint32_t)(R & 7)) * 2u + (uint32_t)(E & 1);
-    idx = zero ? H.zero_entry : idx;
-    const int h = E >> 1;
-    const longlong2 *t = reinterpret_cast<const longlong2 *>(tab + (size_t)idx * 4);
-    const longlong2 v01 = t[0];
-    const longlong2 v23 = t[1];
-    acc[0] += (i128)v01.x << h;
-    acc[1] += (i128)v01.y << h;
-    acc[2] += (i128)v23.x << h;
-    acc[3] += (i128)v23.y << h;
+    t.cls = (((uint32_t)(A - B + H.d_off) << 4) | ((uint32_t)(R & 7) << 1)) | (uint32_t)(E & 1);
+    t.h = E >> 1;
+    return t;
+}
+
+// per-lane accumulation state for the three modes
+template <int ACC>
+struct Acc {
+    int64_t a64[4];
+    i128 a128[4];
+    __device__ void clear() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a64[k] = 0;
+            a128[k] = 0;
+        }
+    }
+};
+
+template <int W, int ACC>
+__device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
+                                         unsigned long long *cnt, const uint32_t (&L)[W], int phi, Acc<ACC> &acc) {
+    const TermClass t = classify<W>(H, S, wd, L, phi);
+    if (ACC == ACC_CLASS) {
+        if (!t.zero) {
+            // counters are laid out [q][class]: 24-bit multiply-add (full rate)
+            const uint32_t slot = __umul24((uint32_t)(t.h >> 5), H.zero_entry) + t.cls;
+            atomicAdd(cnt + slot, (unsigned long long)(1u << (t.h & 31)));
+        }
+    } else {
+        const uint32_t idx = t.zero ? H.zero_entry : t.cls;
+        const longlong2 *p = reinterpret_cast<const longlong2 *>(tab + (size_t)idx * 4);
+        const longlong2 v01 = p[0], v23 = p[1];
+        if (ACC == ACC_I64) {
+            acc.a64[0] += (int64_t)((uint64_t)v01.x << t.h);
+            acc.a64[1] += (int64_t)((uint64_t)v01.y << t.h);
+            acc.a64[2] += (int64_t)((uint64_t)v23.x << t.h);
+            acc.a64[3] += (int64_t)((uint64_t)v23.y << t.h);
+        } else {
+            acc.a128[0] += (i128)v01.x << t.h;
+            acc.a128[1] += (i128)v01.y << t.h;
+            acc.a128[2] += (i128)v23.x << t.h;
+            acc.a128[3] += (i128)v23.y << t.h;
+        }
+    }
 }
 
 // all 2^g assignments of slice s (high parameters = bits of s)
-template <int W, bool MONO>
-__device__ __forceinline__ void run_slice(const ImgHeader &H, const uint32_t *__restrict__ wd,
-                                          const int64_t *tab, uint64_t s, i128 (&acc)[4]) {
-    const uint32_t *col = wd + H.off_col;
+template <int W, bool MONO, int ACC>
+__device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
+                                          unsigned long long *cnt, uint64_t s, Acc<ACC> &acc) {
+    CU32 *col = wd + H.off_col;
     uint32_t L[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) L[w] = wd[H.off_cvec + w];
@@ -81,13 +148,13 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const uint32_t *__
     }
     int phi = 0;
     if (MONO) {
-        const uint32_t *mh = wd + H.off_monohi;
+        CU32 *mh = wd + H.off_monohi;
         for (uint32_t e = 0; e < H.n_monohi; ++e, mh += 3) {
             const uint64_t hm = (uint64_t)mh[1] | ((uint64_t)mh[2] << 32);
             phi += ((s & hm) == hm) ? (int)mh[0] : 0;
         }
     }
-    eval_term<W>(H, wd, tab, L, phi, acc);
+    add_term<W, ACC>(H, S, wd, tab, cnt, L, phi, acc);
     const uint32_t n = 1u << H.g;
     uint32_t gray = 0;
     for (uint32_t t = 1; t < n; ++t) {
@@ -96,9 +163,9 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const uint32_t *__
 #pragma unroll
         for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
         if (MONO) {
-            const uint32_t *didx = wd + H.off_didx;
+            CU32 *didx = wd + H.off_didx;
             const uint32_t e0 = didx[i], e1 = didx[i + 1];
-            const uint32_t *de = wd + H.off_delta + 4 * e0;
+            CU32 *de = wd + H.off_delta + 4 * e0;
             int du = 0, dv = 0;
             for (uint32_t e = e0; e < e1; ++e, de += 4) {
                 const uint32_t wm = de[1];
@@ -111,7 +178,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const uint32_t *__
             const int dd = du + dv;
             phi += ((gray >> i) & 1u) ? dd : -dd;
         }
-        eval_term<W>(H, wd, tab, L, phi, acc);
+        add_term<W, ACC>(H, S, wd, tab, cnt, L, phi, acc);
     }
 }
 
@@ -157,29 +224,95 @@ __device__ __forceinline__ i128 load_i128(const uint64_t *w) {
     return (i128)((unsigned __int128)w[0] | ((unsigned __int128)w[1] << 64));
 }
 
-template <int W, bool MONO>
-__global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t *__restrict__ img,
-                                                      uint64_t s_begin, uint64_t s_count,
-                                                      Partial *__restrict__ partials) {
-    extern __shared__ int64_t s_tab[];
-    const uint32_t *wd = reinterpret_cast<const uint32_t *>(img);
-    const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
-    for (uint32_t i = threadIdx.x; i < H.table_n * 4; i += blockDim.x) s_tab[i] = gtab[i];
+// class counters -> int128 accumulators: counter (class, q) holds sum of 2^(h - 32q) over the
+// terms of that class with h >> 5 == q; its value is that times 2^(32q) times the class entry
+template <int ACC>
+__device__ __forceinline__ void flush_counters(const ImgHeader &H, const int64_t *__restrict__ gtab,
+                                               unsigned long long *cnt, i128 (&out)[4]) {
+    if (ACC != ACC_CLASS) return;
     __syncthreads();
-    i128 acc[4] = {0, 0, 0, 0};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s_count; s += stride)
-        run_slice<W, MONO>(H, wd, s_tab, s_begin + s, acc);
-    block_reduce_store(acc, partials + blockIdx.x);
+    const uint32_t n = H.zero_entry * H.q_limbs;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long c = cnt[i];
+        if (!c) continue;
+        cnt[i] = 0;
+        const uint32_t q = i / H.zero_entry, cls = i - q * H.zero_entry;
+        const int64_t *v = gtab + (size_t)cls * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k] += ((i128)c * (i128)v[k]) << (32 * q);
+    }
+    __syncthreads();
 }
 
-template <int W, bool MONO>
+template <int ACC>
+__device__ __forceinline__ void acc_to_i128(Acc<ACC> &acc, i128 (&out)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (ACC == ACC_I64) out[k] += (i128)acc.a64[k];
+        if (ACC == ACC_I128) out[k] += acc.a128[k];
+    }
+    acc.clear();
+}
+
+// shared-memory prologue of a program: value table (register modes) or zeroed counters
+template <int ACC>
+__device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *__restrict__ gtab,
+                                            int64_t *s_tab, unsigned long long *s_cnt) {
+    if (ACC == ACC_CLASS) {
+        const uint32_t n = H.zero_entry * H.q_limbs;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_cnt[i] = 0;
+    } else {
+        for (uint32_t i = threadIdx.x; i < H.table_n * 4; i += blockDim.x) s_tab[i] = gtab[i];
+    }
+    __syncthreads();
+}
+
+// Rounds of blockDim slices are uniform across the block, so counters can be flushed
+// between rounds (every flush_rounds rounds keeps each counter below 2^64).
+template <int W, bool MONO, int ACC>
+__device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img, uint64_t s_first, uint64_t s_count,
+                                          uint64_t lane0, uint64_t stride, uint32_t flush_rounds, int64_t *s_tab,
+                                          unsigned long long *s_cnt, i128 (&out)[4]) {
+    CU32 *wd = const_words(img);
+    const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
+    Slots<W> S;
+    load_slots<W>(H, wd, S);
+    Acc<ACC> acc;
+    acc.clear();
+    uint32_t rounds = 0;
+    for (uint64_t base = lane0 - threadIdx.x; base < s_count; base += stride) {
+        const uint64_t s = base + threadIdx.x;
+        if (s < s_count) run_slice<W, MONO, ACC>(H, S, wd, s_tab, s_cnt, s_first + s, acc);
+        if (ACC == ACC_CLASS && ++rounds == flush_rounds) {
+            flush_counters<ACC>(H, gtab, s_cnt, out);
+            rounds = 0;
+        }
+    }
+    if (ACC == ACC_CLASS) flush_counters<ACC>(H, gtab, s_cnt, out);
+    acc_to_i128<ACC>(acc, out);
+}
+
+template <int W, bool MONO, int ACC>
+__global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t *__restrict__ img,
+                                                      uint64_t s_begin, uint64_t s_count, uint32_t flush_rounds,
+                                                      Partial *__restrict__ partials) {
+    extern __shared__ int64_t s_dyn[];
+    const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
+    prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
+    i128 out[4] = {0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    run_range<W, MONO, ACC>(H, img, s_begin, s_count, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride,
+                            flush_rounds, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn), out);
+    block_reduce_store(out, partials + blockIdx.x);
+}
+
+template <int W, bool MONO, int ACC>
 __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__restrict__ hdrs,
                                                             const uint64_t *__restrict__ imgs,
-                                                            const WorkItem *__restrict__ items,
-                                                            uint32_t n_items, uint32_t *__restrict__ queue,
+                                                            const WorkItem *__restrict__ items, uint32_t n_items,
+                                                            uint32_t *__restrict__ queue, uint32_t flush_rounds,
                                                             Partial *__restrict__ partials) {
-    extern __shared__ int64_t s_tab[];
+    extern __shared__ int64_t s_dyn[];
     __shared__ uint32_t s_item;
     uint32_t loaded = 0xffffffffu;
     for (;;) {
@@ -192,17 +325,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__r
         const uint32_t prog = __builtin_amdgcn_readfirstlane(wi.prog);
         const ImgHeader H = hdrs[prog];
         const uint8_t *img = reinterpret_cast<const uint8_t *>(imgs[prog]);
-        const uint32_t *wd = reinterpret_cast<const uint32_t *>(img);
-        if (prog != loaded) {
-            const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
-            for (uint32_t i = threadIdx.x; i < H.table_n * 4; i += blockDim.x) s_tab[i] = gtab[i];
-            __syncthreads();
+        const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
+        if (prog != loaded || ACC == ACC_CLASS) {
+            prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
             loaded = prog;
         }
-        i128 acc[4] = {0, 0, 0, 0};
-        for (uint64_t s = wi.s_begin + threadIdx.x; s < wi.s_end; s += blockDim.x)
-            run_slice<W, MONO>(H, wd, s_tab, s, acc);
-        block_reduce_store(acc, partials + wi.out_slot);
+        i128 out[4] = {0, 0, 0, 0};
+        run_range<W, MONO, ACC>(H, img, wi.s_begin, wi.s_end - wi.s_begin, threadIdx.x, blockDim.x, flush_rounds,
+                                s_dyn, reinterpret_cast<unsigned long long *>(s_dyn), out);
+        block_reduce_store(out, partials + wi.out_slot);
     }
 }
 
@@ -262,68 +393,94 @@ __global__ __launch_bounds__(kMaxThreads) void k_finalize_batch(const Partial *_
     finalize_range(partials, item_first[k], item_count[k], args[k], out + k);
 }
 
-template <int W, bool MONO>
+template <typename K>
+hipError_t set_lds(K kern, size_t lds) {
+    if (lds <= 48 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <int W, bool MONO, int ACC>
 hipError_t launch_eval_t(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
-    const size_t lds = (size_t)H.table_n * 32;
-    auto kern = k_eval<W, MONO>;
-    if (lds > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, H,
-                       reinterpret_cast<const uint8_t *>(dimg), s_begin, s_count, partials);
+    const size_t lds = dyn_lds_bytes(H);
+    auto kern = k_eval<W, MONO, ACC>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, H, reinterpret_cast<const uint8_t *>(dimg),
+                       s_begin, s_count, flush_rounds_for(H, threads), partials);
     return hipGetLastError();
 }
 
-template <int W, bool MONO>
-hipError_t launch_batch_t(const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items,
-                          uint32_t n_items, uint32_t *d_queue, Partial *partials, uint32_t blocks,
-                          uint32_t threads, uint32_t table_bytes, hipStream_t stream) {
-    auto kern = k_eval_batch<W, MONO>;
-    if (table_bytes > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)table_bytes);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), table_bytes, stream, d_hdrs, d_imgs, d_items,
-                       n_items, d_queue, partials);
+template <int W, bool MONO, int ACC>
+hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
+                          const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
+                          uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream) {
+    auto kern = k_eval_batch<W, MONO, ACC>;
+    hipError_t e = set_lds(kern, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds_bytes, stream, d_hdrs, d_imgs, d_items, n_items,
+                       d_queue, flush_rounds_for(H0, threads), partials);
     return hipGetLastError();
 }
 
 }  // namespace
 
-#define DISPATCH_W(W_, MONO_, CALL)                                    \
-    switch (W_) {                                                      \
-        case 1: return MONO_ ? CALL(1, true) : CALL(1, false);        \
-        case 2: return MONO_ ? CALL(2, true) : CALL(2, false);        \
-        case 4: return MONO_ ? CALL(4, true) : CALL(4, false);        \
-        case 8: return MONO_ ? CALL(8, true) : CALL(8, false);        \
-        case 16: return MONO_ ? CALL(16, true) : CALL(16, false);     \
-        default: return hipErrorInvalidValue;                          \
+size_t dyn_lds_bytes(const ImgHeader &H) {
+    if (H.acc == ACC_CLASS) return (size_t)H.zero_entry * H.q_limbs * 8;
+    return (size_t)H.table_n * 32;
+}
+
+uint32_t flush_rounds_for(const ImgHeader &H, uint32_t threads) {
+    // one round adds at most threads * 2^g terms of at most 2^31 each to a counter
+    const uint64_t per_round = (uint64_t)threads << H.g;
+    const uint64_t r = ((uint64_t)1 << 32) / (per_round ? per_round : 1);
+    return (uint32_t)(r < 1 ? 1 : (r > 0xffffffffu ? 0xffffffffu : r));
+}
+
+#define DISPATCH(W_, MONO_, ACC_, CALL)                                                      \
+    do {                                                                                     \
+        if ((ACC_) > 2) return hipErrorInvalidValue;                                         \
+        switch (W_) {                                                                        \
+            case 1: DISPATCH_MA(1, MONO_, ACC_, CALL);                                       \
+            case 2: DISPATCH_MA(2, MONO_, ACC_, CALL);                                       \
+            case 4: DISPATCH_MA(4, MONO_, ACC_, CALL);                                       \
+            case 8: DISPATCH_MA(8, MONO_, ACC_, CALL);                                       \
+            case 16: DISPATCH_MA(16, MONO_, ACC_, CALL);                                     \
+            default: return hipErrorInvalidValue;                                            \
+        }                                                                                    \
+    } while (0)
+#define DISPATCH_MA(w, MONO_, ACC_, CALL)                                                    \
+    if (MONO_) {                                                                             \
+        if ((ACC_) == ACC_I64) return CALL(w, true, ACC_I64);                                \
+        if ((ACC_) == ACC_I128) return CALL(w, true, ACC_I128);                              \
+        return CALL(w, true, ACC_CLASS);                                                     \
+    } else {                                                                                 \
+        if ((ACC_) == ACC_I64) return CALL(w, false, ACC_I64);                               \
+        if ((ACC_) == ACC_I128) return CALL(w, false, ACC_I128);                             \
+        return CALL(w, false, ACC_CLASS);                                                    \
     }
 
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                        Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
-    if ((size_t)H.table_n * 32 > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-#define CALL_EVAL(w, m) launch_eval_t<w, m>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
-    DISPATCH_W(H.W, H.has_mono != 0, CALL_EVAL)
+    if (dyn_lds_bytes(H) > MAX_TABLE_BYTES) return hipErrorInvalidValue;
+#define CALL_EVAL(w, m, a) launch_eval_t<w, m, a>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
+    DISPATCH(H.W, H.has_mono != 0, H.acc, CALL_EVAL);
 #undef CALL_EVAL
 }
 
 hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
                              const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue,
-                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t table_bytes,
+                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t lds_bytes,
                              hipStream_t stream) {
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
-    if (table_bytes > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-#define CALL_BATCH(w, m) \
-    launch_batch_t<w, m>(d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, table_bytes, stream)
-    DISPATCH_W(H0.W, H0.has_mono != 0, CALL_BATCH)
+    if (lds_bytes > MAX_TABLE_BYTES) return hipErrorInvalidValue;
+#define CALL_BATCH(w, m, a) \
+    launch_batch_t<w, m, a>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, lds_bytes, stream)
+    DISPATCH(H0.W, H0.has_mono != 0, H0.acc, CALL_BATCH);
 #undef CALL_BATCH
 }
 

@@ -403,8 +403,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             P.perm.push_back(i);
         }
     const int g = q + g_orig;
-    if (g > 30) {
-        *err = "too many pair factors for one Gray walk (at most 30)";
+    if (g > 24) {
+        *err = "too many pair factors for one Gray walk (walk length at most 2^24)";
         return SIM_ERANGE;
     }
     P.walk_bits = g_orig;
@@ -417,17 +417,31 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     };
 
     // ---- forms actually used, in packed positions
+    // every node factor owns its bit of L (so its statistic weights are single steps);
+    // linear phase terms share bits freely
     std::vector<int> form_slot(w.forms.size(), -1);
     std::vector<IrForm> used;
-    auto use_form = [&](int f) {
-        if (form_slot[f] < 0) {
-            form_slot[f] = (int)used.size();
-            used.push_back(IrForm{w.forms[f].cst, permute(w.forms[f].mask)});
-        }
-        return form_slot[f];
+    std::vector<char> node_owned;
+    auto new_bit = [&](int f) {
+        used.push_back(IrForm{w.forms[f].cst, permute(w.forms[f].mask)});
+        node_owned.push_back(0);
+        return (int)used.size() - 1;
     };
-    for (auto &n : w.nodes) n.first = use_form(n.first);
-    for (auto &l : w.lin) l.second = use_form(l.second);
+    for (auto &n : w.nodes) {
+        int f = n.first;
+        int b = form_slot[f];
+        if (b < 0 || node_owned[b]) {
+            b = new_bit(f);
+            if (form_slot[f] < 0) form_slot[f] = b;
+        }
+        node_owned[b] = 1;
+        n.first = b;
+    }
+    for (auto &l : w.lin) {
+        int f = l.second;
+        if (form_slot[f] < 0) form_slot[f] = new_bit(f);
+        l.second = form_slot[f];
+    }
     const int F = (int)used.size();
     int W = 1;
     while (W * 32 < F) W *= 2;
@@ -518,40 +532,34 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     img.insert(img.end(), z0.begin(), z0.end());
     H.off_z1 = (uint32_t)img.size();
     img.insert(img.end(), z1.begin(), z1.end());
-    for (int s = 0; s < N_STATS; ++s) {
-        H.stat_off[s] = (uint32_t)img.size();
+    H.off_slots = (uint32_t)img.size();
+    for (int s = 0; s < N_STATS; ++s)
         H.stat_base[s] = (int32_t)(s == STAT_R ? mod8(base[s]) : base[s]);
-        uint32_t cnt = 0;
-        auto emit = [&](long long weight, const std::vector<uint32_t> &mask) {
-            bool any = false;
-            for (uint32_t v : mask) any |= v != 0;
-            if (!any) return;
-            img.push_back((uint32_t)(int32_t)weight);
-            img.insert(img.end(), mask.begin(), mask.end());
-            ++cnt;
-        };
-        if (s == STAT_R) {
-            for (int bit = 0; bit < 3; ++bit) {
-                std::vector<uint32_t> mask(W, 0);
-                for (int f = 0; f < F; ++f)
-                    if (mod8(wt[s][f]) >> bit & 1) mask[f / 32] |= 1u << (f % 32);
-                emit(1LL << bit, mask);
-            }
-        } else {
-            long long mx = 0;
-            for (int f = 0; f < F; ++f) mx = std::max(mx, std::llabs(wt[s][f]));
-            for (int bit = 0; (1LL << bit) <= mx; ++bit) {
-                std::vector<uint32_t> pm(W, 0), nm(W, 0);
-                for (int f = 0; f < F; ++f) {
-                    long long v = wt[s][f];
-                    if (v > 0 && (v >> bit & 1)) pm[f / 32] |= 1u << (f % 32);
-                    if (v < 0 && ((-v) >> bit & 1)) nm[f / 32] |= 1u << (f % 32);
-                }
-                emit(1LL << bit, pm);
-                emit(-(1LL << bit), nm);
+    int active_slots = 0;
+    for (int i = 0; i < kSlots; ++i) {
+        const int s = slot_stat(i), wgt = slot_weight(i);
+        std::vector<uint32_t> mask(W, 0);
+        bool any = false;
+        for (int f = 0; f < F; ++f) {
+            long long v = wt[s][f];
+            bool on;
+            if (s == STAT_R) on = (mod8(v) & wgt) != 0;
+            else on = v == wgt;
+            if (on) {
+                mask[f / 32] |= 1u << (f % 32);
+                any = true;
             }
         }
-        H.stat_n[s] = cnt;
+        for (int f = 0; f < F; ++f) {
+            long long v = wt[s][f];
+            if (s != STAT_R && v != 0 && v != 1 && v != -1 && !(s == STAT_E && (v == 2 || v == -2))) {
+                *err = "internal: statistic weight outside the fixed slots";
+                return SIM_EINVAL;
+            }
+        }
+        img.push_back(any ? (uint32_t)(int32_t)wgt : 0u);
+        img.insert(img.end(), mask.begin(), mask.end());
+        active_slots += any ? 1 : 0;
     }
     // monomials in packed positions
     const uint64_t walk_mask = g >= 64 ? ~0ull : (((uint64_t)1 << g) - 1);
@@ -597,6 +605,21 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.d_off = (int32_t)(-dmin);
     H.table_n = (uint32_t)(nd * 16 + 1);
     H.zero_entry = (uint32_t)(nd * 16);
+    // accumulation mode: int64 registers when the static bound allows, else per-block class
+    // counters when they fit the LDS budget, else int128 registers
+    {
+        long long emax = base[STAT_E];
+        for (int f = 0; f < F; ++f)
+            if (wt[STAT_E][f] > 0) emax += wt[STAT_E][f];
+        emax += std::max(0LL, std::min(amax, bmax));
+        const int hmax = (int)std::max(0LL, emax) / 2;
+        H.q_limbs = (uint32_t)(hmax / 32 + 1);
+        const long long bound_bits = (long long)w.nodes.size() + w.pe;
+        const size_t class_bytes = (size_t)nd * 16 * H.q_limbs * 8;
+        if (bound_bits <= 62) H.acc = ACC_I64;
+        else if (class_bytes <= 48 * 1024) H.acc = ACC_CLASS;
+        else H.acc = ACC_I128;
+    }
     std::vector<int64_t> table((size_t)H.table_n * 4, 0);
     for (int d = (int)dmin; d <= (int)dmax; ++d)
         for (int r = 0; r < 8; ++r)
@@ -626,8 +649,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // walk step the slice-dependent monomial updates whose walk part holds (5 each, +2),
     // plus the per-slice set-up spread over the 2^g terms of a slice.
     {
-        double ops = W + 10 + 40;
-        for (int s = 0; s < N_STATS; ++s) ops += H.stat_n[s] * (2.0 * W + 1);
+        double acc_ops = H.acc == ACC_I64 ? 14.0 : H.acc == ACC_I128 ? 42.0 : 5.0;
+        double ops = W + 10 + acc_ops + active_slots * (2.0 * W + 1);
         if (has_zero) ops += 3.0 * W + 1;
         double setup = (double)(w.pe - g) * 2.0 * W + 5.0 * H.n_monohi;
         double steps = (double)((uint64_t)1 << g);
