@@ -169,6 +169,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--p-cap", type=int, default=36)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed steps, copy a device buffer of this size once (a plain copy of "
+                         "known size that calibrates the HBM traffic counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -208,6 +211,14 @@ def main():
         ref = val
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb << 20
+        src = torch.empty(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     terms = float(1 << p)

@@ -52,8 +52,15 @@ struct ImgHeader {
     int32_t stat_base[N_STATS];
     uint32_t off_monohi;  // monomials over high positions only: c, mask_lo, mask_hi (slice bits)
     uint32_t n_monohi;
-    uint32_t off_didx;    // g + 1 words: delta entries for walk position i are [didx[i], didx[i+1])
-    uint32_t off_delta;   // entries of 4 words: c, walk mask, slice mask lo, slice mask hi
+    // Gray-step changes of the variable monomials.  At a flip of walk position i the walk bits
+    // below i are fixed (bit i-1 set, lower bits clear), so each monomial containing i either
+    // always contributes when i flips, never does, or depends on walk bits above i:
+    uint32_t off_ui;      // g words: sum of coefficients always firing with no slice part
+    uint32_t off_aidx;    // g + 1 words: slice-dependent always-firing entries of position i are
+    uint32_t off_al;      //   [aidx[i], aidx[i+1]) at off_al, 3 words each: c, slice mask lo, hi
+    uint32_t off_didx;    // g + 1 words: walk-state-dependent entries of position i are
+    uint32_t off_delta;   //   [didx[i], didx[i+1]) at off_delta, 4 words each: c, walk mask
+                          //   (positions above i), slice mask lo, slice mask hi
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
     uint32_t table_n;         // entries (value classes + one zero entry)
     int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e

@@ -147,11 +147,22 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S,
         for (int w = 0; w < W; ++w) L[w] ^= col[j * W + w] & m;
     }
     int phi = 0;
+    uint64_t dal = 0;  // 4-bit field i: always-firing slice-dependent change at a flip of i (mod 8)
     if (MONO) {
         CU32 *mh = wd + H.off_monohi;
         for (uint32_t e = 0; e < H.n_monohi; ++e, mh += 3) {
             const uint64_t hm = (uint64_t)mh[1] | ((uint64_t)mh[2] << 32);
             phi += ((s & hm) == hm) ? (int)mh[0] : 0;
+        }
+        CU32 *aidx = wd + H.off_aidx;
+        for (uint32_t i = 0; i < H.g; ++i) {
+            int f = 0;
+            CU32 *ae = wd + H.off_al + 3 * aidx[i];
+            for (uint32_t e = aidx[i]; e < aidx[i + 1]; ++e, ae += 3) {
+                const uint64_t hm = (uint64_t)ae[1] | ((uint64_t)ae[2] << 32);
+                f += ((s & hm) == hm) ? (int)ae[0] : 0;
+            }
+            dal |= (uint64_t)(f & 7) << (4 * i);
         }
     }
     add_term<W, ACC>(H, S, wd, tab, cnt, L, phi, acc);
@@ -166,7 +177,8 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S,
             CU32 *didx = wd + H.off_didx;
             const uint32_t e0 = didx[i], e1 = didx[i + 1];
             CU32 *de = wd + H.off_delta + 4 * e0;
-            int du = 0, dv = 0;
+            int du = (int)wd[H.off_ui + i];
+            int dv = (int)((dal >> (4 * i)) & 7u);
             for (uint32_t e = e0; e < e1; ++e, de += 4) {
                 const uint32_t wm = de[1];
                 if ((gray & wm) != wm) continue;

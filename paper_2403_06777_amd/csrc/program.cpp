@@ -378,7 +378,12 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // more lanes for the same work) cost nothing; with monomials a longer walk pays off.
     const int want = w.mono.empty() ? 6 : 12;
     int g_orig = std::min(p, std::min(max_walk_bits, want));
+    if (!w.mono.empty()) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
     if (p - g_orig > 62) g_orig = p - 62;
+    if (!w.mono.empty() && q + g_orig > 16) {
+        *err = "too many pair factors together with variable monomials (at most 16 walk bits)";
+        return SIM_ERANGE;
+    }
     // walked parameters: fewest monomials first (they flip most often); high: index order
     std::vector<int> order(p);
     for (int i = 0; i < p; ++i) order[i] = i;
@@ -578,21 +583,46 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         img.push_back((uint32_t)(hm >> 32));
         H.n_monohi++;
     }
-    H.off_didx = (uint32_t)img.size();
-    std::vector<std::vector<uint32_t>> per(g);
+    // per walk position i: always-firing entries (uniform sum, or per-lane list) and the
+    // entries that depend on walk bits above i; entries needing a bit below i - 1 never fire
+    std::vector<int> ui(g, 0);
+    std::vector<std::vector<uint32_t>> al(g), per(g);
     for (int i = 0; i < g; ++i) {
         for (const auto &m : monos) {
             if (!(m.second >> i & 1)) continue;
-            uint64_t others = m.second & ~((uint64_t)1 << i);
-            uint32_t wm = (uint32_t)(others & walk_mask);
-            uint64_t hm = others >> g;
-            per[i].push_back((uint32_t)m.first);
-            per[i].push_back(wm);
-            per[i].push_back((uint32_t)hm);
-            per[i].push_back((uint32_t)(hm >> 32));
+            const uint64_t others = m.second & ~((uint64_t)1 << i);
+            const uint32_t wm = (uint32_t)(others & walk_mask);
+            const uint64_t hm = others >> g;
+            const uint32_t below = i > 0 ? (uint32_t)(((uint64_t)1 << (i - 1)) - 1) : 0u;
+            if (wm & below) continue;                        // needs a bit that is 0: never fires
+            const uint32_t above = wm >> (i + 1) << (i + 1);  // bits above i decide
+            if (!above) {
+                if (!hm) ui[i] = mod8(ui[i] + m.first);
+                else {
+                    al[i].push_back((uint32_t)m.first);
+                    al[i].push_back((uint32_t)hm);
+                    al[i].push_back((uint32_t)(hm >> 32));
+                }
+            } else {
+                per[i].push_back((uint32_t)m.first);
+                per[i].push_back(above);
+                per[i].push_back((uint32_t)hm);
+                per[i].push_back((uint32_t)(hm >> 32));
+            }
         }
     }
+    H.off_ui = (uint32_t)img.size();
+    for (int i = 0; i < g; ++i) img.push_back((uint32_t)ui[i]);
+    H.off_aidx = (uint32_t)img.size();
     uint32_t acc = 0;
+    for (int i = 0; i <= g; ++i) {
+        img.push_back(acc);
+        if (i < g) acc += (uint32_t)(al[i].size() / 3);
+    }
+    H.off_al = (uint32_t)img.size();
+    for (int i = 0; i < g; ++i) img.insert(img.end(), al[i].begin(), al[i].end());
+    H.off_didx = (uint32_t)img.size();
+    acc = 0;
     for (int i = 0; i <= g; ++i) {
         img.push_back(acc);
         if (i < g) acc += (uint32_t)(per[i].size() / 4);
@@ -656,19 +686,23 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         double steps = (double)((uint64_t)1 << g);
         double mono_ops = 0;
         if (!w.mono.empty() && g > 0) {
-            // exact count over one walk: step t flips position ctz(t) with Gray state gray(t)
+            // exact count over one walk: step t flips position ctz(t) with Gray state gray(t);
+            // per step the packed always-firing field (2) and the sign (2), plus 5 per
+            // state-dependent slice entry that fires; per slice the always-firing fields
             const uint32_t *didx = img.data() + H.off_didx;
             const uint32_t *de = img.data() + H.off_delta;
             for (uint64_t t = 1; t < ((uint64_t)1 << g); ++t) {
                 int i = __builtin_ctzll(t);
                 uint32_t gray = (uint32_t)(t ^ (t >> 1));
-                mono_ops += 2;
+                mono_ops += 4;
                 for (uint32_t e = didx[i]; e < didx[i + 1]; ++e) {
                     uint32_t wm = de[4 * e + 1];
                     bool hi = de[4 * e + 2] || de[4 * e + 3];
                     if ((gray & wm) == wm && hi) mono_ops += 5;
                 }
             }
+            const uint32_t *aidx = img.data() + H.off_aidx;
+            setup += 5.0 * aidx[g] + 4.0 * g;
         }
         P.ops_per_term = ops + (setup + mono_ops) / steps;
     }
