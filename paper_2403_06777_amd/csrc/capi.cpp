@@ -511,20 +511,22 @@ int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_s
     // group by kernel variant, keep program order inside a group
     auto variant = [&](uint32_t i) {
         const ImgHeader &H = ps[i]->pk.hdr;
-        return (H.W * 2 + H.has_mono) * 4 + H.acc;
+        return ((H.W * 2 + H.has_mono) * 4 + H.acc) * 4 + (H.acc == ACC_I128 ? 0 : H.slot_menu);
     };
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return variant(a) < variant(b); });
     for (uint32_t i : order) {
         const sim_program *P = ps[i];
         const ImgHeader &H = P->pk.hdr;
+        const uint32_t menu = H.acc == ACC_I128 ? 0u : H.slot_menu;
         if (L->groups.empty() || L->groups.back().W != H.W || L->groups.back().mono != H.has_mono ||
-            L->groups.back().acc != H.acc) {
+            L->groups.back().acc != H.acc || L->groups.back().h0.slot_menu != menu) {
             BatchLayout::Group g;
             g.W = H.W;
             g.mono = H.has_mono;
             g.acc = H.acc;
             g.item_first = (uint32_t)L->items.size();
             g.h0 = H;
+            g.h0.slot_menu = menu;
             L->groups.push_back(g);
         }
         BatchLayout::Group &g = L->groups.back();

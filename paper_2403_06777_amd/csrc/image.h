@@ -29,6 +29,16 @@ IMG_HD constexpr int slot_weight(int i) {
          : i == 7 ? -2 : i == 8 ? 1 : i == 9 ? 2 : 4;
 }
 
+// Menu of compile-time slot sets: a kernel variant computes exactly the slots of its set
+// (branch-free); the packer picks the smallest set that covers the program's active slots
+// and leaves the other slots of that set with zero masks.
+constexpr uint32_t kSlotSetAll = 0x7FFu;    // every slot
+constexpr uint32_t kSlotSetNodes = 0x7C5u;  // A+1, B+1, E-1, E-2, R*: factors 1 + w^{k l}
+constexpr uint32_t kSlotSetPhase = 0x700u;  // R* only: phase terms without factors
+IMG_HD constexpr uint32_t slot_set_of(uint32_t menu_index) {
+    return menu_index == 1 ? kSlotSetNodes : menu_index == 2 ? kSlotSetPhase : kSlotSetAll;
+}
+
 // how the terms of a lane are summed
 enum {
     ACC_I64 = 0,   // every partial sum fits int64 (static bound): four int64 registers
@@ -43,6 +53,7 @@ struct ImgHeader {
     uint32_t has_zero;  // some factor can vanish: test the zero masks
     uint32_t has_mono;  // variable monomials present
     uint32_t acc;       // ACC_* mode
+    uint32_t slot_menu; // index into the slot-set menu (0 all, 1 node factors, 2 phase only)
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j
     uint32_t off_cvec;  // W words: constant bits of the forms

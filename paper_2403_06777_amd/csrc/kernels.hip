@@ -38,16 +38,15 @@ __device__ __forceinline__ CU32 *const_words(const uint8_t *img) {
 // the per-program statistic masks, read once and kept in scalar registers
 template <int W>
 struct Slots {
-    int wgt[kSlots];
     uint32_t m[kSlots][W];
 };
 
-template <int W>
+template <int W, uint32_t SET>
 __device__ __forceinline__ void load_slots(const ImgHeader &H, CU32 *wd, Slots<W> &S) {
 #pragma unroll
     for (int i = 0; i < kSlots; ++i) {
+        if (!((SET >> i) & 1u)) continue;
         CU32 *e = wd + H.off_slots + i * (W + 1);
-        S.wgt[i] = (int)e[0];
 #pragma unroll
         for (int w = 0; w < W; ++w) S.m[i][w] = e[1 + w];
     }
@@ -59,7 +58,7 @@ struct TermClass {
     bool zero;
 };
 
-template <int W>
+template <int W, uint32_t SET>
 __device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W> &S, CU32 *wd,
                                               const uint32_t (&L)[W], int phi) {
     int st[N_STATS];
@@ -67,11 +66,14 @@ __device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W>
     for (int s = 0; s < N_STATS; ++s) st[s] = H.stat_base[s];
 #pragma unroll
     for (int i = 0; i < kSlots; ++i) {
-        if (S.wgt[i] != 0) {
+        if ((SET >> i) & 1u) {  // compile-time: the slot belongs to this kernel's set
             uint32_t c = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) c += popc(L[w] & S.m[i][w]);
-            st[slot_stat(i)] += __mul24((int)c, S.wgt[i]);
+            const int wgt = slot_weight(i);
+            if (wgt == 1) st[slot_stat(i)] += (int)c;
+            else if (wgt == -1) st[slot_stat(i)] -= (int)c;
+            else st[slot_stat(i)] += (int)c * wgt;
         }
     }
     TermClass t;
@@ -105,10 +107,10 @@ struct Acc {
     }
 };
 
-template <int W, int ACC>
+template <int W, int ACC, uint32_t SET>
 __device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
                                          unsigned long long *cnt, const uint32_t (&L)[W], int phi, Acc<ACC> &acc) {
-    const TermClass t = classify<W>(H, S, wd, L, phi);
+    const TermClass t = classify<W, SET>(H, S, wd, L, phi);
     if (ACC == ACC_CLASS) {
         if (!t.zero) {
             // counters are laid out [q][class]: 24-bit multiply-add (full rate)
@@ -134,7 +136,7 @@ __device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, 
 }
 
 // all 2^g assignments of slice s (high parameters = bits of s)
-template <int W, bool MONO, int ACC>
+template <int W, bool MONO, int ACC, uint32_t SET>
 __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
                                           unsigned long long *cnt, uint64_t s, Acc<ACC> &acc) {
     CU32 *col = wd + H.off_col;
@@ -165,7 +167,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S,
             dal |= (uint64_t)(f & 7) << (4 * i);
         }
     }
-    add_term<W, ACC>(H, S, wd, tab, cnt, L, phi, acc);
+    add_term<W, ACC, SET>(H, S, wd, tab, cnt, L, phi, acc);
     const uint32_t n = 1u << H.g;
     uint32_t gray = 0;
     for (uint32_t t = 1; t < n; ++t) {
@@ -190,7 +192,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S,
             const int dd = du + dv;
             phi += ((gray >> i) & 1u) ? dd : -dd;
         }
-        add_term<W, ACC>(H, S, wd, tab, cnt, L, phi, acc);
+        add_term<W, ACC, SET>(H, S, wd, tab, cnt, L, phi, acc);
     }
 }
 
@@ -281,20 +283,20 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
 
 // Rounds of blockDim slices are uniform across the block, so counters can be flushed
 // between rounds (every flush_rounds rounds keeps each counter below 2^64).
-template <int W, bool MONO, int ACC>
+template <int W, bool MONO, int ACC, uint32_t SET>
 __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img, uint64_t s_first, uint64_t s_count,
                                           uint64_t lane0, uint64_t stride, uint32_t flush_rounds, int64_t *s_tab,
                                           unsigned long long *s_cnt, i128 (&out)[4]) {
     CU32 *wd = const_words(img);
     const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
     Slots<W> S;
-    load_slots<W>(H, wd, S);
+    load_slots<W, SET>(H, wd, S);
     Acc<ACC> acc;
     acc.clear();
     uint32_t rounds = 0;
     for (uint64_t base = lane0 - threadIdx.x; base < s_count; base += stride) {
         const uint64_t s = base + threadIdx.x;
-        if (s < s_count) run_slice<W, MONO, ACC>(H, S, wd, s_tab, s_cnt, s_first + s, acc);
+        if (s < s_count) run_slice<W, MONO, ACC, SET>(H, S, wd, s_tab, s_cnt, s_first + s, acc);
         if (ACC == ACC_CLASS && ++rounds == flush_rounds) {
             flush_counters<ACC>(H, gtab, s_cnt, out);
             rounds = 0;
@@ -304,7 +306,7 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
     acc_to_i128<ACC>(acc, out);
 }
 
-template <int W, bool MONO, int ACC>
+template <int W, bool MONO, int ACC, uint32_t SET>
 __global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t *__restrict__ img,
                                                       uint64_t s_begin, uint64_t s_count, uint32_t flush_rounds,
                                                       Partial *__restrict__ partials) {
@@ -313,12 +315,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t
     prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
     i128 out[4] = {0, 0, 0, 0};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    run_range<W, MONO, ACC>(H, img, s_begin, s_count, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride,
+    run_range<W, MONO, ACC, SET>(H, img, s_begin, s_count, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride,
                             flush_rounds, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn), out);
     block_reduce_store(out, partials + blockIdx.x);
 }
 
-template <int W, bool MONO, int ACC>
+template <int W, bool MONO, int ACC, uint32_t SET>
 __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__restrict__ hdrs,
                                                             const uint64_t *__restrict__ imgs,
                                                             const WorkItem *__restrict__ items, uint32_t n_items,
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__r
             loaded = prog;
         }
         i128 out[4] = {0, 0, 0, 0};
-        run_range<W, MONO, ACC>(H, img, wi.s_begin, wi.s_end - wi.s_begin, threadIdx.x, blockDim.x, flush_rounds,
+        run_range<W, MONO, ACC, SET>(H, img, wi.s_begin, wi.s_end - wi.s_begin, threadIdx.x, blockDim.x, flush_rounds,
                                 s_dyn, reinterpret_cast<unsigned long long *>(s_dyn), out);
         block_reduce_store(out, partials + wi.out_slot);
     }
@@ -412,11 +414,11 @@ hipError_t set_lds(K kern, size_t lds) {
                                (int)lds);
 }
 
-template <int W, bool MONO, int ACC>
+template <int W, bool MONO, int ACC, uint32_t SET>
 hipError_t launch_eval_t(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
     const size_t lds = dyn_lds_bytes(H);
-    auto kern = k_eval<W, MONO, ACC>;
+    auto kern = k_eval<W, MONO, ACC, SET>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, H, reinterpret_cast<const uint8_t *>(dimg),
@@ -424,11 +426,11 @@ hipError_t launch_eval_t(const ImgHeader &H, const void *dimg, uint64_t s_begin,
     return hipGetLastError();
 }
 
-template <int W, bool MONO, int ACC>
+template <int W, bool MONO, int ACC, uint32_t SET>
 hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
                           const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
                           uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream) {
-    auto kern = k_eval_batch<W, MONO, ACC>;
+    auto kern = k_eval_batch<W, MONO, ACC, SET>;
     hipError_t e = set_lds(kern, lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds_bytes, stream, d_hdrs, d_imgs, d_items, n_items,
@@ -450,36 +452,44 @@ uint32_t flush_rounds_for(const ImgHeader &H, uint32_t threads) {
     return (uint32_t)(r < 1 ? 1 : (r > 0xffffffffu ? 0xffffffffu : r));
 }
 
-#define DISPATCH(W_, MONO_, ACC_, CALL)                                                      \
+// variant selection: slot set (int128 accumulation only with the full set), accumulation
+// mode, monomials, form-vector width
+#define DISPATCH(W_, MONO_, ACC_, MENU_, CALL)                                               \
     do {                                                                                     \
-        if ((ACC_) > 2) return hipErrorInvalidValue;                                         \
+        if ((ACC_) > 2 || (MENU_) > 2) return hipErrorInvalidValue;                          \
         switch (W_) {                                                                        \
-            case 1: DISPATCH_MA(1, MONO_, ACC_, CALL);                                       \
-            case 2: DISPATCH_MA(2, MONO_, ACC_, CALL);                                       \
-            case 4: DISPATCH_MA(4, MONO_, ACC_, CALL);                                       \
-            case 8: DISPATCH_MA(8, MONO_, ACC_, CALL);                                       \
-            case 16: DISPATCH_MA(16, MONO_, ACC_, CALL);                                     \
+            case 1: DISPATCH_M(1, MONO_, ACC_, MENU_, CALL);                                 \
+            case 2: DISPATCH_M(2, MONO_, ACC_, MENU_, CALL);                                 \
+            case 4: DISPATCH_M(4, MONO_, ACC_, MENU_, CALL);                                 \
+            case 8: DISPATCH_M(8, MONO_, ACC_, MENU_, CALL);                                 \
+            case 16: DISPATCH_M(16, MONO_, ACC_, MENU_, CALL);                               \
             default: return hipErrorInvalidValue;                                            \
         }                                                                                    \
     } while (0)
-#define DISPATCH_MA(w, MONO_, ACC_, CALL)                                                    \
-    if (MONO_) {                                                                             \
-        if ((ACC_) == ACC_I64) return CALL(w, true, ACC_I64);                                \
-        if ((ACC_) == ACC_I128) return CALL(w, true, ACC_I128);                              \
-        return CALL(w, true, ACC_CLASS);                                                     \
-    } else {                                                                                 \
-        if ((ACC_) == ACC_I64) return CALL(w, false, ACC_I64);                               \
-        if ((ACC_) == ACC_I128) return CALL(w, false, ACC_I128);                             \
-        return CALL(w, false, ACC_CLASS);                                                    \
-    }
+#define DISPATCH_M(w, MONO_, ACC_, MENU_, CALL)                                              \
+    if (MONO_) DISPATCH_A(w, true, ACC_, MENU_, CALL);                                       \
+    else DISPATCH_A(w, false, ACC_, MENU_, CALL);
+#define DISPATCH_A(w, m, ACC_, MENU_, CALL)                                                  \
+    do {                                                                                     \
+        if ((ACC_) == ACC_I128) return CALL(w, m, ACC_I128, kSlotSetAll);                    \
+        if ((ACC_) == ACC_I64) {                                                             \
+            if ((MENU_) == 1) return CALL(w, m, ACC_I64, kSlotSetNodes);                     \
+            if ((MENU_) == 2) return CALL(w, m, ACC_I64, kSlotSetPhase);                     \
+            return CALL(w, m, ACC_I64, kSlotSetAll);                                         \
+        }                                                                                    \
+        if ((MENU_) == 1) return CALL(w, m, ACC_CLASS, kSlotSetNodes);                       \
+        if ((MENU_) == 2) return CALL(w, m, ACC_CLASS, kSlotSetPhase);                       \
+        return CALL(w, m, ACC_CLASS, kSlotSetAll);                                           \
+    } while (0)
 
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                        Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
     if (dyn_lds_bytes(H) > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-#define CALL_EVAL(w, m, a) launch_eval_t<w, m, a>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
-    DISPATCH(H.W, H.has_mono != 0, H.acc, CALL_EVAL);
+#define CALL_EVAL(w, m, a, set) \
+    launch_eval_t<w, m, a, set>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
+    DISPATCH(H.W, H.has_mono != 0, H.acc, H.slot_menu, CALL_EVAL);
 #undef CALL_EVAL
 }
 
@@ -490,9 +500,10 @@ hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
     if (lds_bytes > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-#define CALL_BATCH(w, m, a) \
-    launch_batch_t<w, m, a>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, lds_bytes, stream)
-    DISPATCH(H0.W, H0.has_mono != 0, H0.acc, CALL_BATCH);
+#define CALL_BATCH(w, m, a, set) \
+    launch_batch_t<w, m, a, set>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, \
+                                 lds_bytes, stream)
+    DISPATCH(H0.W, H0.has_mono != 0, H0.acc, H0.slot_menu, CALL_BATCH);
 #undef CALL_BATCH
 }
 

@@ -541,6 +541,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     for (int s = 0; s < N_STATS; ++s)
         H.stat_base[s] = (int32_t)(s == STAT_R ? mod8(base[s]) : base[s]);
     int active_slots = 0;
+    uint32_t active_mask = 0;
     for (int i = 0; i < kSlots; ++i) {
         const int s = slot_stat(i), wgt = slot_weight(i);
         std::vector<uint32_t> mask(W, 0);
@@ -565,7 +566,10 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         img.push_back(any ? (uint32_t)(int32_t)wgt : 0u);
         img.insert(img.end(), mask.begin(), mask.end());
         active_slots += any ? 1 : 0;
+        if (any) active_mask |= 1u << i;
     }
+    H.slot_menu = (active_mask & ~kSlotSetPhase) == 0 ? 2u : (active_mask & ~kSlotSetNodes) == 0 ? 1u : 0u;
+    active_slots = __builtin_popcount(slot_set_of(H.slot_menu));
     // monomials in packed positions
     const uint64_t walk_mask = g >= 64 ? ~0ull : (((uint64_t)1 << g) - 1);
     std::vector<std::pair<int, uint64_t>> monos;
