@@ -112,6 +112,8 @@ typedef struct {
     uint32_t n_constraints; /* parameters removed by constraint elimination */
     double ops_per_term;    /* int32 lane operations per term of the evaluation algorithm,
                                counted from the packed program (the roofline's work unit) */
+    double nonzero_fraction; /* exact fraction of the 2^p assignments on which no factor
+                               vanishes (only those terms reach the factor statistics) */
 } sim_info;
 
 /* launch shape of the evaluation kernels; zero fields take the library's choice */

@@ -75,7 +75,7 @@ class sim_info(ctypes.Structure):
                 ("log2_terms", ctypes.c_double), ("n_eval_params", ctypes.c_uint32),
                 ("is_zero", ctypes.c_uint32), ("compile_seconds", ctypes.c_double),
                 ("t_count", ctypes.c_uint32), ("n_constraints", ctypes.c_uint32),
-                ("ops_per_term", ctypes.c_double)]
+                ("ops_per_term", ctypes.c_double), ("nonzero_fraction", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -7,27 +7,52 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzxpar.so")
-SOURCES = ["capi.cpp", "program.cpp", "compiler.cpp", "kernels.hip"]
+SOURCES = ["capi.cpp", "program.cpp", "compiler.cpp", "kernels.hip",
+           "eval_w1.hip", "eval_w2.hip", "eval_w4.hip", "eval_w8.hip", "eval_w16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-fvisibility=hidden",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-fvisibility=hidden",
     # no packed fp32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source to an object in parallel (up to `jobs` at once, default: the
+    CPU count, at most 16), then links the shared library."""
+    objdir = os.path.join(HERE, "_objs")
+    os.makedirs(objdir, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 1)
+    cmds = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmds.append([HIPCC] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)])
+    running, failed = [], []
+    pending = list(cmds)
+    while pending or running:
+        while pending and len(running) < jobs:
+            cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                  text=True)))
+        cmd, proc = running.pop(0)
+        out, _ = proc.communicate()
+        if proc.returncode != 0:
+            failed.append((cmd, out))
+    if failed:
+        for cmd, out in failed:
+            sys.stderr.write(" ".join(cmd) + "\n" + out)
+        raise RuntimeError("hipcc failed building libzxpar.so")
     tmp = OUT + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    proc = subprocess.run(cmd, capture_output=True, text=True)
+    objs = [c[c.index("-o") + 1] for c in cmds]
+    link = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    proc = subprocess.run(link, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building libzxpar.so")
+        raise RuntimeError("linking libzxpar.so failed")
     os.replace(tmp, OUT)
     return OUT
 

@@ -294,6 +294,7 @@ void fill_info(const PackedProgram &pk, double compile_seconds, uint32_t t_count
     out->t_count = t_count;
     out->n_constraints = n_constraints;
     out->ops_per_term = pk.ops_per_term;
+    out->nonzero_fraction = pk.nonzero_fraction;
 }
 }  // namespace
 

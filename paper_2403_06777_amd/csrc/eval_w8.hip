@@ -1,0 +1,4 @@
+// Evaluation kernels for form vectors of 8 words (32 forms per word).
+#include "eval_kernels.h"
+
+INSTANTIATE_EVAL_W(8)

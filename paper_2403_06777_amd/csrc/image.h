@@ -39,6 +39,13 @@ IMG_HD constexpr uint32_t slot_set_of(uint32_t menu_index) {
     return menu_index == 1 ? kSlotSetNodes : menu_index == 2 ? kSlotSetPhase : kSlotSetAll;
 }
 
+// Walk positions 0 .. kInnerBits-1 are stepped in unrolled blocks of 2^kInnerBits terms: the
+// flip positions inside a block are compile-time constants, and the phase of every term of a
+// block relative to its first term is one 4-bit field (mod 8) of a per-lane 64-bit vector built
+// once per block.  Programs with fewer walk bits use the plain step loop.
+constexpr int kInnerBits = 4;
+constexpr int kInnerSteps = 1 << kInnerBits;  // one 64-bit vector of 4-bit fields per block
+
 // how the terms of a lane are summed
 enum {
     ACC_I64 = 0,   // every partial sum fits int64 (static bound): four int64 registers
@@ -72,6 +79,16 @@ struct ImgHeader {
     uint32_t off_didx;    // g + 1 words: walk-state-dependent entries of position i are
     uint32_t off_delta;   //   [didx[i], didx[i+1]) at off_delta, 4 words each: c, walk mask
                           //   (positions above i), slice mask lo, slice mask hi
+    // Inner-block phase vectors.  Field k (bits 4k .. 4k+3) of a vector holds, mod 8, the phase
+    // of step k of a block minus that of step 0; the walk state of step k inside the block is
+    // gray(k) on the inner positions, with the top inner bit inverted in odd blocks, so every
+    // vector comes as an (even, odd) pair, each as (lo, hi) words.  Only monomials with an inner
+    // variable contribute; one is active when its other variables are all 1:
+    uint32_t off_inner;   // 4 words: sum over monomials whose other variables are all inner
+    uint32_t off_c2;      // n_c2 entries, 6 words: even lo, hi, odd lo, hi, slice mask lo, hi
+    uint32_t n_c2;        //   (other variables: slice bits only)
+    uint32_t off_c3;      // n_c3 entries, 7 words: even lo, hi, odd lo, hi, outer walk mask,
+    uint32_t n_c3;        //   slice mask lo, hi (some other variable is an outer walk bit)
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
     uint32_t table_n;         // entries (value classes + one zero entry)
     int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e

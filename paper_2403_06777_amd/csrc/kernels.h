@@ -28,6 +28,9 @@ struct DevResult {
 // largest dynamic LDS a value table may take
 #define MAX_TABLE_BYTES (64 * 1024)
 
+// largest block of the evaluation and finalise kernels
+constexpr int kMaxThreads = 256;
+
 // dynamic LDS of a program: value table (register modes) or class counters
 size_t dyn_lds_bytes(const ImgHeader &H);
 // rounds of `threads` slices between flushes of the class counters
@@ -52,3 +55,12 @@ hipError_t launch_reset_queue(uint32_t *d_queue, hipStream_t stream);
 hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item_first,
                                  const uint32_t *d_item_count, const FinalArgs *d_args, uint32_t n_progs,
                                  DevResult *d_out, hipStream_t stream);
+
+// per-width evaluation launches, instantiated in eval_w<W>.hip (W = 1, 2, 4, 8, 16)
+template <int W>
+hipError_t launch_eval_w(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
+                         Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
+template <int W>
+hipError_t launch_batch_w(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
+                          const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
+                          uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream);

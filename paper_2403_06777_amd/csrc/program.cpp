@@ -28,6 +28,7 @@
 #include "program.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <sstream>
@@ -295,6 +296,38 @@ Zw one_plus_w(int k) {
 }
 
 }  // namespace
+
+// Fraction of assignments on which no node factor vanishes.  A factor with values (v0, v1) on
+// its form l vanishes where l takes the value whose exponent is 4 (1 + w^4 = 0), so the
+// surviving assignments satisfy one affine equation per such factor: an affine subspace of
+// codimension rank (Gaussian elimination over GF(2)), or none if the equations contradict.
+static double nonzero_fraction(const std::vector<IrForm> &forms, const std::vector<std::pair<int, std::pair<int, int>>> &nodes) {
+    std::vector<std::pair<uint64_t, int>> rows;  // mask . x = rhs
+    for (const auto &n : nodes) {
+        const IrForm &f = forms[n.first];
+        const int v0 = n.second.first, v1 = n.second.second;
+        if (v0 != 4 && v1 != 4) continue;
+        const int need = v0 == 4 ? 1 : 0;  // the value of l that keeps the factor non-zero
+        rows.push_back({f.mask, need ^ (int)f.cst});
+    }
+    int rank = 0;
+    for (size_t r = 0; r < rows.size(); ++r) {
+        uint64_t m = rows[r].first;
+        int rhs = rows[r].second;
+        if (!m) {
+            if (rhs) return 0.0;
+            continue;
+        }
+        const uint64_t piv = m & (~m + 1);
+        for (size_t t = r + 1; t < rows.size(); ++t)
+            if (rows[t].first & piv) {
+                rows[t].first ^= m;
+                rows[t].second ^= rhs;
+            }
+        ++rank;
+    }
+    return std::ldexp(1.0, -rank);
+}
 
 int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err) {
     PackedProgram &P = *out;
@@ -634,6 +667,56 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.off_delta = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), per[i].begin(), per[i].end());
 
+    // inner-block phase vectors (walks of at least kInnerBits positions): for each monomial
+    // with an inner variable, field k of the (even, odd) vector is c * ([inner part set at
+    // step k] - [... at step 0]) mod 8; grouped by what else the monomial needs
+    uint64_t inner_vec[2] = {0, 0};
+    std::vector<uint32_t> c2, c3;
+    if (g >= kInnerBits) {
+        const uint64_t inner_mask = ((uint64_t)1 << kInnerBits) - 1;
+        auto field_add = [](uint64_t a, uint64_t b) { return (a + b) & 0x7777777777777777ull; };
+        for (const auto &m : monos) {
+            const uint64_t I = m.second & inner_mask;
+            if (!I) continue;
+            uint64_t vec[2] = {0, 0};
+            for (int odd = 0; odd < 2; ++odd) {
+                const uint64_t y0 = (uint64_t)odd << (kInnerBits - 1);
+                const int f0 = (I & y0) == I;
+                for (int k = 1; k < kInnerSteps; ++k) {
+                    const uint64_t y = (uint64_t)(k ^ (k >> 1)) ^ y0;
+                    const int f = (I & y) == I;
+                    vec[odd] |= (uint64_t)mod8((long long)m.first * (f - f0)) << (4 * k);
+                }
+            }
+            const uint32_t om = (uint32_t)(m.second & walk_mask & ~inner_mask);
+            const uint64_t hm = m.second >> g;
+            if (!om && !hm) {
+                inner_vec[0] = field_add(inner_vec[0], vec[0]);
+                inner_vec[1] = field_add(inner_vec[1], vec[1]);
+                continue;
+            }
+            std::vector<uint32_t> &dst = om ? c3 : c2;
+            dst.push_back((uint32_t)vec[0]);
+            dst.push_back((uint32_t)(vec[0] >> 32));
+            dst.push_back((uint32_t)vec[1]);
+            dst.push_back((uint32_t)(vec[1] >> 32));
+            if (om) dst.push_back(om);
+            dst.push_back((uint32_t)hm);
+            dst.push_back((uint32_t)(hm >> 32));
+        }
+    }
+    H.off_inner = (uint32_t)img.size();
+    for (int odd = 0; odd < 2; ++odd) {
+        img.push_back((uint32_t)inner_vec[odd]);
+        img.push_back((uint32_t)(inner_vec[odd] >> 32));
+    }
+    H.off_c2 = (uint32_t)img.size();
+    H.n_c2 = (uint32_t)(c2.size() / 6);
+    img.insert(img.end(), c2.begin(), c2.end());
+    H.off_c3 = (uint32_t)img.size();
+    H.n_c3 = (uint32_t)(c3.size() / 7);
+    img.insert(img.end(), c3.begin(), c3.end());
+
     // ---- value table
     const int nd = (int)(dmax - dmin + 1);
     H.d_off = (int32_t)(-dmin);
@@ -677,38 +760,59 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     memcpy(P.blob.data() + tab_off, table.data(), table.size() * 8);
 
     // ---- algorithmic work per term, counted in int32 lane operations from the packed
-    // program: Gray-step XOR of one column (W), each statistic mask (W ANDs, W popcounts,
-    // one multiply-add), the zero test (3W + 1), combining the statistics into the table
-    // index and shift (10), shifting and adding four int128 coefficients (4 x 10), and per
-    // walk step the slice-dependent monomial updates whose walk part holds (5 each, +2),
-    // plus the per-slice set-up spread over the 2^g terms of a slice.
+    // program.  Every term: the Gray-step XOR of one column (W) and the zero test (3W + 1);
+    // with monomials the phase field of the step (2).  Only terms on which no factor vanishes
+    // go on to the statistics: each mask (W ANDs, W popcounts, one add), combining them into the
+    // table index and shift (10) and the accumulation (int64: 14, int128: 42, class counter: 5).
+    // The fraction of such terms is exact: the vanishing conditions are affine in x.  Spread
+    // over the terms: the per-slice set-up and, per block of kInnerSteps terms, the outer flip
+    // (W, and with monomials 4 plus 5 per firing slice-dependent entry, 6 per active block
+    // entry), counted exactly over one walk.
     {
-        double acc_ops = H.acc == ACC_I64 ? 14.0 : H.acc == ACC_I128 ? 42.0 : 5.0;
-        double ops = W + 10 + acc_ops + active_slots * (2.0 * W + 1);
+        const double nz = nonzero_fraction(used, w.nodes);
+        P.nonzero_fraction = nz;
+        const double acc_ops = H.acc == ACC_I64 ? 14.0 : H.acc == ACC_I128 ? 42.0 : 5.0;
+        const bool mono = !w.mono.empty();
+        double ops = W + nz * (10 + acc_ops + active_slots * (2.0 * W + 1));
         if (has_zero) ops += 3.0 * W + 1;
+        if (mono) ops += 2;
         double setup = (double)(w.pe - g) * 2.0 * W + 5.0 * H.n_monohi;
-        double steps = (double)((uint64_t)1 << g);
-        double mono_ops = 0;
-        if (!w.mono.empty() && g > 0) {
-            // exact count over one walk: step t flips position ctz(t) with Gray state gray(t);
-            // per step the packed always-firing field (2) and the sign (2), plus 5 per
-            // state-dependent slice entry that fires; per slice the always-firing fields
-            const uint32_t *didx = img.data() + H.off_didx;
-            const uint32_t *de = img.data() + H.off_delta;
-            for (uint64_t t = 1; t < ((uint64_t)1 << g); ++t) {
-                int i = __builtin_ctzll(t);
-                uint32_t gray = (uint32_t)(t ^ (t >> 1));
-                mono_ops += 4;
-                for (uint32_t e = didx[i]; e < didx[i + 1]; ++e) {
-                    uint32_t wm = de[4 * e + 1];
-                    bool hi = de[4 * e + 2] || de[4 * e + 3];
-                    if ((gray & wm) == wm && hi) mono_ops += 5;
+        const uint64_t steps = (uint64_t)1 << g;
+        double walk = 0;
+        const uint32_t *didx = img.data() + H.off_didx;
+        const uint32_t *de = img.data() + H.off_delta;
+        auto flip_cost = [&](int i, uint32_t gray) {
+            double c = W;
+            if (!mono) return c;
+            c += 4;
+            for (uint32_t e = didx[i]; e < didx[i + 1]; ++e) {
+                const uint32_t wm = de[4 * e + 1];
+                const bool hi = de[4 * e + 2] || de[4 * e + 3];
+                if ((gray & wm) == wm && hi) c += 5;
+            }
+            return c;
+        };
+        if (mono) setup += 5.0 * img[H.off_aidx + g] + 4.0 * g;
+        if (g < kInnerBits) {
+            for (uint64_t t = 1; t < steps; ++t)
+                walk += flip_cost(__builtin_ctzll(t), (uint32_t)(t ^ (t >> 1)));
+        } else {
+            if (mono) setup += 6.0 * H.n_c2 + 4;
+            const uint64_t nb = steps >> kInnerBits;
+            const uint32_t *c3 = img.data() + H.off_c3;
+            for (uint64_t b = 0; b < nb; ++b) {
+                const uint32_t gray = (uint32_t)((b ^ (b >> 1)) << kInnerBits);
+                if (b) walk += flip_cost(kInnerBits + __builtin_ctzll(b), gray);
+                if (!mono) continue;
+                walk += 2;
+                for (uint32_t e = 0; e < H.n_c3; ++e) {
+                    const uint32_t om = c3[7 * e + 4];
+                    walk += 1;
+                    if ((gray & om) == om) walk += 6;
                 }
             }
-            const uint32_t *aidx = img.data() + H.off_aidx;
-            setup += 5.0 * aidx[g] + 4.0 * g;
         }
-        P.ops_per_term = ops + (setup + mono_ops) / steps;
+        P.ops_per_term = ops + (setup + walk) / (double)steps;
     }
 
     P.c0 = w.c0;

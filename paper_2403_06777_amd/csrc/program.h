@@ -56,6 +56,7 @@ struct PackedProgram {
     int n_factors = 0, n_mono = 0, n_forms = 0;
     int W = 1;
     double ops_per_term = 0.0;  // algorithmic int32 lane-ops per term (see pack_program)
+    double nonzero_fraction = 1.0;  // exact fraction of assignments where no factor vanishes
 };
 
 // Returns 0 or a negative SIM_E* code with *err set.  max_walk_bits caps the Gray walk.
