@@ -27,6 +27,10 @@ struct sim_program {
     double compile_seconds = 0.0;
     uint32_t t_count = 0;
     uint32_t n_constraints = 0;
+    // resident blocks per compute unit of its evaluation kernel, for occ_threads threads
+    // (queried once; evaluations hold the device lock)
+    uint32_t occ_threads = 0;
+    int occ_blocks = 0;
 };
 
 namespace {
@@ -164,7 +168,19 @@ int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint
                       hipStream_t stream, const sim_tuning *t, sim_zomega *out, float *kernel_ms = nullptr) {
     const PackedProgram &pk = P->pk;
     const uint32_t threads = pick_threads(t);
-    const uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 8u;
+    // By default the grid is what the chip holds at once (every block resident), so that the
+    // rounds of slices inside the kernel, not a second wave of blocks, balance the work.
+    uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 0u;
+    if (!bpc) {
+        sim_program *Pm = const_cast<sim_program *>(P);
+        if (Pm->occ_threads != threads) {
+            int occ = 0;
+            HIP_TRY(eval_occupancy(pk.hdr, threads, &occ));
+            Pm->occ_blocks = std::max(1, occ);
+            Pm->occ_threads = threads;
+        }
+        bpc = (uint32_t)Pm->occ_blocks;
+    }
     uint64_t want = (count + threads - 1) / threads;
     uint64_t cap = (uint64_t)std::max(1, D.cus) * bpc;
     uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));

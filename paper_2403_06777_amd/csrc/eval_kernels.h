@@ -41,7 +41,7 @@ __device__ __forceinline__ CU32 *const_words(const uint8_t *img) {
 template <int W>
 struct Slots {
     uint32_t m[kSlots][W];
-    uint32_t z0[W], z1[W];
+    uint32_t zm[W];
 };
 
 template <int W, uint32_t SET>
@@ -55,8 +55,7 @@ __device__ __forceinline__ void load_slots(const ImgHeader &H, CU32 *wd, Slots<W
     }
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        S.z0[w] = wd[H.off_z0 + w];
-        S.z1[w] = wd[H.off_z1 + w];
+        S.zm[w] = wd[H.off_zmask + w];
     }
 }
 
@@ -66,9 +65,11 @@ struct TermClass {
     bool zero;
 };
 
-template <int W, uint32_t SET>
-__device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W> &S, CU32 *wd,
-                                              const uint32_t (&L)[W], int phi) {
+// ZERO: test the vanishing bits (a compile-time switch so that the walk of a program without
+// such factors carries no test at all)
+template <int W, uint32_t SET, bool ZERO>
+__device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W> &S, const uint32_t (&L)[W],
+                                              int phi) {
     int st[N_STATS];
 #pragma unroll
     for (int s = 0; s < N_STATS; ++s) st[s] = H.stat_base[s];
@@ -86,10 +87,10 @@ __device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W>
     }
     TermClass t;
     t.zero = false;
-    if (H.has_zero) {
+    if (ZERO) {
         uint32_t z = 0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) z |= (~L[w] & S.z0[w]) | (L[w] & S.z1[w]);
+        for (int w = 0; w < W; ++w) z |= L[w] & S.zm[w];
         t.zero = z != 0u;
     }
     const int A = st[STAT_A], B = st[STAT_B];
@@ -115,10 +116,10 @@ struct Acc {
     }
 };
 
-template <int W, int ACC, uint32_t SET>
-__device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
+template <int W, int ACC, uint32_t SET, bool ZERO>
+__device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, const int64_t *tab,
                                          unsigned long long *cnt, const uint32_t (&L)[W], int phi, Acc<ACC> &acc) {
-    const TermClass t = classify<W, SET>(H, S, wd, L, phi);
+    const TermClass t = classify<W, SET, ZERO>(H, S, L, phi);
     if (ACC == ACC_CLASS) {
         if (!t.zero) {
             // counters are laid out [q][class]: 24-bit multiply-add (full rate)
@@ -143,8 +144,10 @@ __device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, 
     }
 }
 
-// field-wise sum mod 8 of two vectors of 4-bit fields holding values 0..7
+// field-wise sum mod 8 of two vectors of 4-bit fields holding values 0..7, and negation mod 8
+// (8 - x never borrows from the next field)
 __device__ __forceinline__ uint32_t field_add(uint32_t a, uint32_t b) { return (a + b) & 0x77777777u; }
+__device__ __forceinline__ uint32_t field_neg(uint32_t a) { return (0x88888888u - a) & 0x77777777u; }
 
 // phase change (monomials) of flipping walk position i to its new value (bit i of gray).  The
 // walk bits below i are fixed at a flip (bit i-1 set, lower bits clear), so only the entries of
@@ -169,10 +172,247 @@ __device__ __forceinline__ int flip_phase(const ImgHeader &H, CU32 *wd, uint32_t
     return ((gray >> i) & 1u) ? dd : -dd;
 }
 
-// all 2^g assignments of slice s (high parameters = bits of s)
-template <int W, bool MONO, int ACC, uint32_t SET>
+// Queue of surviving terms of one wave (programs whose factors can vanish, W <= 4): an entry
+// is a term's form vector and phase, padded to 4 or 8 words; terms are appended by ballot and
+// prefix count and their statistics evaluated 64 at a time, so that sparse survivors do not
+// leave most lanes of a wave idle.  The count is wave-uniform.
+constexpr uint32_t kQueueCap = 128;  // one append (<= 64) on top of < 64 pending entries
+template <int W>
+constexpr bool kCompact = W <= 4;
+template <int W>
+constexpr int kQueueWords = W + 1 <= 4 ? 4 : 8;
+struct WaveQueue {
+    uint32_t *q;  // this wave's kQueueCap entries in LDS
+    uint32_t n;   // pending entries
+};
+
+// evaluates the last `count` (<= 64) pending entries, one per lane
+template <int W, int ACC, uint32_t SET>
+__device__ __forceinline__ void queue_drain(const ImgHeader &H, const Slots<W> &S, const int64_t *tab,
+                                            unsigned long long *cnt, WaveQueue &Q, uint32_t count,
+                                            Acc<ACC> &acc) {
+    const uint32_t lane = threadIdx.x & 63u;
+    Q.n -= count;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < count) {
+        const uint4 *e = reinterpret_cast<const uint4 *>(Q.q + (Q.n + lane) * kQueueWords<W>);
+        const uint4 e0 = e[0];
+        uint32_t words[8] = {e0.x, e0.y, e0.z, e0.w, 0, 0, 0, 0};
+        if (kQueueWords<W> == 8) {
+            const uint4 e1 = e[1];
+            words[4] = e1.x;
+            words[5] = e1.y;
+            words[6] = e1.z;
+            words[7] = e1.w;
+        }
+        uint32_t L[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) L[w] = words[w];
+        add_term<W, ACC, SET, false>(H, S, tab, cnt, L, (int)words[W], acc);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int W>
+__device__ __forceinline__ bool words_equal(const uint32_t (&a)[W], const uint32_t (&b)[W]) {
+    if (W == 1) return a[0] == b[0];
+    if (W == 2) return (((uint64_t)a[1] << 32) | a[0]) == (((uint64_t)b[1] << 32) | b[0]);
+    uint32_t x = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x |= a[w] ^ b[w];
+    return x == 0u;
+}
+
+// The blocks of a slice: 2^(g - kInnerBits) blocks of kInnerSteps terms.  Between blocks one
+// outer walk position flips (column XOR, phase change from the position's lists); inside a
+// block the flip positions are compile-time constants, the inner columns sit in registers and
+// the phase of each term is read from the block's vector of 4-bit fields.
+// With ZERO and CQ (compacting), lanes whose slice is past the end of the range still walk
+// (valid = false) and never report a surviving term, so the queue is always operated on by
+// the whole wave.
+template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ>
+__device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
+                                            unsigned long long *cnt, uint64_t s, bool valid, uint32_t (&L)[W],
+                                            int phi, uint64_t dal, WaveQueue *Q, Acc<ACC> &acc) {
+    static_assert(kInnerBits == 4, "one 64-bit vector of 4-bit fields per block");
+    CU32 *col = wd + H.off_col;
+    uint32_t ck[kInnerBits][W];
+#pragma unroll
+    for (int j = 0; j < kInnerBits; ++j)
+#pragma unroll
+        for (int w = 0; w < W; ++w) ck[j][w] = col[j * W + w];
+    uint32_t cz[kInnerBits][W];  // the inner columns on the vanishing bits
+#pragma unroll
+    for (int j = 0; j < kInnerBits; ++j)
+#pragma unroll
+        for (int w = 0; w < W; ++w) cz[j][w] = ck[j][w] & S.zm[w];
+    // the inner phase vectors of the current outer state (even and odd blocks)
+    uint32_t v0lo = 0, v0hi = 0, v1lo = 0, v1hi = 0;
+    if (MONO) {
+        CU32 *ci = wd + H.off_inner;
+        v0lo = ci[0];
+        v0hi = ci[1];
+        v1lo = ci[2];
+        v1hi = ci[3];
+        CU32 *e2 = wd + H.off_c2;
+        for (uint32_t e = 0; e < H.n_c2; ++e, e2 += 6) {
+            const uint64_t hm = (uint64_t)e2[4] | ((uint64_t)e2[5] << 32);
+            if ((s & hm) == hm) {
+                v0lo = field_add(v0lo, e2[0]);
+                v0hi = field_add(v0hi, e2[1]);
+                v1lo = field_add(v1lo, e2[2]);
+                v1hi = field_add(v1hi, e2[3]);
+            }
+        }
+    }
+    const uint32_t nb = 1u << (H.g - kInnerBits);
+    uint32_t gray = 0;  // walk bits at or above kInnerBits
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (b) {
+            const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b);
+            gray ^= 1u << i;
+#pragma unroll
+            for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
+            if (MONO) {
+                phi += flip_phase(H, wd, i, gray, dal, s);
+                // inner vectors of the monomials that also need outer bits: those of position i
+                // whose other outer bits are set switch on (bit i now 1) or off
+                CU32 *c3idx = wd + H.off_c3idx;
+                const bool on = (gray >> i) & 1u;
+                CU32 *e3 = wd + H.off_c3 + 7 * c3idx[i];
+                for (uint32_t e = c3idx[i]; e < c3idx[i + 1]; ++e, e3 += 7) {
+                    const uint32_t om = e3[4];
+                    if ((gray & om) != om) continue;
+                    uint32_t p0l = e3[0], p0h = e3[1], p1l = e3[2], p1h = e3[3];
+                    if (!on) {
+                        p0l = field_neg(p0l);
+                        p0h = field_neg(p0h);
+                        p1l = field_neg(p1l);
+                        p1h = field_neg(p1h);
+                    }
+                    const uint64_t hm = (uint64_t)e3[5] | ((uint64_t)e3[6] << 32);
+                    if ((s & hm) == hm) {
+                        v0lo = field_add(v0lo, p0l);
+                        v0hi = field_add(v0hi, p0h);
+                        v1lo = field_add(v1lo, p1l);
+                        v1hi = field_add(v1hi, p1h);
+                    }
+                }
+            }
+        }
+        uint32_t flo = 0, fhi = 0;
+        if (MONO) {
+            const bool odd = b & 1u;
+            flo = odd ? v1lo : v0lo;
+            fhi = odd ? v1hi : v0hi;
+        }
+        if (ZERO) {
+            // Term k of the block has L0 ^ P(gray(k)), P the XOR of the inner columns of the set
+            // bits; it survives iff (L0 & zm) equals the uniform P(gray(k)) & zm.  Pass 1 only
+            // compares (one wave ballot per step); pass 2 runs when some lane of the wave has a
+            // surviving term in the block.
+            uint32_t a[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) a[w] = valid ? L[w] & S.zm[w] : wd[H.off_never + w];
+            uint32_t d[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) d[w] = 0;
+            uint64_t any = 0;
+#pragma unroll
+            for (int k = 0; k < kInnerSteps; ++k) {
+                if (k) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) d[w] ^= cz[__builtin_ctz(k)][w];
+                }
+                any |= __ballot(words_equal<W>(a, d));
+            }
+            if (CQ && any) {
+                // pass 2: append the surviving terms (L0 ^ P(gray(k)), phase) to the queue
+                const uint32_t lane = threadIdx.x & 63u;
+                uint32_t pk[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    pk[w] = 0;
+                    d[w] = 0;
+                }
+#pragma unroll
+                for (int k = 0; k < kInnerSteps; ++k) {
+                    if (k) {
+                        const int j = __builtin_ctz(k);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            pk[w] ^= ck[j][w];
+                            d[w] ^= cz[j][w];
+                        }
+                    }
+                    const bool live = words_equal<W>(a, d);
+                    const uint64_t m = __ballot(live);
+                    if (m) {
+                        if (live) {
+                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                            for (int w = 0; w < W; ++w) words[w] = L[w] ^ pk[w];
+                            const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                            words[W] = (uint32_t)(phi + f);
+                            uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
+                            e[0] = make_uint4(words[0], words[1], words[2], words[3]);
+                            if (kQueueWords<W> == 8) e[1] = make_uint4(words[4], words[5], words[6], words[7]);
+                        }
+                        Q->n += (uint32_t)__popcll(m);
+                        (void)lane;
+                        if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, S, tab, cnt, *Q, 64u, acc);
+                    }
+                }
+            } else if (!CQ && any) {
+                uint32_t Lk[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    Lk[w] = L[w];
+                    d[w] = 0;
+                }
+#pragma unroll
+                for (int k = 0; k < kInnerSteps; ++k) {
+                    if (k) {
+                        const int j = __builtin_ctz(k);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            Lk[w] ^= ck[j][w];
+                            d[w] ^= cz[j][w];
+                        }
+                    }
+                    if (words_equal<W>(a, d)) {
+                        const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                        add_term<W, ACC, SET, false>(H, S, tab, cnt, Lk, phi + f, acc);
+                    }
+                }
+            }
+            // the block's last state: gray(kInnerSteps - 1) has only the top inner bit set
+#pragma unroll
+            for (int w = 0; w < W; ++w) L[w] ^= ck[kInnerBits - 1][w];
+        } else {
+            add_term<W, ACC, SET, false>(H, S, tab, cnt, L, phi, acc);
+#pragma unroll
+            for (int k = 1; k < kInnerSteps; ++k) {
+                const int j = __builtin_ctz(k);
+#pragma unroll
+                for (int w = 0; w < W; ++w) L[w] ^= ck[j][w];
+                const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                add_term<W, ACC, SET, false>(H, S, tab, cnt, L, phi + f, acc);
+            }
+        }
+        if (MONO) phi += (int)(fhi >> 28);  // the block's last state
+    }
+}
+
+// all 2^g assignments of slice s (high parameters = bits of s).  CQ: the compacting walk of a
+// program with vanishing factors and at least kInnerBits walk bits (called by the whole wave,
+// valid marks the lanes with a slice); otherwise every other kind of program.
+template <int W, bool MONO, int ACC, uint32_t SET, bool CQ>
 __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
-                                          unsigned long long *cnt, uint64_t s, Acc<ACC> &acc) {
+                                          unsigned long long *cnt, uint64_t s, bool valid, WaveQueue *Q,
+                                          Acc<ACC> &acc) {
     CU32 *col = wd + H.off_col;
     uint32_t L[W];
 #pragma unroll
@@ -201,80 +441,25 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S,
             dal |= (uint64_t)(f & 7) << (4 * i);
         }
     }
-    if (H.g < (uint32_t)kInnerBits) {
-        // short walks: one step at a time
-        add_term<W, ACC, SET>(H, S, wd, tab, cnt, L, phi, acc);
-        uint32_t gray = 0;
-        for (uint32_t t = 1; t < (1u << H.g); ++t) {
-            const uint32_t i = (uint32_t)__builtin_ctz(t);
-            gray ^= 1u << i;
-#pragma unroll
-            for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
-            if (MONO) phi += flip_phase(H, wd, i, gray, dal, s);
-            add_term<W, ACC, SET>(H, S, wd, tab, cnt, L, phi, acc);
-        }
+    if (CQ) {
+        walk_blocks<W, MONO, ACC, SET, true, true>(H, S, wd, tab, cnt, s, valid, L, phi, dal, Q, acc);
         return;
     }
-    // inner columns and the slice's inner phase vectors (even and odd blocks)
-    uint32_t ck[kInnerBits][W];
-#pragma unroll
-    for (int j = 0; j < kInnerBits; ++j)
-#pragma unroll
-        for (int w = 0; w < W; ++w) ck[j][w] = col[j * W + w];
-    uint32_t v0lo = 0, v0hi = 0, v1lo = 0, v1hi = 0;
-    if (MONO) {
-        CU32 *ci = wd + H.off_inner;
-        v0lo = ci[0];
-        v0hi = ci[1];
-        v1lo = ci[2];
-        v1hi = ci[3];
-        CU32 *e2 = wd + H.off_c2;
-        for (uint32_t e = 0; e < H.n_c2; ++e, e2 += 6) {
-            const uint64_t hm = (uint64_t)e2[4] | ((uint64_t)e2[5] << 32);
-            if ((s & hm) == hm) {
-                v0lo = field_add(v0lo, e2[0]);
-                v0hi = field_add(v0hi, e2[1]);
-                v1lo = field_add(v1lo, e2[2]);
-                v1hi = field_add(v1hi, e2[3]);
-            }
-        }
+    if (H.g >= (uint32_t)kInnerBits) {
+        if (!H.has_zero) walk_blocks<W, MONO, ACC, SET, false, false>(H, S, wd, tab, cnt, s, true, L, phi, dal, Q, acc);
+        else if (!kCompact<W>) walk_blocks<W, MONO, ACC, SET, true, false>(H, S, wd, tab, cnt, s, true, L, phi, dal, Q, acc);
+        return;
     }
-    const uint32_t nb = 1u << (H.g - kInnerBits);
-    uint32_t gray = 0;  // walk bits at or above kInnerBits
-    for (uint32_t b = 0; b < nb; ++b) {
-        if (b) {
-            const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b);
-            gray ^= 1u << i;
+    // short walks: one step at a time
+    add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi, acc);
+    uint32_t gray = 0;
+    for (uint32_t t = 1; t < (1u << H.g); ++t) {
+        const uint32_t i = (uint32_t)__builtin_ctz(t);
+        gray ^= 1u << i;
 #pragma unroll
-            for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
-            if (MONO) phi += flip_phase(H, wd, i, gray, dal, s);
-        }
-        uint32_t flo = 0, fhi = 0;
-        if (MONO) {
-            const uint32_t odd = b & 1u;
-            flo = odd ? v1lo : v0lo;
-            fhi = odd ? v1hi : v0hi;
-            CU32 *e3 = wd + H.off_c3;
-            for (uint32_t e = 0; e < H.n_c3; ++e, e3 += 7) {
-                const uint32_t om = e3[4];
-                if ((gray & om) != om) continue;
-                const uint64_t hm = (uint64_t)e3[5] | ((uint64_t)e3[6] << 32);
-                if ((s & hm) == hm) {
-                    flo = field_add(flo, e3[2 * odd]);
-                    fhi = field_add(fhi, e3[2 * odd + 1]);
-                }
-            }
-        }
-        add_term<W, ACC, SET>(H, S, wd, tab, cnt, L, phi, acc);
-#pragma unroll
-        for (int k = 1; k < kInnerSteps; ++k) {
-            const int j = __builtin_ctz(k);
-#pragma unroll
-            for (int w = 0; w < W; ++w) L[w] ^= ck[j][w];
-            const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
-            add_term<W, ACC, SET>(H, S, wd, tab, cnt, L, phi + f, acc);
-        }
-        if (MONO) phi += (int)(fhi >> 28);  // the block's last state
+        for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
+        if (MONO) phi += flip_phase(H, wd, i, gray, dal, s);
+        add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi, acc);
     }
 }
 
@@ -368,22 +553,27 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
 template <int W, bool MONO, int ACC, uint32_t SET>
 __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img, uint64_t s_first, uint64_t s_count,
                                           uint64_t lane0, uint64_t stride, uint32_t flush_rounds, int64_t *s_tab,
-                                          unsigned long long *s_cnt, i128 (&out)[4]) {
+                                          unsigned long long *s_cnt, uint32_t *s_queue, i128 (&out)[4]) {
     CU32 *wd = const_words(img);
     const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
     Slots<W> S;
     load_slots<W, SET>(H, wd, S);
     Acc<ACC> acc;
     acc.clear();
+    WaveQueue Q{s_queue + (threadIdx.x >> 6) * kQueueCap * kQueueWords<W>, 0u};
+    const bool compact = kCompact<W> && H.has_zero && H.g >= (uint32_t)kInnerBits;
     uint32_t rounds = 0;
     for (uint64_t base = lane0 - threadIdx.x; base < s_count; base += stride) {
         const uint64_t s = base + threadIdx.x;
-        if (s < s_count) run_slice<W, MONO, ACC, SET>(H, S, wd, s_tab, s_cnt, s_first + s, acc);
+        const bool valid = s < s_count;
+        if (compact) run_slice<W, MONO, ACC, SET, true>(H, S, wd, s_tab, s_cnt, s_first + (valid ? s : 0), valid, &Q, acc);
+        else if (valid) run_slice<W, MONO, ACC, SET, false>(H, S, wd, s_tab, s_cnt, s_first + s, true, &Q, acc);
         if (ACC == ACC_CLASS && ++rounds == flush_rounds) {
             flush_counters<ACC>(H, gtab, s_cnt, out);
             rounds = 0;
         }
     }
+    if (compact && Q.n) queue_drain<W, ACC, SET>(H, S, s_tab, s_cnt, Q, Q.n, acc);
     if (ACC == ACC_CLASS) flush_counters<ACC>(H, gtab, s_cnt, out);
     acc_to_i128<ACC>(acc, out);
 }
@@ -393,12 +583,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t
                                                       uint64_t s_begin, uint64_t s_count, uint32_t flush_rounds,
                                                       Partial *__restrict__ partials) {
     extern __shared__ int64_t s_dyn[];
+    __shared__ uint4 s_queue[kCompact<W> ? kMaxThreads / 64 * kQueueCap * kQueueWords<W> / 4 : 1];
     const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
     prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
     i128 out[4] = {0, 0, 0, 0};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     run_range<W, MONO, ACC, SET>(H, img, s_begin, s_count, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride,
-                            flush_rounds, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn), out);
+                                 flush_rounds, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
+                                 reinterpret_cast<uint32_t *>(s_queue), out);
     block_reduce_store(out, partials + blockIdx.x);
 }
 
@@ -409,6 +601,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__r
                                                             uint32_t *__restrict__ queue, uint32_t flush_rounds,
                                                             Partial *__restrict__ partials) {
     extern __shared__ int64_t s_dyn[];
+    __shared__ uint4 s_queue[kCompact<W> ? kMaxThreads / 64 * kQueueCap * kQueueWords<W> / 4 : 1];
     __shared__ uint32_t s_item;
     uint32_t loaded = 0xffffffffu;
     for (;;) {
@@ -428,7 +621,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__r
         }
         i128 out[4] = {0, 0, 0, 0};
         run_range<W, MONO, ACC, SET>(H, img, wi.s_begin, wi.s_end - wi.s_begin, threadIdx.x, blockDim.x, flush_rounds,
-                                s_dyn, reinterpret_cast<unsigned long long *>(s_dyn), out);
+                                     s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
+                                     reinterpret_cast<uint32_t *>(s_queue), out);
         block_reduce_store(out, partials + wi.out_slot);
     }
 }
@@ -499,6 +693,22 @@ hipError_t launch_eval_w(const ImgHeader &H, const void *dimg, uint64_t s_begin,
 #undef CALL_EVAL
 }
 
+template <int W, bool MONO, int ACC, uint32_t SET>
+hipError_t occupancy_t(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {
+    const size_t lds = dyn_lds_bytes(H);
+    auto kern = k_eval<W, MONO, ACC, SET>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, (int)threads, lds);
+}
+
+template <int W>
+hipError_t occupancy_w(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {
+#define CALL_OCC(w, m, a, set) occupancy_t<w, m, a, set>(H, threads, blocks_per_cu)
+    DISPATCH_W(W, H.has_mono != 0, H.acc, H.slot_menu, CALL_OCC);
+#undef CALL_OCC
+}
+
 template <int W>
 hipError_t launch_batch_w(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
                           const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
@@ -511,6 +721,7 @@ hipError_t launch_batch_w(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
 }
 
 #define INSTANTIATE_EVAL_W(w)                                                                          \
+    template hipError_t occupancy_w<w>(const ImgHeader &, uint32_t, int *);                            \
     template hipError_t launch_eval_w<w>(const ImgHeader &, const void *, uint64_t, uint64_t, Partial *, \
                                          uint32_t, uint32_t, hipStream_t);                             \
     template hipError_t launch_batch_w<w>(const ImgHeader &, const ImgHeader *, const uint64_t *,      \

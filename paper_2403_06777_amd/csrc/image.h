@@ -63,9 +63,10 @@ struct ImgHeader {
     uint32_t slot_menu; // index into the slot-set menu (0 all, 1 node factors, 2 phase only)
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j
-    uint32_t off_cvec;  // W words: constant bits of the forms
-    uint32_t off_z0;    // W words: forms whose factor vanishes when the form is 0
-    uint32_t off_z1;    // W words: ... when the form is 1
+    uint32_t off_cvec;  // W words: L at the all-zero assignment
+    uint32_t off_zmask; // W words: bits of factors that can vanish; such a bit of L is 1 exactly
+                        // where its factor vanishes (the form, complemented if that is at l = 0)
+    uint32_t off_never; // W words: a value of L & zmask that no block's surviving terms have
     uint32_t off_slots; // kSlots entries of (W + 1) words: weight (0 = unused), mask[W]
     int32_t stat_base[N_STATS];
     uint32_t off_monohi;  // monomials over high positions only: c, mask_lo, mask_hi (slice bits)
@@ -87,8 +88,10 @@ struct ImgHeader {
     uint32_t off_inner;   // 4 words: sum over monomials whose other variables are all inner
     uint32_t off_c2;      // n_c2 entries, 6 words: even lo, hi, odd lo, hi, slice mask lo, hi
     uint32_t n_c2;        //   (other variables: slice bits only)
-    uint32_t off_c3;      // n_c3 entries, 7 words: even lo, hi, odd lo, hi, outer walk mask,
-    uint32_t n_c3;        //   slice mask lo, hi (some other variable is an outer walk bit)
+    uint32_t off_c3idx;   // g + 1 words: entries of outer walk position i (some other variable
+    uint32_t off_c3;      //   is an outer walk bit) are [c3idx[i], c3idx[i+1]) at off_c3, 7 words
+    uint32_t n_c3;        //   each: even lo, hi, odd lo, hi, its other outer walk bits, slice mask
+                          //   lo, hi; at a flip of i with the other bits set it toggles on or off
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
     uint32_t table_n;         // entries (value classes + one zero entry)
     int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e

@@ -56,7 +56,12 @@ hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item
                                  const uint32_t *d_item_count, const FinalArgs *d_args, uint32_t n_progs,
                                  DevResult *d_out, hipStream_t stream);
 
+// resident blocks per compute unit of the single-program evaluation kernel of H
+hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
+
 // per-width evaluation launches, instantiated in eval_w<W>.hip (W = 1, 2, 4, 8, 16)
+template <int W>
+hipError_t occupancy_w(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
 template <int W>
 hipError_t launch_eval_w(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);

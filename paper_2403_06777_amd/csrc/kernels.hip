@@ -85,6 +85,17 @@ uint32_t flush_rounds_for(const ImgHeader &H, uint32_t threads) {
     return (uint32_t)(r < 1 ? 1 : (r > 0xffffffffu ? 0xffffffffu : r));
 }
 
+hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {
+    switch (H.W) {
+        case 1: return occupancy_w<1>(H, threads, blocks_per_cu);
+        case 2: return occupancy_w<2>(H, threads, blocks_per_cu);
+        case 4: return occupancy_w<4>(H, threads, blocks_per_cu);
+        case 8: return occupancy_w<8>(H, threads, blocks_per_cu);
+        case 16: return occupancy_w<16>(H, threads, blocks_per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                        Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)

@@ -406,10 +406,11 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     for (const auto &m : w.mono)
         for (int v : m.first) inc[v - q]++;
     // Walk length: a slice costs a set-up (its high parameters into L, and with variable
-    // monomials a full evaluation of phi) that the 2^g walk steps amortise.  Without variable
-    // monomials the set-up is a few XORs per high parameter, so short walks (fine slices,
-    // more lanes for the same work) cost nothing; with monomials a longer walk pays off.
-    const int want = w.mono.empty() ? 6 : 12;
+    // monomials a full evaluation of phi) that the 2^g walk steps amortise, while the slices
+    // are also the unit that balances the work over the lanes of the chip (a large program
+    // wants many slices per resident wave so that the last round is nearly full).  Without
+    // variable monomials the set-up is a few XORs per high parameter.
+    const int want = w.mono.empty() ? 8 : 10;
     int g_orig = std::min(p, std::min(max_walk_bits, want));
     if (!w.mono.empty()) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
     if (p - g_orig > 62) g_orig = p - 62;
@@ -503,7 +504,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     std::vector<long long> wt[N_STATS];
     for (int s = 0; s < N_STATS; ++s) wt[s].assign(F, 0);
     long long base[N_STATS] = {0, 0, 0, 0};
-    std::vector<uint32_t> z0(W, 0), z1(W, 0);
+    std::vector<uint32_t> zmask(W, 0), zflip(W, 0);
     bool has_zero = false;
     typedef int (*ClsFn)(int);
     ClsFn fns[N_STATS] = {cls_A, cls_B, cls_E, cls_R};
@@ -514,16 +515,25 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             base[s] += fns[s](v0);
             wt[s][f] += fns[s](v1) - fns[s](v0);
         }
-        if (v0 == 4) {
-            z0[f / 32] |= 1u << (f % 32);
-            has_zero = true;
-        }
-        if (v1 == 4) {
-            z1[f / 32] |= 1u << (f % 32);
-            has_zero = true;
-        }
     }
     for (const auto &l : w.lin) wt[STAT_R][l.second] += l.first;
+    // Factors that can vanish (one value of their form gives 1 + w^4 = 0): on every term that
+    // survives, their form takes the other value, so the statistic weights of their bit (the
+    // factor's own, and those of linear terms sharing the bit) are constants folded into the
+    // base.  Their bit of L is kept as "the factor vanishes" (the constant vector is
+    // complemented where that happens at l = 0), so a term is zero iff L & zmask != 0.
+    for (const auto &n : w.nodes) {
+        const int f = n.first, v0 = n.second.first, v1 = n.second.second;
+        if (v0 != 4 && v1 != 4) continue;
+        const int keep = v0 == 4 ? 1 : 0;  // value of the form on surviving terms
+        zmask[f / 32] |= 1u << (f % 32);
+        if (v0 == 4) zflip[f / 32] |= 1u << (f % 32);
+        has_zero = true;
+        for (int s = 0; s < N_STATS; ++s) {
+            base[s] += wt[s][f] * keep;
+            wt[s][f] = 0;
+        }
+    }
     for (int f = 0; f < F; ++f) {
         if (wt[STAT_A][f] > 0) amax += wt[STAT_A][f]; else amin += wt[STAT_A][f];
         if (wt[STAT_B][f] > 0) bmax += wt[STAT_B][f]; else bmin += wt[STAT_B][f];
@@ -564,12 +574,43 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         std::vector<uint32_t> cv(W, 0);
         for (int f = 0; f < F; ++f)
             if (used[f].cst) cv[f / 32] |= 1u << (f % 32);
+        for (int k = 0; k < W; ++k) cv[k] ^= zflip[k];
         img.insert(img.end(), cv.begin(), cv.end());
     }
-    H.off_z0 = (uint32_t)img.size();
-    img.insert(img.end(), z0.begin(), z0.end());
-    H.off_z1 = (uint32_t)img.size();
-    img.insert(img.end(), z1.begin(), z1.end());
+    H.off_zmask = (uint32_t)img.size();
+    img.insert(img.end(), zmask.begin(), zmask.end());
+    // a pattern no block can match: the masked start vector of a surviving term is one of the
+    // 16 combinations of the inner columns on the vanishing bits, all inside zmask
+    H.off_never = (uint32_t)img.size();
+    {
+        std::vector<uint32_t> nv(W, 0);
+        bool outside = false;
+        for (int k = 0; k < W; ++k) {
+            nv[k] = ~zmask[k];
+            outside = outside || nv[k] != 0;
+        }
+        if (!outside && g >= kInnerBits) {
+            std::vector<std::vector<uint32_t>> combos;
+            for (int y = 0; y < (1 << kInnerBits); ++y) {
+                std::vector<uint32_t> c(W, 0);
+                for (int j = 0; j < kInnerBits; ++j)
+                    if (y >> j & 1)
+                        for (int f = 0; f < F; ++f)
+                            if (used[f].mask >> j & 1) c[f / 32] ^= 1u << (f % 32);
+                for (int k = 0; k < W; ++k) c[k] &= zmask[k];
+                combos.push_back(c);
+            }
+            for (uint32_t cand = 1;; ++cand) {
+                std::vector<uint32_t> c(W, 0);
+                c[0] = cand;
+                if (std::find(combos.begin(), combos.end(), c) == combos.end()) {
+                    nv = c;
+                    break;
+                }
+            }
+        }
+        img.insert(img.end(), nv.begin(), nv.end());
+    }
     H.off_slots = (uint32_t)img.size();
     for (int s = 0; s < N_STATS; ++s)
         H.stat_base[s] = (int32_t)(s == STAT_R ? mod8(base[s]) : base[s]);
@@ -671,7 +712,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // with an inner variable, field k of the (even, odd) vector is c * ([inner part set at
     // step k] - [... at step 0]) mod 8; grouped by what else the monomial needs
     uint64_t inner_vec[2] = {0, 0};
-    std::vector<uint32_t> c2, c3;
+    std::vector<uint32_t> c2;
+    std::vector<std::vector<uint32_t>> c3pos(g);  // per outer walk position
     if (g >= kInnerBits) {
         const uint64_t inner_mask = ((uint64_t)1 << kInnerBits) - 1;
         auto field_add = [](uint64_t a, uint64_t b) { return (a + b) & 0x7777777777777777ull; };
@@ -695,14 +737,32 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 inner_vec[1] = field_add(inner_vec[1], vec[1]);
                 continue;
             }
-            std::vector<uint32_t> &dst = om ? c3 : c2;
-            dst.push_back((uint32_t)vec[0]);
-            dst.push_back((uint32_t)(vec[0] >> 32));
-            dst.push_back((uint32_t)vec[1]);
-            dst.push_back((uint32_t)(vec[1] >> 32));
-            if (om) dst.push_back(om);
-            dst.push_back((uint32_t)hm);
-            dst.push_back((uint32_t)(hm >> 32));
+            if (!om) {
+                c2.push_back((uint32_t)vec[0]);
+                c2.push_back((uint32_t)(vec[0] >> 32));
+                c2.push_back((uint32_t)vec[1]);
+                c2.push_back((uint32_t)(vec[1] >> 32));
+                c2.push_back((uint32_t)hm);
+                c2.push_back((uint32_t)(hm >> 32));
+                continue;
+            }
+            // needs outer walk bits: its activation toggles when one of them flips while the
+            // others are set; at a flip of outer position i the outer bits below i - 1 are clear
+            for (int i = kInnerBits; i < g; ++i) {
+                if (!(om >> i & 1)) continue;
+                const uint32_t other = om & ~(1u << i);
+                const uint32_t clear_below =
+                    i - 1 > kInnerBits ? ((1u << (i - 1)) - 1) & ~((1u << kInnerBits) - 1) : 0u;
+                if (other & clear_below) continue;
+                std::vector<uint32_t> &dst = c3pos[i];
+                dst.push_back((uint32_t)vec[0]);
+                dst.push_back((uint32_t)(vec[0] >> 32));
+                dst.push_back((uint32_t)vec[1]);
+                dst.push_back((uint32_t)(vec[1] >> 32));
+                dst.push_back(other);
+                dst.push_back((uint32_t)hm);
+                dst.push_back((uint32_t)(hm >> 32));
+            }
         }
     }
     H.off_inner = (uint32_t)img.size();
@@ -713,9 +773,17 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.off_c2 = (uint32_t)img.size();
     H.n_c2 = (uint32_t)(c2.size() / 6);
     img.insert(img.end(), c2.begin(), c2.end());
+    H.off_c3idx = (uint32_t)img.size();
+    {
+        uint32_t n = 0;
+        for (int i = 0; i <= g; ++i) {
+            img.push_back(n);
+            if (i < g) n += (uint32_t)(c3pos[i].size() / 7);
+        }
+        H.n_c3 = n;
+    }
     H.off_c3 = (uint32_t)img.size();
-    H.n_c3 = (uint32_t)(c3.size() / 7);
-    img.insert(img.end(), c3.begin(), c3.end());
+    for (int i = 0; i < g; ++i) img.insert(img.end(), c3pos[i].begin(), c3pos[i].end());
 
     // ---- value table
     const int nd = (int)(dmax - dmin + 1);
@@ -759,32 +827,43 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     if (!img.empty()) memcpy(P.blob.data(), img.data(), word_bytes);
     memcpy(P.blob.data() + tab_off, table.data(), table.size() * 8);
 
-    // ---- algorithmic work per term, counted in int32 lane operations from the packed
-    // program.  Every term: the Gray-step XOR of one column (W) and the zero test (3W + 1);
-    // with monomials the phase field of the step (2).  Only terms on which no factor vanishes
-    // go on to the statistics: each mask (W ANDs, W popcounts, one add), combining them into the
-    // table index and shift (10) and the accumulation (int64: 14, int128: 42, class counter: 5).
-    // The fraction of such terms is exact: the vanishing conditions are affine in x.  Spread
-    // over the terms: the per-slice set-up and, per block of kInnerSteps terms, the outer flip
-    // (W, and with monomials 4 plus 5 per firing slice-dependent entry, 6 per active block
-    // entry), counted exactly over one walk.
+    // ---- algorithmic work per term, in int32 lane (vector) operations counted from the packed
+    // program; work on wave-uniform values (list walking, program constants) runs on the
+    // scalar unit and is not counted.  The statistics of a term, needed only where no factor
+    // vanishes (an exact fraction: the vanishing conditions are affine in x): per mask W ANDs,
+    // W popcounts and one add, the table index and shift (10), the accumulation (int64 14,
+    // int128 42, class counter 5) and with monomials the term's phase field (2).
+    //  * walks of at least kInnerBits positions: with factors that can vanish, each term's
+    //    vanishing test (a W-word compare) and for a surviving term the rebuild of its form
+    //    vector (W); otherwise each term's column XOR (W).  Per block: the outer column XOR (W),
+    //    with vanishing factors the masked start vector and the end XOR (2W), with monomials
+    //    the vector-pair selection (2), the flip's own change (5), 5 per firing slice-dependent
+    //    flip entry and 12 per toggling inner-vector entry (slice test, four field adds);
+    //  * shorter walks: per term the column XOR (W), the vanishing test (2W) and the flip
+    //    (5 plus 5 per firing slice-dependent entry);
+    //  * per slice: the high parameters into L (2W each), 5 per slice-dependent monomial entry,
+    //    4 per walk position for the packed always-firing fields, 12 per inner-vector entry.
     {
         const double nz = nonzero_fraction(used, w.nodes);
         P.nonzero_fraction = nz;
         const double acc_ops = H.acc == ACC_I64 ? 14.0 : H.acc == ACC_I128 ? 42.0 : 5.0;
         const bool mono = !w.mono.empty();
-        double ops = W + nz * (10 + acc_ops + active_slots * (2.0 * W + 1));
-        if (has_zero) ops += 3.0 * W + 1;
-        if (mono) ops += 2;
-        double setup = (double)(w.pe - g) * 2.0 * W + 5.0 * H.n_monohi;
+        const bool blocks = g >= kInnerBits;
+        const double stats = 10 + acc_ops + active_slots * (2.0 * W + 1) + (mono ? 2 : 0);
+        double ops;
+        if (blocks && has_zero) ops = W + nz * (W + stats);
+        else if (blocks) ops = W + stats;
+        else ops = W + (has_zero ? 2.0 * W : 0) + nz * stats;
+        double setup = (double)(w.pe - g) * 2.0 * W;
+        if (mono) setup += 5.0 * H.n_monohi + 5.0 * img[H.off_aidx + g] + 4.0 * g + (blocks ? 12.0 * H.n_c2 : 0);
         const uint64_t steps = (uint64_t)1 << g;
         double walk = 0;
         const uint32_t *didx = img.data() + H.off_didx;
         const uint32_t *de = img.data() + H.off_delta;
         auto flip_cost = [&](int i, uint32_t gray) {
-            double c = W;
+            double c = 0;
             if (!mono) return c;
-            c += 4;
+            c += 5;
             for (uint32_t e = didx[i]; e < didx[i + 1]; ++e) {
                 const uint32_t wm = de[4 * e + 1];
                 const bool hi = de[4 * e + 2] || de[4 * e + 3];
@@ -792,23 +871,22 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             }
             return c;
         };
-        if (mono) setup += 5.0 * img[H.off_aidx + g] + 4.0 * g;
-        if (g < kInnerBits) {
+        if (!blocks) {
             for (uint64_t t = 1; t < steps; ++t)
                 walk += flip_cost(__builtin_ctzll(t), (uint32_t)(t ^ (t >> 1)));
         } else {
-            if (mono) setup += 6.0 * H.n_c2 + 4;
             const uint64_t nb = steps >> kInnerBits;
+            const uint32_t *c3idx = img.data() + H.off_c3idx;
             const uint32_t *c3 = img.data() + H.off_c3;
-            for (uint64_t b = 0; b < nb; ++b) {
+            walk += (double)nb * ((has_zero ? 2.0 * W : 0) + (mono ? 2 : 0));
+            for (uint64_t b = 1; b < nb; ++b) {
+                const int i = kInnerBits + __builtin_ctzll(b);
                 const uint32_t gray = (uint32_t)((b ^ (b >> 1)) << kInnerBits);
-                if (b) walk += flip_cost(kInnerBits + __builtin_ctzll(b), gray);
+                walk += W + flip_cost(i, gray);
                 if (!mono) continue;
-                walk += 2;
-                for (uint32_t e = 0; e < H.n_c3; ++e) {
-                    const uint32_t om = c3[7 * e + 4];
-                    walk += 1;
-                    if ((gray & om) == om) walk += 6;
+                for (uint32_t e = c3idx[i]; e < c3idx[i + 1]; ++e) {
+                    const uint32_t other = c3[7 * e + 4];
+                    if ((gray & other) == other) walk += 12;
                 }
             }
         }
