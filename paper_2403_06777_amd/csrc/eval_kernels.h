@@ -37,7 +37,16 @@ __device__ __forceinline__ CU32 *const_words(const uint8_t *img) {
     return (CU32 *)(uintptr_t)img;
 }
 
-// the per-program statistic and zero masks, read once and kept in scalar registers
+// A zero the compiler cannot see through: image reads offset by it are not hoisted out of
+// loops, so masks needed only on a rare path are read there instead of occupying scalar
+// registers for the whole walk.
+__device__ __forceinline__ uint32_t opaque_zero() {
+    uint32_t z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
+// the per-program statistic and zero masks, kept in scalar registers
 template <int W>
 struct Slots {
     uint32_t m[kSlots][W];
@@ -188,9 +197,11 @@ struct WaveQueue {
 
 // evaluates the last `count` (<= 64) pending entries, one per lane
 template <int W, int ACC, uint32_t SET>
-__device__ __forceinline__ void queue_drain(const ImgHeader &H, const Slots<W> &S, const int64_t *tab,
+__device__ __forceinline__ void queue_drain(const ImgHeader &H, CU32 *wd, const int64_t *tab,
                                             unsigned long long *cnt, WaveQueue &Q, uint32_t count,
                                             Acc<ACC> &acc) {
+    Slots<W> S;
+    load_slots<W, SET>(H, wd + opaque_zero(), S);
     const uint32_t lane = threadIdx.x & 63u;
     Q.n -= count;
     __builtin_amdgcn_wave_barrier();
@@ -230,10 +241,12 @@ __device__ __forceinline__ bool words_equal(const uint32_t (&a)[W], const uint32
 // With ZERO and CQ (compacting), lanes whose slice is past the end of the range still walk
 // (valid = false) and never report a surviving term, so the queue is always operated on by
 // the whole wave.
+// Blocks [b0, b1) of the slice are walked; L and phi hold the state of block b0's first term.
 template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ>
 __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
-                                            unsigned long long *cnt, uint64_t s, bool valid, uint32_t (&L)[W],
-                                            int phi, uint64_t dal, WaveQueue *Q, Acc<ACC> &acc) {
+                                            unsigned long long *cnt, uint64_t s, bool valid, uint32_t b0,
+                                            uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, WaveQueue *Q,
+                                            Acc<ACC> &acc) {
     static_assert(kInnerBits == 4, "one 64-bit vector of 4-bit fields per block");
     CU32 *col = wd + H.off_col;
     uint32_t ck[kInnerBits][W];
@@ -246,6 +259,14 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     for (int j = 0; j < kInnerBits; ++j)
 #pragma unroll
         for (int w = 0; w < W; ++w) cz[j][w] = ck[j][w] & S.zm[w];
+    // per lane: the masked start vector of a block is (L & zmv) | nvv, the never-matching
+    // pattern on lanes without a slice
+    uint32_t zmv[W], nvv[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        zmv[w] = valid ? S.zm[w] : 0u;
+        nvv[w] = valid ? 0u : wd[H.off_never + w];
+    }
     // the inner phase vectors of the current outer state (even and odd blocks)
     uint32_t v0lo = 0, v0hi = 0, v1lo = 0, v1hi = 0;
     if (MONO) {
@@ -265,10 +286,24 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             }
         }
     }
-    const uint32_t nb = 1u << (H.g - kInnerBits);
-    uint32_t gray = 0;  // walk bits at or above kInnerBits
-    for (uint32_t b = 0; b < nb; ++b) {
-        if (b) {
+    uint32_t gray = (b0 ^ (b0 >> 1)) << kInnerBits;  // walk bits at or above kInnerBits
+    if (MONO && b0) {
+        // inner-and-outer monomials already switched on at the start state
+        CU32 *e3 = wd + H.off_c3all;
+        for (uint32_t e = 0; e < H.n_c3all; ++e, e3 += 7) {
+            const uint32_t om = e3[4];
+            if ((gray & om) != om) continue;
+            const uint64_t hm = (uint64_t)e3[5] | ((uint64_t)e3[6] << 32);
+            if ((s & hm) == hm) {
+                v0lo = field_add(v0lo, e3[0]);
+                v0hi = field_add(v0hi, e3[1]);
+                v1lo = field_add(v1lo, e3[2]);
+                v1hi = field_add(v1hi, e3[3]);
+            }
+        }
+    }
+    for (uint32_t b = b0; b < b1; ++b) {
+        if (b != b0) {
             const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b);
             gray ^= 1u << i;
 #pragma unroll
@@ -306,17 +341,81 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             flo = odd ? v1lo : v0lo;
             fhi = odd ? v1hi : v0hi;
         }
-        if (ZERO) {
+        if (ZERO && CQ) {
             // Term k of the block has L0 ^ P(gray(k)), P the XOR of the inner columns of the set
-            // bits; it survives iff (L0 & zm) equals the uniform P(gray(k)) & zm.  Pass 1 only
-            // compares (one wave ballot per step); pass 2 runs when some lane of the wave has a
-            // surviving term in the block.
+            // bits, and survives iff a = (L0 & zm) equals P(gray(k)) & zm.  The coordinates of a
+            // in the reduced basis of those vectors are its pivot bits; a is in their span iff
+            // removing the picked basis vectors leaves zero, and then y = gray(k) of one
+            // surviving step follows from the basis vectors' inner-column combinations (the
+            // others are y ^ the null-space combinations).
+            uint32_t a[W], x[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                a[w] = (L[w] & zmv[w]) | nvv[w];
+                x[w] = a[w];
+            }
+            uint32_t y = 0;
+            CU32 *bs = wd + H.off_ibasis;
+#pragma unroll
+            for (int i = 0; i < kInnerBits; ++i) {
+                if ((uint32_t)i >= H.inner_rank) break;
+                CU32 *e = bs + i * (3 + W);
+                const uint32_t pw = e[0], pb = e[1], cm = e[2];
+                uint32_t aw = a[0];
+#pragma unroll
+                for (int w = 1; w < W; ++w) aw = pw == (uint32_t)w ? a[w] : aw;
+                const uint32_t m = 0u - ((aw >> pb) & 1u);
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] ^= e[3 + w] & m;
+                y ^= cm & m;
+            }
+            uint32_t zero[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) zero[w] = 0;
+            const bool hit = words_equal<W>(x, zero);
+            const uint64_t m = __ballot(hit);
+            if (m) {
+                // pass 2: append each lane's surviving terms (L0 ^ P(gray(k)), phase) to the queue
+                const uint32_t below =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const uint32_t n_kern = kInnerBits - H.inner_rank;
+                CU32 *kn = wd + H.off_ikern;
+                for (uint32_t z = 0; z < (1u << n_kern); ++z) {
+                    uint32_t yz = y;
+                    for (uint32_t t = 0; t < n_kern; ++t)
+                        if ((z >> t) & 1u) yz ^= kn[t];
+                    if (hit) {
+                        const uint32_t k = yz ^ (yz >> 1) ^ (yz >> 2) ^ (yz >> 3);  // gray(k) = yz
+                        uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                        for (int w = 0; w < W; ++w) words[w] = L[w];
+#pragma unroll
+                        for (int j = 0; j < kInnerBits; ++j) {
+                            const uint32_t mj = 0u - ((yz >> j) & 1u);
+#pragma unroll
+                            for (int w = 0; w < W; ++w) words[w] ^= ck[j][w] & mj;
+                        }
+                        const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                        words[W] = (uint32_t)(phi + f);
+                        uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
+                        e[0] = make_uint4(words[0], words[1], words[2], words[3]);
+                        if (kQueueWords<W> == 8) e[1] = make_uint4(words[4], words[5], words[6], words[7]);
+                    }
+                    Q->n += (uint32_t)__popcll(m);
+                    if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, wd, tab, cnt, *Q, 64u, acc);
+                }
+            }
+            // the block's last state: gray(kInnerSteps - 1) has only the top inner bit set
+#pragma unroll
+            for (int w = 0; w < W; ++w) L[w] ^= ck[kInnerBits - 1][w];
+        } else if (ZERO) {
+            // wide form vectors: compare with each step's value, evaluate the survivors in place
             uint32_t a[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) a[w] = valid ? L[w] & S.zm[w] : wd[H.off_never + w];
+            for (int w = 0; w < W; ++w) a[w] = (L[w] & zmv[w]) | nvv[w];
             uint32_t d[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) d[w] = 0;
+            for (int w = 0; w < W; ++w) d[w] = opaque_zero();
             uint64_t any = 0;
 #pragma unroll
             for (int k = 0; k < kInnerSteps; ++k) {
@@ -326,46 +425,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                 }
                 any |= __ballot(words_equal<W>(a, d));
             }
-            if (CQ && any) {
-                // pass 2: append the surviving terms (L0 ^ P(gray(k)), phase) to the queue
-                const uint32_t lane = threadIdx.x & 63u;
-                uint32_t pk[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    pk[w] = 0;
-                    d[w] = 0;
-                }
-#pragma unroll
-                for (int k = 0; k < kInnerSteps; ++k) {
-                    if (k) {
-                        const int j = __builtin_ctz(k);
-#pragma unroll
-                        for (int w = 0; w < W; ++w) {
-                            pk[w] ^= ck[j][w];
-                            d[w] ^= cz[j][w];
-                        }
-                    }
-                    const bool live = words_equal<W>(a, d);
-                    const uint64_t m = __ballot(live);
-                    if (m) {
-                        if (live) {
-                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-                            for (int w = 0; w < W; ++w) words[w] = L[w] ^ pk[w];
-                            const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
-                            words[W] = (uint32_t)(phi + f);
-                            uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
-                            e[0] = make_uint4(words[0], words[1], words[2], words[3]);
-                            if (kQueueWords<W> == 8) e[1] = make_uint4(words[4], words[5], words[6], words[7]);
-                        }
-                        Q->n += (uint32_t)__popcll(m);
-                        (void)lane;
-                        if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, S, tab, cnt, *Q, 64u, acc);
-                    }
-                }
-            } else if (!CQ && any) {
+            if (any) {
                 uint32_t Lk[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
@@ -406,13 +466,23 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     }
 }
 
-// all 2^g assignments of slice s (high parameters = bits of s).  CQ: the compacting walk of a
+// Assignments of slice s (high parameters = bits of s): blocks [b0, b1) of its walk, or with
+// fewer than kInnerBits walk bits the whole walk (b0 = 0, b1 = 1).  CQ: the compacting walk of a
 // program with vanishing factors and at least kInnerBits walk bits (called by the whole wave,
 // valid marks the lanes with a slice); otherwise every other kind of program.
 template <int W, bool MONO, int ACC, uint32_t SET, bool CQ>
-__device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
-                                          unsigned long long *cnt, uint64_t s, bool valid, WaveQueue *Q,
+__device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const int64_t *tab, unsigned long long *cnt,
+                                          uint64_t s, bool valid, uint32_t b0, uint32_t b1, WaveQueue *Q,
                                           Acc<ACC> &acc) {
+    // the compacting walk needs only the vanishing masks (the queue reads the statistic
+    // masks when it evaluates terms)
+    Slots<W> S;
+    if (CQ) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) S.zm[w] = wd[H.off_zmask + w];
+    } else {
+        load_slots<W, SET>(H, wd + opaque_zero(), S);
+    }
     CU32 *col = wd + H.off_col;
     uint32_t L[W];
 #pragma unroll
@@ -441,13 +511,34 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, const Slots<W> &S,
             dal |= (uint64_t)(f & 7) << (4 * i);
         }
     }
+    if (b0) {
+        // the walk starts at block b0: its first state has the walk bits of gray(b0 * 2^K)
+        const uint32_t t0 = b0 << kInnerBits;
+        const uint32_t g0 = t0 ^ (t0 >> 1);
+        for (uint32_t bits = g0; bits; bits &= bits - 1u) {
+            const uint32_t j = (uint32_t)__builtin_ctz(bits);
+#pragma unroll
+            for (int w = 0; w < W; ++w) L[w] ^= col[j * W + w];
+        }
+        if (MONO) {
+            CU32 *mw = wd + H.off_monowalk;
+            for (uint32_t e = 0; e < H.n_monowalk; ++e, mw += 4) {
+                const uint32_t wm = mw[1];
+                if ((g0 & wm) != wm) continue;
+                const uint64_t hm = (uint64_t)mw[2] | ((uint64_t)mw[3] << 32);
+                phi += ((s & hm) == hm) ? (int)mw[0] : 0;
+            }
+        }
+    }
     if (CQ) {
-        walk_blocks<W, MONO, ACC, SET, true, true>(H, S, wd, tab, cnt, s, valid, L, phi, dal, Q, acc);
+        walk_blocks<W, MONO, ACC, SET, true, true>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q, acc);
         return;
     }
     if (H.g >= (uint32_t)kInnerBits) {
-        if (!H.has_zero) walk_blocks<W, MONO, ACC, SET, false, false>(H, S, wd, tab, cnt, s, true, L, phi, dal, Q, acc);
-        else if (!kCompact<W>) walk_blocks<W, MONO, ACC, SET, true, false>(H, S, wd, tab, cnt, s, true, L, phi, dal, Q, acc);
+        if (!H.has_zero)
+            walk_blocks<W, MONO, ACC, SET, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
+        else if (!kCompact<W>)
+            walk_blocks<W, MONO, ACC, SET, true, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
         return;
     }
     // short walks: one step at a time
@@ -548,49 +639,84 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
     __syncthreads();
 }
 
-// Rounds of blockDim slices are uniform across the block, so counters can be flushed
-// between rounds (every flush_rounds rounds keeps each counter below 2^64).
+// Values that are the same in every lane of the wave, kept in scalar registers (the compiler
+// cannot always prove it, for instance after a 64-bit division).
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    return ((uint64_t)uniform32((uint32_t)(x >> 32)) << 32) | uniform32((uint32_t)x);
+}
+
+// Work of one range of slices.  The unit is one block of the walks of a group of 64
+// consecutive slices (one slice per lane; with fewer than kInnerBits walk bits a whole walk),
+// and wave w of the nw waves that share the range takes a contiguous run of units, so the waves
+// differ by at most one unit and every lane of a wave is at the same block.  Lanes whose slice
+// is past the end of the range do nothing (or, in the compacting walk, walk without results).
+// With class counters the runs are cut into chunks of at most chunk_units units, the same
+// number of chunks in every wave of the workgroup, and the counters are flushed after each.
 template <int W, bool MONO, int ACC, uint32_t SET>
 __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img, uint64_t s_first, uint64_t s_count,
-                                          uint64_t lane0, uint64_t stride, uint32_t flush_rounds, int64_t *s_tab,
+                                          uint64_t wave, uint64_t n_waves, uint64_t chunk_units, int64_t *s_tab,
                                           unsigned long long *s_cnt, uint32_t *s_queue, i128 (&out)[4]) {
     CU32 *wd = const_words(img);
     const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
-    Slots<W> S;
-    load_slots<W, SET>(H, wd, S);
     Acc<ACC> acc;
     acc.clear();
     WaveQueue Q{s_queue + (threadIdx.x >> 6) * kQueueCap * kQueueWords<W>, 0u};
-    const bool compact = kCompact<W> && H.has_zero && H.g >= (uint32_t)kInnerBits;
-    uint32_t rounds = 0;
-    for (uint64_t base = lane0 - threadIdx.x; base < s_count; base += stride) {
-        const uint64_t s = base + threadIdx.x;
-        const bool valid = s < s_count;
-        if (compact) run_slice<W, MONO, ACC, SET, true>(H, S, wd, s_tab, s_cnt, s_first + (valid ? s : 0), valid, &Q, acc);
-        else if (valid) run_slice<W, MONO, ACC, SET, false>(H, S, wd, s_tab, s_cnt, s_first + s, true, &Q, acc);
-        if (ACC == ACC_CLASS && ++rounds == flush_rounds) {
+    const bool blocks = H.g >= (uint32_t)kInnerBits;
+    const bool compact = kCompact<W> && H.has_zero && blocks;
+    const uint32_t lg_nb = blocks ? H.g - kInnerBits : 0u;  // units per slice group = 2^lg_nb
+    const uint64_t n_units = ((s_count + 63) >> 6) << lg_nb;
+    const uint64_t q = uniform64(n_units / n_waves), r = uniform64(n_units % n_waves);
+    const uint64_t u_begin = uniform64(wave * q + (wave < r ? wave : r));
+    const uint64_t u_end = uniform64(u_begin + q + (wave < r ? 1 : 0));
+    const uint64_t most = q + (r ? 1 : 0);  // largest run of any wave
+    const uint64_t chunk = ACC == ACC_CLASS && chunk_units ? chunk_units : (most ? most : 1);
+    const uint64_t n_chunks = uniform64((most + chunk - 1) / chunk);
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint64_t c = 0; c < n_chunks; ++c) {
+        const uint64_t c0 = u_begin + c * chunk;
+        const uint64_t c1 = c0 + chunk < u_end ? c0 + chunk : u_end;
+        for (uint64_t u = c0; u < c1;) {
+            const uint64_t group = uniform64(u >> lg_nb);
+            const uint32_t b0 = uniform32((uint32_t)(u & ((1ull << lg_nb) - 1)));
+            const uint64_t left = c1 - u;
+            const uint32_t b1 =
+                uniform32((uint64_t)(1u << lg_nb) - b0 < left ? (1u << lg_nb) : b0 + (uint32_t)left);
+            const uint64_t s = (group << 6) + lane;
+            const bool valid = s < s_count;
+            if (compact)
+                run_slice<W, MONO, ACC, SET, true>(H, wd, s_tab, s_cnt, s_first + (valid ? s : 0), valid, b0,
+                                                   blocks ? b1 : 1u, &Q, acc);
+            else if (valid)
+                run_slice<W, MONO, ACC, SET, false>(H, wd, s_tab, s_cnt, s_first + s, true, b0,
+                                                    blocks ? b1 : 1u, &Q, acc);
+            u += b1 - b0;
+        }
+        if (ACC == ACC_CLASS && c + 1 < n_chunks) {
+            if (compact && Q.n) queue_drain<W, ACC, SET>(H, wd, s_tab, s_cnt, Q, Q.n, acc);
             flush_counters<ACC>(H, gtab, s_cnt, out);
-            rounds = 0;
         }
     }
-    if (compact && Q.n) queue_drain<W, ACC, SET>(H, S, s_tab, s_cnt, Q, Q.n, acc);
+    if (compact && Q.n) queue_drain<W, ACC, SET>(H, wd, s_tab, s_cnt, Q, Q.n, acc);
     if (ACC == ACC_CLASS) flush_counters<ACC>(H, gtab, s_cnt, out);
     acc_to_i128<ACC>(acc, out);
 }
 
 template <int W, bool MONO, int ACC, uint32_t SET>
 __global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t *__restrict__ img,
-                                                      uint64_t s_begin, uint64_t s_count, uint32_t flush_rounds,
+                                                      uint64_t s_begin, uint64_t s_count, uint64_t chunk_units,
                                                       Partial *__restrict__ partials) {
     extern __shared__ int64_t s_dyn[];
     __shared__ uint4 s_queue[kCompact<W> ? kMaxThreads / 64 * kQueueCap * kQueueWords<W> / 4 : 1];
     const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
     prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
     i128 out[4] = {0, 0, 0, 0};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    run_range<W, MONO, ACC, SET>(H, img, s_begin, s_count, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride,
-                                 flush_rounds, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
-                                 reinterpret_cast<uint32_t *>(s_queue), out);
+    // wave-uniform by construction; readfirstlane tells the compiler so
+    const uint64_t wave = __builtin_amdgcn_readfirstlane((uint32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    run_range<W, MONO, ACC, SET>(H, img, s_begin, s_count, wave, n_waves, chunk_units, s_dyn,
+                                 reinterpret_cast<unsigned long long *>(s_dyn), reinterpret_cast<uint32_t *>(s_queue),
+                                 out);
     block_reduce_store(out, partials + blockIdx.x);
 }
 
@@ -598,7 +724,7 @@ template <int W, bool MONO, int ACC, uint32_t SET>
 __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__restrict__ hdrs,
                                                             const uint64_t *__restrict__ imgs,
                                                             const WorkItem *__restrict__ items, uint32_t n_items,
-                                                            uint32_t *__restrict__ queue, uint32_t flush_rounds,
+                                                            uint32_t *__restrict__ queue, uint64_t chunk_units,
                                                             Partial *__restrict__ partials) {
     extern __shared__ int64_t s_dyn[];
     __shared__ uint4 s_queue[kCompact<W> ? kMaxThreads / 64 * kQueueCap * kQueueWords<W> / 4 : 1];
@@ -620,8 +746,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__r
             loaded = prog;
         }
         i128 out[4] = {0, 0, 0, 0};
-        run_range<W, MONO, ACC, SET>(H, img, wi.s_begin, wi.s_end - wi.s_begin, threadIdx.x, blockDim.x, flush_rounds,
-                                     s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
+        run_range<W, MONO, ACC, SET>(H, img, wi.s_begin, wi.s_end - wi.s_begin,
+                                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), blockDim.x >> 6,
+                                     chunk_units, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
                                      reinterpret_cast<uint32_t *>(s_queue), out);
         block_reduce_store(out, partials + wi.out_slot);
     }
@@ -642,7 +769,7 @@ hipError_t launch_eval_t(const ImgHeader &H, const void *dimg, uint64_t s_begin,
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, H, reinterpret_cast<const uint8_t *>(dimg),
-                       s_begin, s_count, flush_rounds_for(H, threads), partials);
+                       s_begin, s_count, chunk_units_for(H, threads), partials);
     return hipGetLastError();
 }
 
@@ -654,7 +781,7 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
     hipError_t e = set_lds(kern, lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds_bytes, stream, d_hdrs, d_imgs, d_items, n_items,
-                       d_queue, flush_rounds_for(H0, threads), partials);
+                       d_queue, chunk_units_for(H0, threads), partials);
     return hipGetLastError();
 }
 

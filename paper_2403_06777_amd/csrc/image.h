@@ -67,6 +67,10 @@ struct ImgHeader {
     uint32_t off_zmask; // W words: bits of factors that can vanish; such a bit of L is 1 exactly
                         // where its factor vanishes (the form, complemented if that is at l = 0)
     uint32_t off_never; // W words: a value of L & zmask that no block's surviving terms have
+    uint32_t inner_rank;  // rank r of the inner columns on the vanishing bits (walks of at least
+    uint32_t off_ibasis;  //   kInnerBits positions): r entries of 3 + W words (pivot word, pivot
+                          //   bit, inner columns making it up, reduced basis vector), then at
+    uint32_t off_ikern;   //   off_ikern the 4 - r null-space combinations of the inner columns
     uint32_t off_slots; // kSlots entries of (W + 1) words: weight (0 = unused), mask[W]
     int32_t stat_base[N_STATS];
     uint32_t off_monohi;  // monomials over high positions only: c, mask_lo, mask_hi (slice bits)
@@ -92,6 +96,12 @@ struct ImgHeader {
     uint32_t off_c3;      //   is an outer walk bit) are [c3idx[i], c3idx[i+1]) at off_c3, 7 words
     uint32_t n_c3;        //   each: even lo, hi, odd lo, hi, its other outer walk bits, slice mask
                           //   lo, hi; at a flip of i with the other bits set it toggles on or off
+    // A walk may start at any block of a slice (the work of a wave is a contiguous range of
+    // blocks); its start state then needs:
+    uint32_t off_c3all;   // n_c3all entries, 7 words: the inner-and-outer monomials once each
+    uint32_t n_c3all;     //   (even lo, hi, odd lo, hi, outer walk mask, slice mask lo, hi)
+    uint32_t off_monowalk;  // n_monowalk entries, 4 words: every monomial with a walk part
+    uint32_t n_monowalk;    //   (c, walk mask, slice mask lo, hi)
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
     uint32_t table_n;         // entries (value classes + one zero entry)
     int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e

@@ -33,8 +33,9 @@ constexpr int kMaxThreads = 256;
 
 // dynamic LDS of a program: value table (register modes) or class counters
 size_t dyn_lds_bytes(const ImgHeader &H);
-// rounds of `threads` slices between flushes of the class counters
-uint32_t flush_rounds_for(const ImgHeader &H, uint32_t threads);
+// work units per wave between flushes of the class counters (every workgroup adds fewer than
+// 2^32 terms of at most 2^31 each to a counter between flushes)
+uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads);
 
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
                        Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);

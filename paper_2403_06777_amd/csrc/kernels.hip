@@ -78,11 +78,12 @@ size_t dyn_lds_bytes(const ImgHeader &H) {
     return (size_t)H.table_n * 32;
 }
 
-uint32_t flush_rounds_for(const ImgHeader &H, uint32_t threads) {
-    // one round adds at most threads * 2^g terms of at most 2^31 each to a counter
-    const uint64_t per_round = (uint64_t)threads << H.g;
-    const uint64_t r = ((uint64_t)1 << 32) / (per_round ? per_round : 1);
-    return (uint32_t)(r < 1 ? 1 : (r > 0xffffffffu ? 0xffffffffu : r));
+uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads) {
+    // a unit is one block (2^kInnerBits terms) of 64 lanes, or one whole walk of 2^g terms
+    const uint32_t lg_terms = H.g >= (uint32_t)kInnerBits ? (uint32_t)kInnerBits : H.g;
+    const uint64_t per_unit = (uint64_t)(threads ? threads : 64) << lg_terms;  // terms per unit in a workgroup
+    const uint64_t c = ((uint64_t)1 << 32) / per_unit;
+    return c ? c : 1;
 }
 
 hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {

@@ -406,12 +406,13 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     for (const auto &m : w.mono)
         for (int v : m.first) inc[v - q]++;
     // Walk length: a slice costs a set-up (its high parameters into L, and with variable
-    // monomials a full evaluation of phi) that the 2^g walk steps amortise, while the slices
-    // are also the unit that balances the work over the lanes of the chip (a large program
-    // wants many slices per resident wave so that the last round is nearly full).  Without
-    // variable monomials the set-up is a few XORs per high parameter.
-    const int want = w.mono.empty() ? 8 : 10;
+    // monomials a full evaluation of phi) that the 2^g walk steps amortise; without variable
+    // monomials the set-up is a few XORs per high parameter.  The kernels balance work in
+    // blocks of a walk, so long walks cost no balance, but a wave holds 64 slices, so the walk
+    // leaves at least 64 slices where the program is large enough.
+    const int want = w.mono.empty() ? 8 : 12;
     int g_orig = std::min(p, std::min(max_walk_bits, want));
+    if (p - g_orig < 6) g_orig = std::max(std::min(p, kInnerBits), p - 6);
     if (!w.mono.empty()) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
     if (p - g_orig > 62) g_orig = p - 62;
     if (!w.mono.empty() && q + g_orig > 16) {
@@ -611,6 +612,57 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         }
         img.insert(img.end(), nv.begin(), nv.end());
     }
+    // The masked start vector a of a block has a surviving term at step k iff a equals the
+    // combination of the inner columns on the vanishing bits picked by gray(k).  A reduced
+    // basis of their span (each basis vector owns a pivot bit no other has) lets a lane read the
+    // coordinates of a off its pivot bits: a is in the span iff it equals that combination, and
+    // the inner columns' coefficients of a basis vector turn the coordinates into gray(k); the
+    // null space (dependent columns) gives the other steps with the same vector.
+    {
+        std::vector<std::vector<uint32_t>> basis;  // reduced basis vectors
+        std::vector<int> pivot;                    // their pivot bits
+        std::vector<uint32_t> comb;                // inner columns making up each
+        std::vector<uint32_t> kern;                // null-space basis (4-bit combinations)
+        if (g >= kInnerBits) {
+            for (int j = 0; j < kInnerBits; ++j) {
+                std::vector<uint32_t> v(W, 0);
+                for (int f = 0; f < F; ++f)
+                    if (used[f].mask >> j & 1) v[f / 32] |= 1u << (f % 32);
+                for (int k = 0; k < W; ++k) v[k] &= zmask[k];
+                uint32_t c = 1u << j;
+                for (size_t i = 0; i < basis.size(); ++i)
+                    if (v[pivot[i] / 32] >> (pivot[i] % 32) & 1) {
+                        for (int k = 0; k < W; ++k) v[k] ^= basis[i][k];
+                        c ^= comb[i];
+                    }
+                int pb = -1;
+                for (int k = 0; k < W && pb < 0; ++k)
+                    if (v[k]) pb = 32 * k + __builtin_ctz(v[k]);
+                if (pb < 0) {
+                    kern.push_back(c);
+                    continue;
+                }
+                for (size_t i = 0; i < basis.size(); ++i)
+                    if (basis[i][pb / 32] >> (pb % 32) & 1) {
+                        for (int k = 0; k < W; ++k) basis[i][k] ^= v[k];
+                        comb[i] ^= c;
+                    }
+                basis.push_back(v);
+                pivot.push_back(pb);
+                comb.push_back(c);
+            }
+        }
+        H.inner_rank = (uint32_t)basis.size();
+        H.off_ibasis = (uint32_t)img.size();
+        for (size_t i = 0; i < basis.size(); ++i) {
+            img.push_back((uint32_t)(pivot[i] / 32));
+            img.push_back((uint32_t)(pivot[i] % 32));
+            img.push_back(comb[i]);
+            img.insert(img.end(), basis[i].begin(), basis[i].end());
+        }
+        H.off_ikern = (uint32_t)img.size();
+        img.insert(img.end(), kern.begin(), kern.end());
+    }
     H.off_slots = (uint32_t)img.size();
     for (int s = 0; s < N_STATS; ++s)
         H.stat_base[s] = (int32_t)(s == STAT_R ? mod8(base[s]) : base[s]);
@@ -712,7 +764,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // with an inner variable, field k of the (even, odd) vector is c * ([inner part set at
     // step k] - [... at step 0]) mod 8; grouped by what else the monomial needs
     uint64_t inner_vec[2] = {0, 0};
-    std::vector<uint32_t> c2;
+    std::vector<uint32_t> c2, c3all;
     std::vector<std::vector<uint32_t>> c3pos(g);  // per outer walk position
     if (g >= kInnerBits) {
         const uint64_t inner_mask = ((uint64_t)1 << kInnerBits) - 1;
@@ -746,6 +798,13 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 c2.push_back((uint32_t)(hm >> 32));
                 continue;
             }
+            c3all.push_back((uint32_t)vec[0]);
+            c3all.push_back((uint32_t)(vec[0] >> 32));
+            c3all.push_back((uint32_t)vec[1]);
+            c3all.push_back((uint32_t)(vec[1] >> 32));
+            c3all.push_back(om);
+            c3all.push_back((uint32_t)hm);
+            c3all.push_back((uint32_t)(hm >> 32));
             // needs outer walk bits: its activation toggles when one of them flips while the
             // others are set; at a flip of outer position i the outer bits below i - 1 are clear
             for (int i = kInnerBits; i < g; ++i) {
@@ -784,6 +843,22 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     }
     H.off_c3 = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), c3pos[i].begin(), c3pos[i].end());
+    // for a walk that starts inside a slice: each inner-and-outer monomial once, with its whole
+    // outer mask, and every monomial with a walk part (c, walk mask, slice mask lo, hi)
+    H.off_c3all = (uint32_t)img.size();
+    H.n_c3all = (uint32_t)(c3all.size() / 7);
+    img.insert(img.end(), c3all.begin(), c3all.end());
+    H.off_monowalk = (uint32_t)img.size();
+    for (const auto &m : monos) {
+        const uint32_t wm = (uint32_t)(m.second & walk_mask);
+        if (!wm) continue;
+        const uint64_t hm = m.second >> g;
+        img.push_back((uint32_t)m.first);
+        img.push_back(wm);
+        img.push_back((uint32_t)hm);
+        img.push_back((uint32_t)(hm >> 32));
+        H.n_monowalk++;
+    }
 
     // ---- value table
     const int nd = (int)(dmax - dmin + 1);
