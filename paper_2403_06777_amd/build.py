@@ -7,8 +7,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzxpar.so")
-SOURCES = ["capi.cpp", "program.cpp", "compiler.cpp", "kernels.hip",
-           "eval_w1.hip", "eval_w2.hip", "eval_w4.hip", "eval_w8.hip", "eval_w16.hip"]
+# the evaluation kernels are instantiated per form-vector width and monomial flag, one unit
+# each, largest first so that the parallel build finishes early
+SOURCES = ["eval_w16_m1.hip", "eval_w16_m0.hip", "eval_w8_m1.hip", "eval_w8_m0.hip", "eval_w4_m1.hip",
+           "eval_w4_m0.hip", "eval_w2_m1.hip", "eval_w2_m0.hip", "eval_w1_m1.hip", "eval_w1_m0.hip",
+           "kernels.hip", "capi.cpp", "program.cpp", "compiler.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -163,28 +163,41 @@ uint32_t pick_threads(const sim_tuning *t) {
     return th;
 }
 
-// one evaluation of a slice range: kernel + finaliser + readback (device lock held)
-int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint64_t count, bool raw,
-                      hipStream_t stream, const sim_tuning *t, sim_zomega *out, float *kernel_ms = nullptr) {
-    const PackedProgram &pk = P->pk;
-    const uint32_t threads = pick_threads(t);
-    // By default the grid is what the chip holds at once (every block resident), so that the
-    // rounds of slices inside the kernel, not a second wave of blocks, balance the work.
+// Grid of the single-program kernel over `count` slices: by default what the chip holds at
+// once (every block resident), so that the kernel's own split of the work into per-wave runs of
+// blocks, not a second wave of workgroups, balances it; never more waves than work units (one
+// 2^kInnerBits-term block of 64 slices, or one whole short walk of 64 slices).
+int eval_grid(DeviceState &D, const sim_program *P, uint64_t count, uint32_t threads, const sim_tuning *t,
+              uint32_t *blocks) {
+    const ImgHeader &H = P->pk.hdr;
     uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 0u;
     if (!bpc) {
         sim_program *Pm = const_cast<sim_program *>(P);
         if (Pm->occ_threads != threads) {
             int occ = 0;
-            HIP_TRY(eval_occupancy(pk.hdr, threads, &occ));
+            HIP_TRY(eval_occupancy(H, threads, &occ));
             Pm->occ_blocks = std::max(1, occ);
             Pm->occ_threads = threads;
         }
         bpc = (uint32_t)Pm->occ_blocks;
     }
-    uint64_t want = (count + threads - 1) / threads;
-    uint64_t cap = (uint64_t)std::max(1, D.cus) * bpc;
-    uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+    const uint32_t lg_units = H.g >= (uint32_t)kInnerBits ? H.g - kInnerBits : 0u;
+    const uint64_t units = ((count + 63) / 64) << std::min<uint32_t>(lg_units, 40);
+    const uint64_t waves_per_block = threads / 64;
+    const uint64_t want = (units + waves_per_block - 1) / waves_per_block;
+    const uint64_t cap = (uint64_t)std::max(1, D.cus) * bpc;
+    *blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+    return SIM_OK;
+}
+
+// one evaluation of a slice range: kernel + finaliser + readback (device lock held)
+int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint64_t count, bool raw,
+                      hipStream_t stream, const sim_tuning *t, sim_zomega *out, float *kernel_ms = nullptr) {
+    const PackedProgram &pk = P->pk;
+    const uint32_t threads = pick_threads(t);
+    uint32_t blocks = 1;
     int rc;
+    if ((rc = eval_grid(D, P, count, threads, t, &blocks))) return rc;
     if ((rc = ensure(D.partials, (size_t)blocks * sizeof(Partial)))) return rc;
     if ((rc = ensure(D.result, sizeof(DevResult)))) return rc;
     if ((rc = ensure_host(D, sizeof(DevResult)))) return rc;
@@ -505,12 +518,25 @@ struct BatchLayout {
     std::vector<uint32_t> firsts, counts;  // per program: its items
     std::vector<FinalArgs> args;
     std::vector<uint32_t> live;  // indices of programs that need the GPU
+    // programs large enough to fill the GPU alone run as single-program launches (resident grid)
+    // beside the work queue of the small ones; their partials follow the items'
+    struct Big {
+        uint32_t prog;
+        uint64_t s0, count;
+        uint32_t blocks, slot;
+    };
+    std::vector<Big> big;
+    size_t n_partials = 0;
 };
+
+// terms from which a program in a batch gets its own launch
+constexpr uint64_t kBigTerms = (uint64_t)1 << 26;
+constexpr uint32_t kBigThreads = 256;
 
 constexpr uint64_t kMaxItemsPerProgram = 4096;
 
-int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_slice, const uint64_t *n_slices,
-                 bool raw, const sim_tuning *t, BatchLayout *L) {
+int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const uint64_t *first_slice,
+                 const uint64_t *n_slices, bool raw, const sim_tuning *t, BatchLayout *L) {
     L->hdrs.resize(n);
     L->imgs.resize(n);
     L->firsts.assign(n, 0);
@@ -523,20 +549,40 @@ int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_s
         L->imgs[i] = (uint64_t)(uintptr_t)P->dimg;
         L->args[i] = final_args(P->pk, raw);
         uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;
-        if (!P->pk.zero && cnt) order.push_back((uint32_t)i);
+        if (P->pk.zero || !cnt) continue;
+        const uint32_t lg = std::min<uint32_t>(P->pk.hdr.g, 62);
+        if (cnt >= (kBigTerms >> lg)) {
+            BatchLayout::Big b;
+            b.prog = (uint32_t)i;
+            b.s0 = first_slice ? first_slice[i] : 0;
+            b.count = cnt;
+            b.slot = 0;
+            int rc = eval_grid(D, P, cnt, kBigThreads, nullptr, &b.blocks);
+            if (rc) return rc;
+            L->big.push_back(b);
+            L->live.push_back((uint32_t)i);
+            continue;
+        }
+        order.push_back((uint32_t)i);
     }
     // group by kernel variant, keep program order inside a group
+    auto menu_of = [](const ImgHeader &H) { return H.acc == ACC_I128 ? 0u : H.slot_menu; };
+    // the node-slots-in-word-0 variants exist for widths 2 to 8 with the node or full slot sets
+    auto word0_of = [&](const ImgHeader &H) {
+        return H.node_word0 && H.W > 1 && H.W < 16 && H.acc != ACC_I128 && menu_of(H) != 2 ? 1u : 0u;
+    };
     auto variant = [&](uint32_t i) {
         const ImgHeader &H = ps[i]->pk.hdr;
-        return ((H.W * 2 + H.has_mono) * 4 + H.acc) * 4 + (H.acc == ACC_I128 ? 0 : H.slot_menu);
+        return (((H.W * 2 + H.has_mono) * 4 + H.acc) * 4 + menu_of(H)) * 2 + word0_of(H);
     };
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return variant(a) < variant(b); });
     for (uint32_t i : order) {
         const sim_program *P = ps[i];
         const ImgHeader &H = P->pk.hdr;
-        const uint32_t menu = H.acc == ACC_I128 ? 0u : H.slot_menu;
+        const uint32_t menu = menu_of(H), word0 = word0_of(H);
         if (L->groups.empty() || L->groups.back().W != H.W || L->groups.back().mono != H.has_mono ||
-            L->groups.back().acc != H.acc || L->groups.back().h0.slot_menu != menu) {
+            L->groups.back().acc != H.acc || L->groups.back().h0.slot_menu != menu ||
+            L->groups.back().h0.node_word0 != word0) {
             BatchLayout::Group g;
             g.W = H.W;
             g.mono = H.has_mono;
@@ -544,6 +590,7 @@ int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_s
             g.item_first = (uint32_t)L->items.size();
             g.h0 = H;
             g.h0.slot_menu = menu;
+            g.h0.node_word0 = word0;
             L->groups.push_back(g);
         }
         BatchLayout::Group &g = L->groups.back();
@@ -572,7 +619,15 @@ int build_layout(const sim_program *const *ps, size_t n, const uint64_t *first_s
         g.n_items = (uint32_t)L->items.size() - g.item_first;
         L->live.push_back(i);
     }
-    if (L->items.size() > 0xffffffffu) return fail(SIM_ERANGE, "too many work items");
+    size_t slot = L->items.size();
+    for (auto &b : L->big) {
+        b.slot = (uint32_t)slot;
+        L->firsts[b.prog] = b.slot;
+        L->counts[b.prog] = b.blocks;
+        slot += b.blocks;
+    }
+    L->n_partials = slot;
+    if (L->n_partials > 0xffffffffu) return fail(SIM_ERANGE, "too many work items");
     return SIM_OK;
 }
 
@@ -586,7 +641,7 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
     const size_t ng = L.groups.size();
     // kernel variants run concurrently: group k on auxiliary stream k % kAux, forked from and
     // joined back into `stream` with events (also valid under stream capture)
-    const bool fork = ng > 1;
+    const bool fork = ng > 1 || (ng > 0 && !L.big.empty());
     if (fork) {
         int rc = ensure_aux(D);
         if (rc) return rc;
@@ -604,6 +659,10 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
                                   blocks, threads, g.lds_bytes, s));
         ++gi;
     }
+    // the large programs one after another on the caller's stream, beside the queued groups
+    for (const auto &b : L.big)
+        HIP_TRY(launch_eval(L.hdrs[b.prog], (const void *)(uintptr_t)L.imgs[b.prog], b.s0, b.count,
+                            d_parts + b.slot, b.blocks, kBigThreads, stream));
     if (fork) {
         for (int a = 0; a < kAux && a < (int)ng; ++a) {
             HIP_TRY(hipEventRecord(D.ev_join[a], D.aux[a]));
@@ -653,7 +712,7 @@ int upload_layout(DeviceState &D, const BatchLayout &L, size_t n, hipStream_t st
         memcpy(h + o_args, L.args.data(), n * sizeof(FinalArgs));
     }
     if (!L.items.empty()) memcpy(h + o_items, L.items.data(), L.items.size() * sizeof(WorkItem));
-    if ((rc = ensure(D.partials, std::max<size_t>(1, L.items.size()) * sizeof(Partial)))) return rc;
+    if ((rc = ensure(D.partials, std::max<size_t>(1, L.n_partials) * sizeof(Partial)))) return rc;
     if ((rc = ensure(D.result, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
     if ((rc = ensure(D.queue, std::max<size_t>(1, L.groups.size()) * 4))) return rc;
     if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
@@ -694,7 +753,7 @@ int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, con
     DeviceState &D = g_dev[dev];
     std::lock_guard<std::mutex> lk(D.mu);
     BatchLayout L;
-    if ((rc = build_layout(ps, n, first, count, raw, t, &L))) return rc;
+    if ((rc = build_layout(D, ps, n, first, count, raw, t, &L))) return rc;
     hipStream_t st = (hipStream_t)stream;
     LayoutPtrs LP;
     if ((rc = upload_layout(D, L, n, st, &LP))) return rc;
@@ -825,13 +884,15 @@ int sim_batch_plan_create(const sim_program *const *ps, size_t n, const sim_tuni
         plan->tuning = *t;
         plan->has_tuning = true;
     }
-    if ((rc = build_layout(ps, n, nullptr, nullptr, false, t, &plan->L))) return rc;
+    // the device lock covers the layout (occupancy queries) and the capture (auxiliary streams)
+    std::lock_guard<std::mutex> lk(g_dev[dev].mu);
+    if ((rc = build_layout(g_dev[dev], ps, n, nullptr, nullptr, false, t, &plan->L))) return rc;
     const BatchLayout &L = plan->L;
     hipStream_t st = (hipStream_t)stream;
     auto alloc = [&](DevBuf &b, size_t bytes) { return ensure(b, std::max<size_t>(bytes, 64)); };
     if ((rc = alloc(plan->hdrs, n * sizeof(ImgHeader))) || (rc = alloc(plan->imgs, n * 8)) ||
         (rc = alloc(plan->items, L.items.size() * sizeof(WorkItem))) ||
-        (rc = alloc(plan->parts, L.items.size() * sizeof(Partial))) || (rc = alloc(plan->firsts, n * 4)) ||
+        (rc = alloc(plan->parts, L.n_partials * sizeof(Partial))) || (rc = alloc(plan->firsts, n * 4)) ||
         (rc = alloc(plan->counts, n * 4)) || (rc = alloc(plan->args, n * sizeof(FinalArgs))) ||
         (rc = alloc(plan->result, n * sizeof(DevResult))) || (rc = alloc(plan->queue, L.groups.size() * 4 + 4)))
         return rc;

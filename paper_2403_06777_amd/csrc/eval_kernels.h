@@ -60,7 +60,7 @@ __device__ __forceinline__ void load_slots(const ImgHeader &H, CU32 *wd, Slots<W
         if (!((SET >> i) & 1u)) continue;
         CU32 *e = wd + H.off_slots + i * (W + 1);
 #pragma unroll
-        for (int w = 0; w < W; ++w) S.m[i][w] = e[1 + w];
+        for (int w = 0; w < slot_words(SET, i, W); ++w) S.m[i][w] = e[1 + w];
     }
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -87,7 +87,7 @@ __device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W>
         if ((SET >> i) & 1u) {  // compile-time: the slot belongs to this kernel's set
             uint32_t c = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) c += popc(L[w] & S.m[i][w]);
+            for (int w = 0; w < slot_words(SET, i, W); ++w) c += popc(L[w] & S.m[i][w]);
             const int wgt = slot_weight(i);
             if (wgt == 1) st[slot_stat(i)] += (int)c;
             else if (wgt == -1) st[slot_stat(i)] -= (int)c;
@@ -787,36 +787,44 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
 
 }  // namespace
 
-// variant selection within one width: slot set (int128 accumulation only with the full set),
-// accumulation mode, monomials
-#define DISPATCH_W(w, MONO_, ACC_, MENU_, CALL)                                             \
-    do {                                                                                     \
-        if ((ACC_) > 2 || (MENU_) > 2) return hipErrorInvalidValue;                          \
-        DISPATCH_M(w, MONO_, ACC_, MENU_, CALL);                                             \
-    } while (0)
-#define DISPATCH_M(w, MONO_, ACC_, MENU_, CALL)                                              \
-    if (MONO_) DISPATCH_A(w, true, ACC_, MENU_, CALL);                                       \
-    else DISPATCH_A(w, false, ACC_, MENU_, CALL);
+// variant selection within one width: slot set (int128 accumulation only with the full set;
+// node slots in word 0 for widths 2 to 8), accumulation mode, monomials
 #define DISPATCH_A(w, m, ACC_, MENU_, CALL)                                                  \
     do {                                                                                     \
         if ((ACC_) == ACC_I128) return CALL(w, m, ACC_I128, kSlotSetAll);                    \
         if ((ACC_) == ACC_I64) {                                                             \
-            if ((MENU_) == 1) return CALL(w, m, ACC_I64, kSlotSetNodes);                     \
             if ((MENU_) == 2) return CALL(w, m, ACC_I64, kSlotSetPhase);                     \
+            if (w > 1 && w < 16 && N0_) {                                                    \
+                if ((MENU_) == 1) return CALL(w, m, ACC_I64, kSlotSetNodes | kNW0);          \
+                return CALL(w, m, ACC_I64, kSlotSetAll | kNW0);                              \
+            }                                                                                \
+            if ((MENU_) == 1) return CALL(w, m, ACC_I64, kSlotSetNodes);                     \
             return CALL(w, m, ACC_I64, kSlotSetAll);                                         \
         }                                                                                    \
-        if ((MENU_) == 1) return CALL(w, m, ACC_CLASS, kSlotSetNodes);                       \
         if ((MENU_) == 2) return CALL(w, m, ACC_CLASS, kSlotSetPhase);                       \
+        if (w > 1 && w < 16 && N0_) {                                                        \
+            if ((MENU_) == 1) return CALL(w, m, ACC_CLASS, kSlotSetNodes | kNW0);            \
+            return CALL(w, m, ACC_CLASS, kSlotSetAll | kNW0);                                \
+        }                                                                                    \
+        if ((MENU_) == 1) return CALL(w, m, ACC_CLASS, kSlotSetNodes);                       \
         return CALL(w, m, ACC_CLASS, kSlotSetAll);                                           \
     } while (0)
 
 
-template <int W>
-hipError_t launch_eval_w(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                         Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
+#define DISPATCH_WM(w, m, ACC_, MENU_, CALL)                                                 \
+    do {                                                                                     \
+        if ((ACC_) > 2 || (MENU_) > 2) return hipErrorInvalidValue;                          \
+        constexpr uint32_t kNW0 = kSlotsNodeWord0;                                           \
+        DISPATCH_A(w, m, ACC_, MENU_, CALL);                                                 \
+    } while (0)
+
+template <int W, bool MONO>
+hipError_t launch_eval_wm(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
+                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
 #define CALL_EVAL(w, m, a, set) \
     launch_eval_t<w, m, a, set>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
-    DISPATCH_W(W, H.has_mono != 0, H.acc, H.slot_menu, CALL_EVAL);
+    const bool N0_ = H.node_word0 != 0;
+    DISPATCH_WM(W, MONO, H.acc, H.slot_menu, CALL_EVAL);
 #undef CALL_EVAL
 }
 
@@ -829,28 +837,30 @@ hipError_t occupancy_t(const ImgHeader &H, uint32_t threads, int *blocks_per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, (int)threads, lds);
 }
 
-template <int W>
-hipError_t occupancy_w(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {
+template <int W, bool MONO>
+hipError_t occupancy_wm(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {
 #define CALL_OCC(w, m, a, set) occupancy_t<w, m, a, set>(H, threads, blocks_per_cu)
-    DISPATCH_W(W, H.has_mono != 0, H.acc, H.slot_menu, CALL_OCC);
+    const bool N0_ = H.node_word0 != 0;
+    DISPATCH_WM(W, MONO, H.acc, H.slot_menu, CALL_OCC);
 #undef CALL_OCC
 }
 
-template <int W>
-hipError_t launch_batch_w(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                          const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
-                          uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream) {
+template <int W, bool MONO>
+hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
+                           const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
+                           uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream) {
 #define CALL_BATCH(w, m, a, set) \
     launch_batch_t<w, m, a, set>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, \
                                  lds_bytes, stream)
-    DISPATCH_W(W, H0.has_mono != 0, H0.acc, H0.slot_menu, CALL_BATCH);
+    const bool N0_ = H0.node_word0 != 0;
+    DISPATCH_WM(W, MONO, H0.acc, H0.slot_menu, CALL_BATCH);
 #undef CALL_BATCH
 }
 
-#define INSTANTIATE_EVAL_W(w)                                                                          \
-    template hipError_t occupancy_w<w>(const ImgHeader &, uint32_t, int *);                            \
-    template hipError_t launch_eval_w<w>(const ImgHeader &, const void *, uint64_t, uint64_t, Partial *, \
-                                         uint32_t, uint32_t, hipStream_t);                             \
-    template hipError_t launch_batch_w<w>(const ImgHeader &, const ImgHeader *, const uint64_t *,      \
-                                          const WorkItem *, uint32_t, uint32_t *, Partial *, uint32_t, \
-                                          uint32_t, uint32_t, hipStream_t);
+#define INSTANTIATE_EVAL_WM(w, m)                                                                     \
+    template hipError_t occupancy_wm<w, m>(const ImgHeader &, uint32_t, int *);                       \
+    template hipError_t launch_eval_wm<w, m>(const ImgHeader &, const void *, uint64_t, uint64_t,     \
+                                             Partial *, uint32_t, uint32_t, hipStream_t);             \
+    template hipError_t launch_batch_wm<w, m>(const ImgHeader &, const ImgHeader *, const uint64_t *, \
+                                              const WorkItem *, uint32_t, uint32_t *, Partial *,      \
+                                              uint32_t, uint32_t, uint32_t, hipStream_t);

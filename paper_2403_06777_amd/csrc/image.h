@@ -38,6 +38,12 @@ constexpr uint32_t kSlotSetPhase = 0x700u;  // R* only: phase terms without fact
 IMG_HD constexpr uint32_t slot_set_of(uint32_t menu_index) {
     return menu_index == 1 ? kSlotSetNodes : menu_index == 2 ? kSlotSetPhase : kSlotSetAll;
 }
+// Added to a slot set: the node-factor slots (A, B, E) have bits in word 0 only (at most 32
+// node factors, whose bits come first), so they read one word; the phase slots read all W.
+constexpr uint32_t kSlotsNodeWord0 = 0x80000000u;
+IMG_HD constexpr int slot_words(uint32_t set, int slot, int W) {
+    return (set & kSlotsNodeWord0) && slot_stat(slot) != STAT_R ? 1 : W;
+}
 
 // Walk positions 0 .. kInnerBits-1 are stepped in unrolled blocks of 2^kInnerBits terms: the
 // flip positions inside a block are compile-time constants, and the phase of every term of a
@@ -61,6 +67,7 @@ struct ImgHeader {
     uint32_t has_mono;  // variable monomials present
     uint32_t acc;       // ACC_* mode
     uint32_t slot_menu; // index into the slot-set menu (0 all, 1 node factors, 2 phase only)
+    uint32_t node_word0;  // the node-factor slot masks are zero beyond word 0
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j
     uint32_t off_cvec;  // W words: L at the all-zero assignment

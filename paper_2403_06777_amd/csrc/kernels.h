@@ -60,13 +60,14 @@ hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item
 // resident blocks per compute unit of the single-program evaluation kernel of H
 hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
 
-// per-width evaluation launches, instantiated in eval_w<W>.hip (W = 1, 2, 4, 8, 16)
-template <int W>
-hipError_t occupancy_w(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
-template <int W>
-hipError_t launch_eval_w(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                         Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
-template <int W>
-hipError_t launch_batch_w(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                          const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
-                          uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream);
+// evaluation launches per form-vector width W (1, 2, 4, 8, 16) and monomial flag, instantiated
+// in eval_w<W>_m<0|1>.hip
+template <int W, bool MONO>
+hipError_t occupancy_wm(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
+template <int W, bool MONO>
+hipError_t launch_eval_wm(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
+                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
+template <int W, bool MONO>
+hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
+                           const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
+                           uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream);

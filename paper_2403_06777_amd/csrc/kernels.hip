@@ -86,15 +86,24 @@ uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads) {
     return c ? c : 1;
 }
 
+// width and monomial flag of a program select the instantiation unit
+#define SWITCH_WM(H_, CALL)                                   \
+    do {                                                      \
+        const bool m_ = (H_).has_mono != 0;                   \
+        switch ((H_).W) {                                     \
+            case 1: return m_ ? CALL(1, true) : CALL(1, false);   \
+            case 2: return m_ ? CALL(2, true) : CALL(2, false);   \
+            case 4: return m_ ? CALL(4, true) : CALL(4, false);   \
+            case 8: return m_ ? CALL(8, true) : CALL(8, false);   \
+            case 16: return m_ ? CALL(16, true) : CALL(16, false); \
+            default: return hipErrorInvalidValue;             \
+        }                                                     \
+    } while (0)
+
 hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu) {
-    switch (H.W) {
-        case 1: return occupancy_w<1>(H, threads, blocks_per_cu);
-        case 2: return occupancy_w<2>(H, threads, blocks_per_cu);
-        case 4: return occupancy_w<4>(H, threads, blocks_per_cu);
-        case 8: return occupancy_w<8>(H, threads, blocks_per_cu);
-        case 16: return occupancy_w<16>(H, threads, blocks_per_cu);
-        default: return hipErrorInvalidValue;
-    }
+#define CALL_OCC(w, m) occupancy_wm<w, m>(H, threads, blocks_per_cu)
+    SWITCH_WM(H, CALL_OCC);
+#undef CALL_OCC
 }
 
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
@@ -102,14 +111,9 @@ hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, u
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
     if (dyn_lds_bytes(H) > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-    switch (H.W) {
-        case 1: return launch_eval_w<1>(H, dimg, s_begin, s_count, partials, blocks, threads, stream);
-        case 2: return launch_eval_w<2>(H, dimg, s_begin, s_count, partials, blocks, threads, stream);
-        case 4: return launch_eval_w<4>(H, dimg, s_begin, s_count, partials, blocks, threads, stream);
-        case 8: return launch_eval_w<8>(H, dimg, s_begin, s_count, partials, blocks, threads, stream);
-        case 16: return launch_eval_w<16>(H, dimg, s_begin, s_count, partials, blocks, threads, stream);
-        default: return hipErrorInvalidValue;
-    }
+#define CALL_EVAL(w, m) launch_eval_wm<w, m>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
+    SWITCH_WM(H, CALL_EVAL);
+#undef CALL_EVAL
 }
 
 hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
@@ -119,16 +123,9 @@ hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
     if (lds_bytes > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-#define CALL_BATCH(w) \
-    launch_batch_w<w>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, lds_bytes, stream)
-    switch (H0.W) {
-        case 1: return CALL_BATCH(1);
-        case 2: return CALL_BATCH(2);
-        case 4: return CALL_BATCH(4);
-        case 8: return CALL_BATCH(8);
-        case 16: return CALL_BATCH(16);
-        default: return hipErrorInvalidValue;
-    }
+#define CALL_BATCH(w, m) \
+    launch_batch_wm<w, m>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, lds_bytes, stream)
+    SWITCH_WM(H0, CALL_BATCH);
 #undef CALL_BATCH
 }
 

@@ -695,6 +695,17 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         if (any) active_mask |= 1u << i;
     }
     H.slot_menu = (active_mask & ~kSlotSetPhase) == 0 ? 2u : (active_mask & ~kSlotSetNodes) == 0 ? 1u : 0u;
+    {
+        // node-factor bits are allocated first, so with at most 32 node factors the A, B and E
+        // masks live in word 0
+        bool word0 = W > 1;
+        for (int i = 0; i < kSlots && word0; ++i) {
+            if (slot_stat(i) == STAT_R) continue;
+            const uint32_t *m = img.data() + H.off_slots + i * (W + 1) + 1;
+            for (int k = 1; k < W; ++k) word0 = word0 && m[k] == 0;
+        }
+        H.node_word0 = word0 ? 1u : 0u;
+    }
     active_slots = __builtin_popcount(slot_set_of(H.slot_menu));
     // monomials in packed positions
     const uint64_t walk_mask = g >= 64 ? ~0ull : (((uint64_t)1 << g) - 1);
@@ -905,8 +916,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // ---- algorithmic work per term, in int32 lane (vector) operations counted from the packed
     // program; work on wave-uniform values (list walking, program constants) runs on the
     // scalar unit and is not counted.  The statistics of a term, needed only where no factor
-    // vanishes (an exact fraction: the vanishing conditions are affine in x): per mask W ANDs,
-    // W popcounts and one add, the table index and shift (10), the accumulation (int64 14,
+    // vanishes (an exact fraction: the vanishing conditions are affine in x): per mask one AND
+    // and one popcount per word it spans and one add, the table index and shift (10), the accumulation (int64 14,
     // int128 42, class counter 5) and with monomials the term's phase field (2).
     //  * walks of at least kInnerBits positions: with factors that can vanish, each term's
     //    vanishing test (a W-word compare) and for a surviving term the rebuild of its form
@@ -924,7 +935,11 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         const double acc_ops = H.acc == ACC_I64 ? 14.0 : H.acc == ACC_I128 ? 42.0 : 5.0;
         const bool mono = !w.mono.empty();
         const bool blocks = g >= kInnerBits;
-        const double stats = 10 + acc_ops + active_slots * (2.0 * W + 1) + (mono ? 2 : 0);
+        double slot_ops = 0;
+        const uint32_t set = slot_set_of(H.slot_menu) | (H.node_word0 ? kSlotsNodeWord0 : 0u);
+        for (int i = 0; i < kSlots; ++i)
+            if (set >> i & 1) slot_ops += 2.0 * slot_words(set, i, W) + 1;
+        const double stats = 10 + acc_ops + slot_ops + (mono ? 2 : 0);
         double ops;
         if (blocks && has_zero) ops = W + nz * (W + stats);
         else if (blocks) ops = W + stats;

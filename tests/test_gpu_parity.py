@@ -228,3 +228,41 @@ def test_finalize_batch_matches_single_finalize():
     finally:
         for h in hs:
             zx.sim_program_free(h)
+
+
+def test_batch_with_programs_above_the_own_launch_size(o2):
+    # programs of 2^26 terms and more run as their own launches inside a batch and its captured
+    # plan, beside the queued small ones; closed forms (oracle block sums) pin the large ones
+    full, blocks = wl.block_separable_program(11, 28, factors_per_block=4, lin_per_block=2, pairs_per_block=1,
+                                              scramble=True)
+    expect_big = zw.ONE
+    for blk in blocks:
+        expect_big = zw.mul(expect_big, o2.evaluate(blk.to_text(), threads=1)["raw"])
+    mono_full, mono_blocks = wl.block_separable_program(12, 32, factors_per_block=3, lin_per_block=1,
+                                                        mono_per_block=3, scramble=False)
+    expect_mono = zw.ONE
+    for blk in mono_blocks:
+        expect_mono = zw.mul(expect_mono, o2.evaluate(blk.to_text(), threads=1)["raw"])
+    texts = [full.to_text()] + _batch_programs()[:5] + [mono_full.to_text()]
+    hs = [zx.sim_program_from_ir(t) for t in texts]
+    plan = None
+    try:
+        expect = [zw.canonical(expect_big, 0)] + [oracle_value(o2, t) for t in texts[1:6]] + \
+                 [zw.canonical(expect_mono, 0)]
+        say("large in batch")
+        assert zx.sim_eval_batch(hs) == expect
+        plan = zx.sim_batch_plan_create(hs, None)
+        for rep in range(3):
+            say("large in plan", rep)
+            assert zx.sim_batch_plan_run(plan, len(hs)) == expect
+            assert zx.sim_eval_amplitude(hs[1]) == expect[1]
+        # ranges of the large program inside a batch equal its own range partials
+        info = zx.sim_program_info(hs[0])
+        ns = info["n_slices"]
+        raws = zx.sim_eval_ranges([hs[0], hs[0]], [0, ns // 3], [ns // 3, ns - ns // 3])
+        assert zx.sim_raw_add(raws[0], raws[1]) == zx.sim_eval_range(hs[0], 0, ns)
+    finally:
+        if plan:
+            zx.sim_batch_plan_free(plan)
+        for h in hs:
+            zx.sim_program_free(h)
