@@ -569,7 +569,7 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
     auto menu_of = [](const ImgHeader &H) { return H.acc == ACC_I128 ? 0u : H.slot_menu; };
     // the node-slots-in-word-0 variants exist for widths 2 to 8 with the node or full slot sets
     auto word0_of = [&](const ImgHeader &H) {
-        return H.node_word0 && H.W > 1 && H.W < 16 && H.acc != ACC_I128 && menu_of(H) != 2 ? 1u : 0u;
+        return H.node_word0 && H.W > 1 && H.W < 16 && H.acc != ACC_I128 && menu_of(H) < 2 ? 1u : 0u;
     };
     auto variant = [&](uint32_t i) {
         const ImgHeader &H = ps[i]->pk.hdr;

@@ -51,7 +51,12 @@ template <int W>
 struct Slots {
     uint32_t m[kSlots][W];
     uint32_t zm[W];
+    const uint32_t *ntab;  // node table in LDS (sets with kSlotsNodeTable)
+    uint32_t nmask;        // node bits of word 0
 };
+
+// the dynamic LDS of the kernels (value table or class counters, then the node table)
+extern __shared__ int64_t s_dyn[];
 
 template <int W, uint32_t SET>
 __device__ __forceinline__ void load_slots(const ImgHeader &H, CU32 *wd, Slots<W> &S) {
@@ -66,6 +71,10 @@ __device__ __forceinline__ void load_slots(const ImgHeader &H, CU32 *wd, Slots<W
     for (int w = 0; w < W; ++w) {
         S.zm[w] = wd[H.off_zmask + w];
     }
+    if (SET & kSlotsNodeTable) {
+        S.ntab = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s_dyn) + H.ntab_lds);
+        S.nmask = H.ntab_n - 1u;
+    }
 }
 
 struct TermClass {
@@ -79,6 +88,26 @@ struct TermClass {
 template <int W, uint32_t SET, bool ZERO>
 __device__ __forceinline__ TermClass classify(const ImgHeader &H, const Slots<W> &S, const uint32_t (&L)[W],
                                               int phi) {
+    if (SET & kSlotsNodeTable) {
+        // node factors from the table; the phase slots count the linear terms
+        const uint32_t e = S.ntab[L[0] & S.nmask];
+        int rl = H.stat_base[STAT_R];
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) {
+            if (!((SET >> i) & 1u)) continue;
+            uint32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) c += popc(L[w] & S.m[i][w]);
+            rl += (int)c * slot_weight(i);
+        }
+        TermClass t;
+        t.zero = ZERO && (e & 1u);
+        const int R = (int)(e >> 16) + rl + phi;
+        const uint32_t E = (e >> 8) & 0xFFu;
+        t.cls = ((((e >> 1) & 0x7Fu) << 4) | ((uint32_t)(R & 7) << 1)) | (E & 1u);
+        t.h = (int)(E >> 1);
+        return t;
+    }
     int st[N_STATS];
 #pragma unroll
     for (int s = 0; s < N_STATS; ++s) st[s] = H.stat_base[s];
@@ -636,6 +665,12 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
     } else {
         for (uint32_t i = threadIdx.x; i < H.table_n * 4; i += blockDim.x) s_tab[i] = gtab[i];
     }
+    if (H.ntab_n) {
+        const uint32_t *g = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(gtab) -
+                                                               H.table_byte_off) + H.off_ntab;
+        uint32_t *d = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_tab) + H.ntab_lds);
+        for (uint32_t i = threadIdx.x; i < H.ntab_n; i += blockDim.x) d[i] = g[i];
+    }
     __syncthreads();
 }
 
@@ -794,6 +829,7 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
         if ((ACC_) == ACC_I128) return CALL(w, m, ACC_I128, kSlotSetAll);                    \
         if ((ACC_) == ACC_I64) {                                                             \
             if ((MENU_) == 2) return CALL(w, m, ACC_I64, kSlotSetPhase);                     \
+            if ((MENU_) == 3 && w <= 8) return CALL(w, m, ACC_I64, kSlotSetPhase | kNTAB);   \
             if (w > 1 && w < 16 && N0_) {                                                    \
                 if ((MENU_) == 1) return CALL(w, m, ACC_I64, kSlotSetNodes | kNW0);          \
                 return CALL(w, m, ACC_I64, kSlotSetAll | kNW0);                              \
@@ -802,6 +838,7 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
             return CALL(w, m, ACC_I64, kSlotSetAll);                                         \
         }                                                                                    \
         if ((MENU_) == 2) return CALL(w, m, ACC_CLASS, kSlotSetPhase);                       \
+        if ((MENU_) == 3 && w <= 8) return CALL(w, m, ACC_CLASS, kSlotSetPhase | kNTAB);     \
         if (w > 1 && w < 16 && N0_) {                                                        \
             if ((MENU_) == 1) return CALL(w, m, ACC_CLASS, kSlotSetNodes | kNW0);            \
             return CALL(w, m, ACC_CLASS, kSlotSetAll | kNW0);                                \
@@ -813,8 +850,10 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
 
 #define DISPATCH_WM(w, m, ACC_, MENU_, CALL)                                                 \
     do {                                                                                     \
-        if ((ACC_) > 2 || (MENU_) > 2) return hipErrorInvalidValue;                          \
+        if ((ACC_) > 2 || (MENU_) > 3) return hipErrorInvalidValue;                          \
+        if ((MENU_) == 3 && ((ACC_) == ACC_I128 || (w) > 8)) return hipErrorInvalidValue;    \
         constexpr uint32_t kNW0 = kSlotsNodeWord0;                                           \
+        constexpr uint32_t kNTAB = kSlotsNodeTable;                                          \
         DISPATCH_A(w, m, ACC_, MENU_, CALL);                                                 \
     } while (0)
 

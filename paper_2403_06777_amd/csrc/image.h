@@ -35,8 +35,16 @@ IMG_HD constexpr int slot_weight(int i) {
 constexpr uint32_t kSlotSetAll = 0x7FFu;    // every slot
 constexpr uint32_t kSlotSetNodes = 0x7C5u;  // A+1, B+1, E-1, E-2, R*: factors 1 + w^{k l}
 constexpr uint32_t kSlotSetPhase = 0x700u;  // R* only: phase terms without factors
+// Added to the phase-only set: the node factors are looked up in a table indexed by their bits
+// (at most kMaxTableNodes node factors, bits 0 .. n-1 of word 0), whose entry holds the term's
+// vanishing flag, A - B (offset), E and the node part of R; only the phase slots are counted.
+constexpr uint32_t kSlotsNodeTable = 0x40000000u;
+constexpr int kMaxTableNodes = 10;
 IMG_HD constexpr uint32_t slot_set_of(uint32_t menu_index) {
-    return menu_index == 1 ? kSlotSetNodes : menu_index == 2 ? kSlotSetPhase : kSlotSetAll;
+    return menu_index == 1 ? kSlotSetNodes
+         : menu_index == 2 ? kSlotSetPhase
+         : menu_index == 3 ? (kSlotSetPhase | kSlotsNodeTable)
+                           : kSlotSetAll;
 }
 // Added to a slot set: the node-factor slots (A, B, E) have bits in word 0 only (at most 32
 // node factors, whose bits come first), so they read one word; the phase slots read all W.
@@ -66,7 +74,12 @@ struct ImgHeader {
     uint32_t has_zero;  // some factor can vanish: test the zero masks
     uint32_t has_mono;  // variable monomials present
     uint32_t acc;       // ACC_* mode
-    uint32_t slot_menu; // index into the slot-set menu (0 all, 1 node factors, 2 phase only)
+    uint32_t slot_menu; // index into the slot-set menu (0 all, 1 node factors, 2 phase only,
+                        // 3 phase with the node table)
+    uint32_t ntab_n;    // node table entries (2^node factors), 0 without the table
+    uint32_t off_ntab;  // ntab_n words: bit 0 vanishes, bits 1-7 A - B + d_off, bits 8-15 E,
+                        // bits 16-18 the node part of R (mod 8)
+    uint32_t ntab_lds;  // byte offset of the node table in dynamic LDS
     uint32_t node_word0;  // the node-factor slot masks are zero beyond word 0
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j

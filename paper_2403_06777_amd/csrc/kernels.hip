@@ -28,10 +28,15 @@ __device__ void finalize_range(const Partial *partials, uint32_t first, uint32_t
         for (int k = 0; k < 4; ++k) acc[k] += load_i128(partials[first + i].w + 2 * k);
     for (int k = 0; k < 4; ++k) s_sum[threadIdx.x][k] = acc[k];
     __syncthreads();
+    // tree reduction over the workgroup (blockDim.x is a power of two)
+    for (uint32_t half = blockDim.x / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half)
+            for (int k = 0; k < 4; ++k) s_sum[threadIdx.x][k] += s_sum[threadIdx.x + half][k];
+        __syncthreads();
+    }
     if (threadIdx.x != 0) return;
     Zw sum = zw_zero();
-    for (uint32_t t = 0; t < blockDim.x; ++t)
-        for (int k = 0; k < 4; ++k) sum.c[k] += s_sum[t][k];
+    for (int k = 0; k < 4; ++k) sum.c[k] = s_sum[0][k];
     uint32_t flags = 0;
     int32_t e = 0;
     Zw r = sum;
@@ -74,8 +79,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_finalize_batch(const Partial *_
 }  // namespace
 
 size_t dyn_lds_bytes(const ImgHeader &H) {
-    if (H.acc == ACC_CLASS) return (size_t)H.zero_entry * H.q_limbs * 8;
-    return (size_t)H.table_n * 32;
+    const size_t base = H.acc == ACC_CLASS ? (size_t)H.zero_entry * H.q_limbs * 8 : (size_t)H.table_n * 32;
+    return H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4 : base;
 }
 
 uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads) {

@@ -518,6 +518,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         }
     }
     for (const auto &l : w.lin) wt[STAT_R][l.second] += l.first;
+    std::vector<long long> wt_lin(F, 0);  // phase weights of the linear terms alone
+    long long base_lin = 0;
+    for (const auto &l : w.lin) wt_lin[l.second] += l.first;
     // Factors that can vanish (one value of their form gives 1 + w^4 = 0): on every term that
     // survives, their form takes the other value, so the statistic weights of their bit (the
     // factor's own, and those of linear terms sharing the bit) are constants folded into the
@@ -534,6 +537,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             base[s] += wt[s][f] * keep;
             wt[s][f] = 0;
         }
+        base_lin += wt_lin[f] * keep;
+        wt_lin[f] = 0;
     }
     for (int f = 0; f < F; ++f) {
         if (wt[STAT_A][f] > 0) amax += wt[STAT_A][f]; else amin += wt[STAT_A][f];
@@ -551,6 +556,27 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         return SIM_ERANGE;
     }
     if (dmin > dmax) dmin = dmax = 0;
+    const int nd = (int)(dmax - dmin + 1);
+    // accumulation mode: int64 registers when the static bound allows, else per-block class
+    // counters when they fit the LDS budget, else int128 registers
+    uint32_t acc_mode, q_limbs;
+    {
+        long long emax = base[STAT_E];
+        for (int f = 0; f < F; ++f)
+            if (wt[STAT_E][f] > 0) emax += wt[STAT_E][f];
+        emax += std::max(0LL, std::min(amax, bmax));
+        const int hmax = (int)std::max(0LL, emax) / 2;
+        q_limbs = (uint32_t)(hmax / 32 + 1);
+        const long long bound_bits = (long long)w.nodes.size() + w.pe;
+        const size_t class_bytes = (size_t)nd * 16 * q_limbs * 8;
+        if (bound_bits <= 62) acc_mode = ACC_I64;
+        else if (class_bytes <= 48 * 1024) acc_mode = ACC_CLASS;
+        else acc_mode = ACC_I128;
+    }
+    // node table: few node factors (their bits are 0 .. n-1, allocated first), W up to 8
+    const int n_nodes = (int)w.nodes.size();
+    bool use_ntab = n_nodes >= 1 && n_nodes <= kMaxTableNodes && acc_mode != ACC_I128 && W <= 8;
+    for (int j = 0; j < n_nodes && use_ntab; ++j) use_ntab = w.nodes[j].first == j;
 
     // ---- image words
     std::vector<uint32_t> img;
@@ -666,6 +692,15 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.off_slots = (uint32_t)img.size();
     for (int s = 0; s < N_STATS; ++s)
         H.stat_base[s] = (int32_t)(s == STAT_R ? mod8(base[s]) : base[s]);
+    if (use_ntab) {
+        // the table carries the node factors; the phase slots count the linear terms alone
+        for (int s = 0; s < N_STATS; ++s) {
+            std::fill(wt[s].begin(), wt[s].end(), 0LL);
+            H.stat_base[s] = 0;
+        }
+        wt[STAT_R] = wt_lin;
+        H.stat_base[STAT_R] = (int32_t)mod8(base_lin);
+    }
     int active_slots = 0;
     uint32_t active_mask = 0;
     for (int i = 0; i < kSlots; ++i) {
@@ -694,7 +729,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         active_slots += any ? 1 : 0;
         if (any) active_mask |= 1u << i;
     }
-    H.slot_menu = (active_mask & ~kSlotSetPhase) == 0 ? 2u : (active_mask & ~kSlotSetNodes) == 0 ? 1u : 0u;
+    H.slot_menu = use_ntab ? 3u
+                : (active_mask & ~kSlotSetPhase) == 0 ? 2u
+                : (active_mask & ~kSlotSetNodes) == 0 ? 1u : 0u;
     {
         // node-factor bits are allocated first, so with at most 32 node factors the A, B and E
         // masks live in word 0
@@ -706,7 +743,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         }
         H.node_word0 = word0 ? 1u : 0u;
     }
-    active_slots = __builtin_popcount(slot_set_of(H.slot_menu));
+    active_slots = __builtin_popcount(slot_set_of(H.slot_menu) & kSlotSetAll);
     // monomials in packed positions
     const uint64_t walk_mask = g >= 64 ? ~0ull : (((uint64_t)1 << g) - 1);
     std::vector<std::pair<int, uint64_t>> monos;
@@ -872,24 +909,38 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     }
 
     // ---- value table
-    const int nd = (int)(dmax - dmin + 1);
     H.d_off = (int32_t)(-dmin);
     H.table_n = (uint32_t)(nd * 16 + 1);
     H.zero_entry = (uint32_t)(nd * 16);
-    // accumulation mode: int64 registers when the static bound allows, else per-block class
-    // counters when they fit the LDS budget, else int128 registers
+    H.acc = acc_mode;
+    H.q_limbs = q_limbs;
     {
-        long long emax = base[STAT_E];
-        for (int f = 0; f < F; ++f)
-            if (wt[STAT_E][f] > 0) emax += wt[STAT_E][f];
-        emax += std::max(0LL, std::min(amax, bmax));
-        const int hmax = (int)std::max(0LL, emax) / 2;
-        H.q_limbs = (uint32_t)(hmax / 32 + 1);
-        const long long bound_bits = (long long)w.nodes.size() + w.pe;
-        const size_t class_bytes = (size_t)nd * 16 * H.q_limbs * 8;
-        if (bound_bits <= 62) H.acc = ACC_I64;
-        else if (class_bytes <= 48 * 1024) H.acc = ACC_CLASS;
-        else H.acc = ACC_I128;
+        const size_t base_lds = acc_mode == ACC_CLASS ? (size_t)H.zero_entry * q_limbs * 8 : (size_t)H.table_n * 32;
+        H.ntab_lds = (uint32_t)((base_lds + 15) & ~(size_t)15);
+    }
+    // the node table: entry u describes the node factors with bits u of L
+    H.off_ntab = (uint32_t)img.size();
+    if (use_ntab) {
+        H.ntab_n = 1u << n_nodes;
+        for (uint32_t u = 0; u < H.ntab_n; ++u) {
+            long long st[N_STATS] = {0, 0, 0, 0};
+            bool vanish = false;
+            for (int j = 0; j < n_nodes; ++j) {
+                const int bit = (int)(u >> j & 1) ^ (int)(zflip[0] >> j & 1);
+                const int v = bit ? w.nodes[j].second.second : w.nodes[j].second.first;
+                if (v == 4) vanish = true;
+                for (int s2 = 0; s2 < N_STATS; ++s2) st[s2] += fns[s2](v);
+            }
+            uint32_t e = 1u;
+            if (!vanish) {
+                const long long m = std::min(st[STAT_A], st[STAT_B]);
+                const long long dd = st[STAT_A] - st[STAT_B] - dmin;
+                const long long ee = st[STAT_E] + m;
+                const long long rr = mod8(st[STAT_R] + 2 * m);
+                e = ((uint32_t)dd << 1) | ((uint32_t)ee << 8) | ((uint32_t)rr << 16);
+            }
+            img.push_back(e);
+        }
     }
     std::vector<int64_t> table((size_t)H.table_n * 4, 0);
     for (int d = (int)dmin; d <= (int)dmax; ++d)
@@ -917,8 +968,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // program; work on wave-uniform values (list walking, program constants) runs on the
     // scalar unit and is not counted.  The statistics of a term, needed only where no factor
     // vanishes (an exact fraction: the vanishing conditions are affine in x): per mask one AND
-    // and one popcount per word it spans and one add, the table index and shift (10), the accumulation (int64 14,
-    // int128 42, class counter 5) and with monomials the term's phase field (2).
+    // and one popcount-accumulate per word it spans (with the node table: one AND and one LDS
+    // read for all node factors), the table index and shift (8), the accumulation (int64 12,
+    // int128 40, class counter 5) and with monomials the term's phase field (2).
     //  * walks of at least kInnerBits positions: with factors that can vanish, each term's
     //    vanishing test (a W-word compare) and for a surviving term the rebuild of its form
     //    vector (W); otherwise each term's column XOR (W).  Per block: the outer column XOR (W),
@@ -932,14 +984,14 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     {
         const double nz = nonzero_fraction(used, w.nodes);
         P.nonzero_fraction = nz;
-        const double acc_ops = H.acc == ACC_I64 ? 14.0 : H.acc == ACC_I128 ? 42.0 : 5.0;
+        const double acc_ops = H.acc == ACC_I64 ? 12.0 : H.acc == ACC_I128 ? 40.0 : 5.0;
         const bool mono = !w.mono.empty();
         const bool blocks = g >= kInnerBits;
         double slot_ops = 0;
         const uint32_t set = slot_set_of(H.slot_menu) | (H.node_word0 ? kSlotsNodeWord0 : 0u);
         for (int i = 0; i < kSlots; ++i)
-            if (set >> i & 1) slot_ops += 2.0 * slot_words(set, i, W) + 1;
-        const double stats = 10 + acc_ops + slot_ops + (mono ? 2 : 0);
+            if (set >> i & 1) slot_ops += 2.0 * slot_words(set, i, W);
+        const double stats = 8 + acc_ops + slot_ops + (mono ? 2 : 0);
         double ops;
         if (blocks && has_zero) ops = W + nz * (W + stats);
         else if (blocks) ops = W + stats;

@@ -266,3 +266,15 @@ def test_batch_with_programs_above_the_own_launch_size(o2):
             zx.sim_batch_plan_free(plan)
         for h in hs:
             zx.sim_program_free(h)
+
+
+@pytest.mark.parametrize("n_nodes,n_lin,p", [(1, 3, 9), (5, 40, 14), (10, 100, 16), (7, 200, 13), (3, 0, 18)])
+def test_node_table_programs(o2, n_nodes, n_lin, p):
+    # at most 10 node factors (general a, b: some can vanish), linear phase terms sharing forms
+    # with them, widths 1 to 8 words: the node factors come from the node table
+    for seed in range(3):
+        prog = wl.random_program(100 + seed, p, n_nodes=n_nodes, n_pairs=0, n_lin=n_lin, n_mono=p if seed == 2 else 0,
+                                 scalar_range=2, shared_forms=bool(seed % 2))
+        text = prog.to_text()
+        say("node table", n_nodes, n_lin, p, seed, zx.sim_ir_info(text)["n_forms"])
+        assert gpu_value(text) == oracle_value(o2, text)
