@@ -11,8 +11,10 @@ parameters, 64 factors 1 + w^{k l(x)} (k uniform in 1..7, l a random affine form
 """
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -23,6 +25,37 @@ sys.path.insert(0, ROOT)
 METRIC = "exact terms/sec in Z[ω] sums; batched query p50/p99 vs one-launch-per-query"
 # int32 VALU lane operations per second of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# The evaluation kernel and what decides its code for a program.  Figures taken with hardware
+# counters (HBM traffic, instruction counts) are recorded in the kernel's profile together with
+# a fingerprint of these files and reported only while the fingerprint still matches.
+KERNEL_SOURCES = ["paper_2403_06777_amd/csrc/eval_kernels.h", "paper_2403_06777_amd/csrc/image.h",
+                  "paper_2403_06777_amd/csrc/program.cpp", "paper_2403_06777_amd/csrc/zw.h"]
+KERNEL_PROFILE = "profiles/k_eval_kernel_sized_p32.md"
+
+
+def kernel_fingerprint() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_figures() -> dict:
+    """The counter line of the kernel's profile, when it was measured on these kernel sources."""
+    try:
+        with open(os.path.join(ROOT, KERNEL_PROFILE)) as fh:
+            text = fh.read()
+    except OSError:
+        return {}
+    m = re.search(r"^measured: (.*)$", text, re.M)
+    if not m:
+        return {}
+    fields = dict(kv.split("=", 1) for kv in m.group(1).split())
+    if fields.get("kernel-sources") != kernel_fingerprint():
+        return {}
+    return fields
 
 
 def cpu_baseline(ir_text: str, p: int, target_s: float) -> dict:
@@ -226,6 +259,7 @@ def main():
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1000.0
     ops = info["ops_per_term"] * terms
     achieved = ops / avg_kernel_s / 1e12
+    counters = counter_figures()
     out = {
         "metric": METRIC,
         "value": value,
@@ -256,9 +290,14 @@ def main():
             "peak": ALU_PEAK_TOPS,
             "unit": "TOP/s (int32 lane ops)",
             "frac": achieved / ALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": int(counters["traffic-bytes"]) if counters else None,
             "kernel_ms": avg_kernel_s * 1000.0,
             "ops_per_term": info["ops_per_term"],
+            "nonzero_fraction": info["nonzero_fraction"],
+            # rocprofv3 counters of the same kernel (profile), per term (= per lane of a wave step)
+            "counters": ({"valu_instr_per_term": float(counters["valu-per-term"]),
+                          "salu_instr_per_term": float(counters["salu-per-term"]),
+                          "valu_utilisation": float(counters["valu-util"])} if counters else None),
         },
         "result": {"coeffs": [str(c) for c in ref[0]], "sqrt2_exp": ref[1]},
     }
