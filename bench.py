@@ -88,6 +88,70 @@ def percentile(xs, q):
     return xs[min(len(xs) - 1, max(0, int(round(q * (len(xs) - 1)))))]
 
 
+def outcomes_section(stream, seed: int = 1, n_max: int = 1000) -> dict:
+    """Repeated strong simulation (Section 4): one outcome-parametric compilation whose output
+    bits are parameters, then the amplitudes of N output strings in one batched call, against
+    compiling and evaluating each string on its own.  S_N = N (t_c + t_e) / (t_c' + t_e'(N)),
+    with S_inf = (t_c + t_e) / (per-string t_e') and N_inflec = t_c' / (per-string t_e')."""
+    import paper_2403_06777_amd as zx
+    import workloads as wl
+
+    c, _ = wl.circuit_scale(seed)
+    text = wl.circuit_text(c)
+    n = c.n_qubits
+    rng = wl.SplitMix64(0x0C0FFEE, seed)
+    from workloads.circuits import random_bits
+    ys = [random_bits(rng, n) for _ in range(n_max)]
+    t0 = time.perf_counter()
+    h = zx.sim_compile(text, zx.outcomes_query(n), p_cap=40)
+    tc_param = time.perf_counter() - t0
+    info = zx.sim_program_info(h)
+    try:
+        zx.sim_eval_outcomes(h, ys[:4], stream)
+        evals = {}
+        vals = None
+        for N in (1, 10, 100, n_max):
+            reps = 3 if N < n_max else 1
+            best = None
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                v = zx.sim_eval_outcomes(h, ys[:N], stream)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            evals[N] = best
+            if N == n_max:
+                vals = v
+        # the baseline: compile and evaluate each string (a sample of them)
+        K = 64
+        t0 = time.perf_counter()
+        same = True
+        p_fixed = []
+        for i in range(K):
+            h1 = zx.sim_compile(text, zx.amplitude_query(ys[i]), p_cap=40)
+            try:
+                p_fixed.append(zx.sim_program_info(h1)["n_params"])
+                same = same and zx.sim_eval_amplitude(h1, stream) == vals[i]
+            finally:
+                zx.sim_program_free(h1)
+        per_string = (time.perf_counter() - t0) / K
+    finally:
+        zx.sim_program_free(h)
+    te_unit = evals[n_max] / n_max
+    rows = []
+    for N, te in sorted(evals.items()):
+        rows.append({"N": N, "param_total_s": tc_param + te, "per_string_total_s": N * per_string,
+                     "S_N": N * per_string / (tc_param + te)})
+    return {
+        "workload": f"circuit-scale seed {seed}: {n} qubits, 600 Clifford + 40 T gates; N random output strings",
+        "p_outcome_program": info["n_params"], "n_outer": info["n_outer"],
+        "p_per_string_median": sorted(p_fixed)[len(p_fixed) // 2],
+        "compile_param_s": tc_param, "per_string_compile_eval_s": per_string,
+        "param_eval_per_string_s": te_unit,
+        "S_inf": per_string / te_unit, "N_inflec": tc_param / te_unit,
+        "rows": rows, "results_identical": same,
+    }
+
+
 def batch_section(stream, p_cap: int) -> dict:
     """512 amplitude queries of uneven size: one autotuned, graph-captured persistent launch
     versus one launch per query on the same stream; every result must agree exactly."""
@@ -200,6 +264,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-outcomes", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--p-cap", type=int, default=36)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -304,6 +369,8 @@ def main():
     zx.sim_program_free(h)
     if not args.no_batch:
         out["batch"] = batch_section(stream, args.p_cap)
+    if not args.no_outcomes:
+        out["outcomes"] = outcomes_section(stream)
     if not args.no_serve:
         out["serving"] = serve_section(stream, args.serve_requests, min(args.p_cap, 32))
     if not args.no_cpu_baseline:

@@ -75,8 +75,12 @@ typedef struct {
 
 /* A query on a Clifford+T circuit (Section 2.2).  AMPLITUDE: <y|C|0^n> with y_i =
  * out_bits[i] (0/1 bytes, n_qubits of them).  MARGINAL: P(qubit = value) =
- * <0^n| C^dag (|value><value|_qubit (x) I) C |0^n>, the doubled diagram of Fig. 3. */
-enum { SIM_QUERY_AMPLITUDE = 0, SIM_QUERY_MARGINAL = 1 };
+ * <0^n| C^dag (|value><value|_qubit (x) I) C |0^n>, the doubled diagram of Fig. 3.
+ * OUTCOMES: the amplitude with every output bit y_i a Boolean parameter of the program (the
+ * output effects become polar-phase spiders, Section 3.2), so one compilation serves every
+ * output string (the repeated strong simulation of Section 4); out_bits is ignored and the
+ * program's last n_qubits parameters are y_0 .. y_{n-1} (see sim_eval_outcomes). */
+enum { SIM_QUERY_AMPLITUDE = 0, SIM_QUERY_MARGINAL = 1, SIM_QUERY_OUTCOMES = 2 };
 typedef struct {
     uint32_t kind;
     uint32_t n_qubits;
@@ -114,6 +118,9 @@ typedef struct {
                                counted from the packed program (the roofline's work unit) */
     double nonzero_fraction; /* exact fraction of the 2^p assignments on which no factor
                                vanishes (only those terms reach the factor statistics) */
+    uint32_t n_outer;       /* query parameters (OUTCOMES programs: n_qubits, else 0); an output
+                               string costs 2^(p - n_outer) terms */
+    uint32_t reserved_info;
 } sim_info;
 
 /* launch shape of the evaluation kernels; zero fields take the library's choice */
@@ -217,6 +224,15 @@ SIM_API void sim_batch_plan_free(sim_batch_plan *plan);
 SIM_API int sim_eval_ranges(const sim_program *const *progs, const uint64_t *first_slice,
                     const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
                     sim_zomega *raw);
+
+/* Amplitudes of an OUTCOMES program (query kind SIM_QUERY_OUTCOMES) for n output strings:
+ * bits holds n rows of n_outer bytes (0/1), row k = y_0 .. y_{n_outer-1}; out[k] =
+ * <y|C|0^n> in canonical form, bit-identical to compiling and evaluating the AMPLITUDE query
+ * for y.  The query parameters are the top bits of the slice index, so each string is one
+ * contiguous slice range; all n ranges run as one batch (same kernels and launch shapes as
+ * sim_eval_batch).  SIM_EINVAL if prog has no query parameters or a byte is not 0/1. */
+SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *bits, void *stream,
+                              const sim_tuning *t, sim_zomega *out);
 
 /* sim_finalize for n programs in one launch: out[i] = finalised raws[i] of progs[i]. */
 SIM_API int sim_finalize_batch(const sim_program *const *progs, const sim_zomega *raws, size_t n,

@@ -249,7 +249,18 @@ static void read_program(program_t *P) {
     P->p = (int)parse_int(&lx);
     if (P->p < 0 || P->p > 62) die("p out of range");
 
-    expect_word(&lx, "forms");
+    /* optional: the last K parameters are query parameters; a query fixes them, which is a
+       range of the binary order here, so the sum itself is unchanged */
+    char *t = expect_tok(&lx);
+    if (strcmp(t, "outer") == 0) {
+        long long k = parse_int(&lx);
+        if (k < 0 || k > P->p) die("outer out of range");
+        t = expect_tok(&lx);
+    }
+    if (strcmp(t, "forms") != 0) {
+        fprintf(stderr, "o2_eval: expected 'forms', got '%s'\n", t);
+        exit(2);
+    }
     P->n_forms = (int)parse_int(&lx);
     P->forms = calloc(P->n_forms + 1, sizeof(form_t));
     for (int i = 0; i < P->n_forms; i++) {

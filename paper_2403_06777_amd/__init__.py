@@ -10,6 +10,7 @@ from .binding import (  # noqa: F401
     SimError,
     amplitude_query,
     marginal_query,
+    outcomes_query,
     sim_batch_plan_create,
     sim_batch_plan_free,
     sim_batch_plan_run,
@@ -20,6 +21,7 @@ from .binding import (  # noqa: F401
     sim_eval_batch,
     sim_eval_range,
     sim_eval_timed,
+    sim_eval_outcomes,
     sim_eval_ranges,
     sim_finalize,
     sim_finalize_batch,

@@ -25,6 +25,7 @@ SIM_EBUSY = -5
 SIM_ZOMEGA_RAW = 1
 SIM_QUERY_AMPLITUDE = 0
 SIM_QUERY_MARGINAL = 1
+SIM_QUERY_OUTCOMES = 2
 
 _CODES = {SIM_EINVAL: "SIM_EINVAL", SIM_ERANGE: "SIM_ERANGE", SIM_ENOMEM: "SIM_ENOMEM",
           SIM_EDEVICE: "SIM_EDEVICE", SIM_EBUSY: "SIM_EBUSY"}
@@ -75,7 +76,8 @@ class sim_info(ctypes.Structure):
                 ("log2_terms", ctypes.c_double), ("n_eval_params", ctypes.c_uint32),
                 ("is_zero", ctypes.c_uint32), ("compile_seconds", ctypes.c_double),
                 ("t_count", ctypes.c_uint32), ("n_constraints", ctypes.c_uint32),
-                ("ops_per_term", ctypes.c_double), ("nonzero_fraction", ctypes.c_double)]
+                ("ops_per_term", ctypes.c_double), ("nonzero_fraction", ctypes.c_double),
+                ("n_outer", ctypes.c_uint32), ("reserved_info", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -112,6 +114,8 @@ SIGNATURES = [
                                              ctypes.POINTER(_P)]),
     ("sim_batch_plan_run", ctypes.c_int, [_P, _P, ctypes.POINTER(sim_zomega)]),
     ("sim_batch_plan_free", None, [_P]),
+    ("sim_eval_outcomes", ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint8), _P,
+                                         ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
     ("sim_eval_ranges", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                        ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
@@ -187,6 +191,11 @@ def amplitude_query(out_bits: str):
 
 def marginal_query(n_qubits: int, qubit: int, value: int):
     return _query(SIM_QUERY_MARGINAL, n_qubits, None, qubit, value)
+
+
+def outcomes_query(n_qubits: int):
+    """Every output bit a parameter: one compilation for all output strings."""
+    return _query(SIM_QUERY_OUTCOMES, n_qubits, None)
 
 
 def _opts(p_cap: int = 0, eliminate_constraints: bool = True):
@@ -337,6 +346,16 @@ def sim_eval_ranges(progs: Sequence[int], first_slices: Sequence[int], n_slices:
     outs = (sim_zomega * max(1, n))()
     _check(lib().sim_eval_ranges(_prog_array(progs), firsts, counts, n, _stream(stream), _tuning(tuning), outs))
     return [outs[i].coeffs() for i in range(n)]
+
+
+def sim_eval_outcomes(prog: int, out_strings: Sequence[str], stream=None, tuning: Optional[dict] = None):
+    """Amplitudes <y|C|0> of an OUTCOMES program for output strings such as "0110"."""
+    n = len(out_strings)
+    k = len(out_strings[0]) if n else 0
+    bits = (ctypes.c_uint8 * max(1, n * k))(*[1 if ch == "1" else 0 for y in out_strings for ch in y])
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_eval_outcomes(prog, n, bits, _stream(stream), _tuning(tuning), outs))
+    return [_scalar(outs[i]) for i in range(n)]
 
 
 def sim_batch_plan_create(progs: Sequence[int], tuning: Optional[dict] = None, stream=None) -> int:

@@ -324,6 +324,7 @@ void fill_info(const PackedProgram &pk, double compile_seconds, uint32_t t_count
     out->n_constraints = n_constraints;
     out->ops_per_term = pk.ops_per_term;
     out->nonzero_fraction = pk.nonzero_fraction;
+    out->n_outer = (uint32_t)pk.outer;
 }
 }  // namespace
 
@@ -801,6 +802,27 @@ extern "C" {
 int sim_eval_batch(const sim_program *const *ps, size_t n, void *stream, const sim_tuning *t, sim_zomega *out) {
     if (n && !out) return fail(SIM_EINVAL, "null output");
     return run_batch(ps, n, nullptr, nullptr, false, stream, t, out);
+}
+
+int sim_eval_outcomes(const sim_program *P, size_t n, const uint8_t *bits, void *stream, const sim_tuning *t,
+                      sim_zomega *out) {
+    if (!P || (n && (!bits || !out))) return fail(SIM_EINVAL, "null argument");
+    const int k = P->pk.outer;
+    if (k <= 0) return fail(SIM_EINVAL, "the program has no query parameters (compile an OUTCOMES query)");
+    // the query parameters are the top k bits of the slice index
+    const uint32_t low = (uint32_t)(P->pk.hdr.pe - P->pk.hdr.g) - (uint32_t)k;
+    std::vector<const sim_program *> ps(n, P);
+    std::vector<uint64_t> first(n), count(n, (uint64_t)1 << low);
+    for (size_t r = 0; r < n; ++r) {
+        uint64_t y = 0;
+        for (int i = 0; i < k; ++i) {
+            const uint8_t b = bits[r * (size_t)k + i];
+            if (b > 1) return fail(SIM_EINVAL, "output bits must be 0 or 1");
+            y |= (uint64_t)b << i;
+        }
+        first[r] = y << low;
+    }
+    return run_batch(ps.data(), n, first.data(), count.data(), false, stream, t, out);
 }
 
 int sim_eval_ranges(const sim_program *const *ps, const uint64_t *first_slice, const uint64_t *n_slices, size_t n,

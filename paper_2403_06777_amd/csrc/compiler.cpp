@@ -27,6 +27,10 @@
 // 4. Constraints.  A factor 1 + w^{4 (c xor l(x))} is 2 or 0: with constraint elimination on,
 //    one parameter of l is solved for and substituted into every form, which halves the term
 //    count per constraint without changing the sum.
+// 5. Outcome-parametric queries.  With every output bit y_i a parameter, the effect <y_i| is a
+//    spider of polar phase pi (c xor y_i) (Section 3.2), the simplification runs unchanged, and
+//    the y_i are never solved for: the program's last n parameters are y_0 .. y_{n-1}, so one
+//    compilation answers every output string.
 // The scalar is tracked exactly in Z[w] with a power of sqrt2 throughout.
 
 #include "compiler.h"
@@ -206,6 +210,7 @@ struct Builder {
     std::vector<int> phase;                      // a_v
     std::vector<std::pair<int, int>> toggles;    // Hadamard edges, toggled
     std::map<std::vector<int>, int> pm;          // phase on a parity of spiders
+    std::vector<std::pair<int, int>> polar;      // (spider, parameter): phase + pi x_parameter
     Scalar sc;
 
     int new_spider(int a) {
@@ -242,6 +247,13 @@ struct Builder {
         }
         int h = new_spider(((L.c ^ y) & 1) ? 4 : 0);
         for (int s : L.S) toggles.push_back({h, s});
+        sc.e -= 2;
+    }
+    // <y| with y = parameter k: the spider of the effect gets the polar phase pi (c xor x_k)
+    void constrain_param(const Label &L, int k) {
+        int h = new_spider((L.c & 1) ? 4 : 0);
+        for (int s : L.S) toggles.push_back({h, s});
+        polar.push_back({h, k});
         sc.e -= 2;
     }
     // phases on parities -> graph-like form
@@ -514,8 +526,9 @@ struct Graph {
 
 // ------------------------------------------------------------------ IR emission
 
-void emit_ir(const Emitted &em, int n_params, const Scalar &sc, bool eliminate, int p_cap, IrProgram *out,
-             CompileStats *stats) {
+// Parameters 0 .. n_outer-1 are query parameters: never eliminated, emitted last (in order).
+void emit_ir(const Emitted &em, int n_params, int n_outer, const Scalar &sc, bool eliminate, int p_cap,
+             IrProgram *out, CompileStats *stats) {
     Scalar s = sc;
     std::vector<std::pair<Form, int>> nodes = em.nodes, lins = em.lins;
     std::vector<char> gone(n_params, 0);
@@ -533,8 +546,15 @@ void emit_ir(const Emitted &em, int n_params, const Scalar &sc, bool eliminate, 
                 s.one_plus_w(a + 4 * f.c);
                 continue;
             }
-            // nonzero iff l(x) = a/4: solve for the lowest parameter of l
-            const int k = f.m.lowest();
+            // nonzero iff l(x) = a/4: solve for the lowest decomposition parameter of l (a
+            // constraint on query parameters alone stays a factor)
+            int k = -1;
+            for (int b = n_outer; b < n_params && k < 0; ++b)
+                if (f.m.test(b)) k = b;
+            if (k < 0) {
+                kept.push_back(nodes[i]);
+                continue;
+            }
             const int rhs = (a / 4) ^ f.c;
             auto subst = [&](Form &g) {
                 if (g.m.test(k)) {
@@ -551,14 +571,16 @@ void emit_ir(const Emitted &em, int n_params, const Scalar &sc, bool eliminate, 
         }
         nodes = kept;
     }
-    // renumber surviving parameters
+    // renumber surviving parameters: decomposition parameters first, then the query parameters
     std::vector<int> newidx(n_params, -1);
     int p = 0;
-    for (int k = 0; k < n_params; ++k)
+    for (int k = n_outer; k < n_params; ++k)
         if (!gone[k]) newidx[k] = p++;
+    const int p_decomp = p;
+    for (int k = 0; k < n_outer; ++k) newidx[k] = p++;
     if (p > 62) throw CompileError{SIM_ERANGE, "p = " + std::to_string(p) + " exceeds 62"};
-    if (p > p_cap)
-        throw CompileError{SIM_ERANGE, "p = " + std::to_string(p) + " exceeds the cap " + std::to_string(p_cap)};
+    if (p_decomp > p_cap)
+        throw CompileError{SIM_ERANGE, "p = " + std::to_string(p_decomp) + " exceeds the cap " + std::to_string(p_cap)};
     auto remap = [&](const PBits &m) {
         uint64_t r = 0;
         for (int k = 0; k < n_params; ++k)
@@ -567,6 +589,7 @@ void emit_ir(const Emitted &em, int n_params, const Scalar &sc, bool eliminate, 
     };
     IrProgram P;
     P.p = p;
+    P.outer = n_outer;
     std::map<std::pair<uint64_t, int>, int> form_ids;
     auto form_of = [&](const Form &f) {
         auto key = std::make_pair(remap(f.m), f.c);
@@ -623,10 +646,15 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
         std::vector<Gate> seq;
         int proj_q = -1, proj_v = 0;
         size_t proj_at = 0;
+        int n_outer = 0;
         if (q.kind == SIM_QUERY_AMPLITUDE) {
             if (!q.out_bits) throw CompileError{SIM_EINVAL, "amplitude query without output bits"};
             for (int i = 0; i < n; ++i)
                 if (q.out_bits[i] > 1) throw CompileError{SIM_EINVAL, "output bits must be 0 or 1"};
+            seq = gates;
+        } else if (q.kind == SIM_QUERY_OUTCOMES) {
+            if (n > 62) throw CompileError{SIM_ERANGE, "more than 62 output parameters"};
+            n_outer = n;
             seq = gates;
         } else if (q.kind == SIM_QUERY_MARGINAL) {
             if (q.qubit >= (uint32_t)n || q.value > 1) throw CompileError{SIM_EINVAL, "bad marginal query"};
@@ -685,7 +713,10 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
                 }
             }
         }
-        for (int i = 0; i < n; ++i) B.constrain(wire[i], q.kind == SIM_QUERY_AMPLITUDE ? (int)q.out_bits[i] : 0);
+        for (int i = 0; i < n; ++i) {
+            if (q.kind == SIM_QUERY_OUTCOMES) B.constrain_param(wire[i], i);
+            else B.constrain(wire[i], q.kind == SIM_QUERY_AMPLITUDE ? (int)q.out_bits[i] : 0);
+        }
         B.flush_phases();
 
         Emitted em;
@@ -704,6 +735,8 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
             G.sc = &sc;
             G.em = &em;
             for (const auto &t : B.toggles) G.toggle(t.first, t.second);
+            for (const auto &pv : B.polar) G.l[pv.first].flip(pv.second);
+            G.n_params = n_outer;  // parameters 0 .. n_outer-1 are the output bits
             for (int v = 0; v < G.n; ++v) t_like += G.a[v] & 1;
             const int p_limit = kParamWords * 64;
             while (!sc.zero && G.step(p_limit)) {
@@ -711,7 +744,7 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
             n_params = G.n_params;
         }
         stats->t_count = t_like;
-        emit_ir(em, n_params, sc, opts.eliminate_constraints, opts.p_cap, out, stats);
+        emit_ir(em, std::max(n_params, n_outer), n_outer, sc, opts.eliminate_constraints, opts.p_cap, out, stats);
     } catch (const CompileError &ce) {
         *err = ce.msg;
         return ce.code;

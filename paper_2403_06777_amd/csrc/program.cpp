@@ -145,6 +145,10 @@ bool ir_parse(const char *text, size_t len, IrProgram *out, std::string *err) {
         if (get_int(&lx, 1, 1) != 1) throw ParseError{"unsupported IR version"};
         expect(&lx, "p");
         P.p = (int)get_int(&lx, 0, 62);
+        if (lx.pos < lx.toks.size() && lx.toks[lx.pos].first == "outer") {
+            ++lx.pos;
+            P.outer = (int)get_int(&lx, 0, P.p);
+        }
         expect(&lx, "forms");
         long long nf = get_int(&lx, 0, 1 << 20);
         for (long long i = 0; i < nf; ++i) {
@@ -212,7 +216,9 @@ bool ir_parse(const char *text, size_t len, IrProgram *out, std::string *err) {
 
 std::string ir_print(const IrProgram &P) {
     std::ostringstream os;
-    os << "zxir 1\np " << P.p << "\nforms " << P.forms.size() << "\n";
+    os << "zxir 1\np " << P.p << "\n";
+    if (P.outer) os << "outer " << P.outer << "\n";
+    os << "forms " << P.forms.size() << "\n";
     for (const auto &f : P.forms) os << "f " << f.cst << " " << std::hex << f.mask << std::dec << "\n";
     os << "nodes " << P.nodes.size() << "\n";
     for (const auto &n : P.nodes) os << "n " << n.form << " " << n.a << " " << n.b << "\n";
@@ -411,17 +417,20 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // blocks of a walk, so long walks cost no balance, but a wave holds 64 slices, so the walk
     // leaves at least 64 slices where the program is large enough.
     const int want = w.mono.empty() ? 8 : 12;
-    int g_orig = std::min(p, std::min(max_walk_bits, want));
-    if (p - g_orig < 6) g_orig = std::max(std::min(p, kInnerBits), p - 6);
+    const int inner_p = p - ir.outer;  // query parameters are never walked
+    int g_orig = std::min(inner_p, std::min(max_walk_bits, want));
+    if (p - g_orig < 6) g_orig = std::max(std::min(inner_p, kInnerBits), p - 6);
+    g_orig = std::min(g_orig, inner_p);
     if (!w.mono.empty()) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
     if (p - g_orig > 62) g_orig = p - 62;
     if (!w.mono.empty() && q + g_orig > 16) {
         *err = "too many pair factors together with variable monomials (at most 16 walk bits)";
         return SIM_ERANGE;
     }
-    // walked parameters: fewest monomials first (they flip most often); high: index order
-    std::vector<int> order(p);
-    for (int i = 0; i < p; ++i) order[i] = i;
+    // walked parameters: fewest monomials first (they flip most often); high: index order, so
+    // the query parameters (the last `outer`) are the top slice bits
+    std::vector<int> order(inner_p);
+    for (int i = 0; i < inner_p; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return inc[a] < inc[b]; });
     std::vector<int> walked(order.begin(), order.begin() + g_orig);
     std::sort(walked.begin(), walked.end(), [&](int a, int b) {
@@ -448,6 +457,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         return SIM_ERANGE;
     }
     P.walk_bits = g_orig;
+    P.outer = ir.outer;
     P.n_slices = (uint64_t)1 << (w.pe - g);
     auto permute = [&](uint64_t m) {
         uint64_t r = 0;

@@ -30,6 +30,7 @@ struct IrMono {
 
 struct IrProgram {
     int p = 0;
+    int outer = 0;  // the last `outer` parameters are query parameters (kept as top slice bits)
     std::vector<IrForm> forms;
     std::vector<IrNode> nodes;
     std::vector<IrPair> pairs;
@@ -49,6 +50,7 @@ struct PackedProgram {
     int p = 0;                  // parameters of the program (terms = 2^p)
     int q = 0;                  // pair factors turned into walk parameters
     int walk_bits = 0;          // original parameters enumerated inside a slice
+    int outer = 0;              // query parameters: the top `outer` bits of a slice index
     uint64_t n_slices = 1;
     Zw c0 = zw_one();           // constant, canonical
     int32_t e = 0;

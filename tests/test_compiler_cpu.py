@@ -166,3 +166,62 @@ def test_compile_is_fast_and_deterministic():
     b = zx.sim_compile_to_ir(text, zx.amplitude_query(y))
     assert a[0] == b[0]
     assert time.time() - t0 < 5
+
+
+def _ir_header(ir):
+    """p, query parameters, scalar and sqrt2 exponent of an IR text"""
+    toks = ir.split()
+    p = int(toks[toks.index("p") + 1])
+    outer = int(toks[toks.index("outer") + 1]) if "outer" in toks else 0
+    k = toks.index("scalar")
+    return p, outer, tuple(int(t) for t in toks[k + 1:k + 5]), int(toks[k + 5])
+
+
+def _outcome_value(o2, ir, y):
+    # the query parameters are the last ones, y_i <-> parameter p - n + i: in the binary order
+    # a string is the contiguous range of its top bits
+    p, outer, scalar, e = _ir_header(ir)
+    low = p - outer
+    idx = sum(1 << i for i, ch in enumerate(y) if ch == "1")
+    raw = o2.evaluate(ir, first=idx << low, count=1 << low)["raw"]
+    return zw.canonical(zw.mul(scalar, raw), e)
+
+
+def test_outcome_parametric_compile_all_strings(o2):
+    # one compilation, every output string: equal to the exact state vector entry and to the
+    # program compiled for that string alone (Section 4's repeated strong simulation)
+    for seed in range(12):
+        c, _ = wl.tiny_circuit(seed)
+        text = wl.circuit_text(c)
+        ir, info = zx.sim_compile_to_ir(text, zx.outcomes_query(c.n_qubits))
+        p, outer, _, _ = _ir_header(ir)
+        assert outer == c.n_qubits == info["n_outer"] and p >= outer
+        st = sv.exact_state(text)
+        for idx in range(1 << c.n_qubits):
+            y = "".join("1" if idx >> i & 1 else "0" for i in range(c.n_qubits))
+            got = _outcome_value(o2, ir, y)
+            assert got == zw.canonical(st.vec[idx], -st.k), (seed, y)
+            if idx % 21 == 0:
+                assert got == compiled_value(o2, text, zx.amplitude_query(y))[0]
+
+
+def test_outcome_parametric_random_circuits(o2):
+    for seed in range(20):
+        n = 2 + seed % 6
+        c = _rand_circuit(300 + seed, n, 12 + 3 * seed, seed % 9)
+        text = wl.circuit_text(c)
+        ir, info = zx.sim_compile_to_ir(text, zx.outcomes_query(n), eliminate_constraints=bool(seed % 2))
+        st = sv.exact_state(text)
+        for idx in range(1 << n):
+            y = "".join("1" if idx >> i & 1 else "0" for i in range(n))
+            assert _outcome_value(o2, ir, y) == zw.canonical(st.vec[idx], -st.k), (seed, y)
+
+
+def test_outcome_parametric_query_parameters_are_reported():
+    c, _ = wl.tiny_circuit(3)
+    ir, _ = zx.sim_compile_to_ir(wl.circuit_text(c), zx.outcomes_query(c.n_qubits))
+    info = zx.sim_ir_info(ir)
+    p, outer, _, _ = _ir_header(ir)
+    assert info["n_outer"] == outer == c.n_qubits and info["n_params"] == p
+    # the IR round-trips with its query parameters
+    assert zx.sim_ir_info(ir)["n_slices"] >= 1 << outer

@@ -73,3 +73,55 @@ def test_batch_queries_subset(o2):
     finally:
         for h in hs:
             zx.sim_program_free(h)
+
+
+def _strings(n):
+    return ["".join("1" if idx >> i & 1 else "0" for i in range(n)) for idx in range(1 << n)]
+
+
+def test_outcome_parametric_all_strings_on_gpu():
+    # one compilation per circuit; every output string's amplitude from one batched call
+    from oracle import zomega as zw
+    for seed in range(10):
+        c, _ = wl.tiny_circuit(seed)
+        text = wl.circuit_text(c)
+        h = zx.sim_compile(text, zx.outcomes_query(c.n_qubits))
+        try:
+            ys = _strings(c.n_qubits)
+            say("outcomes tiny", seed, zx.sim_program_info(h)["n_params"])
+            got = zx.sim_eval_outcomes(h, ys)
+            st = sv.exact_state(text)
+            assert got == [zw.canonical(st.vec[i], -st.k) for i in range(len(ys))], seed
+            # a repeated call on a subset equals the first
+            assert zx.sim_eval_outcomes(h, ys[5:9]) == got[5:9]
+        finally:
+            zx.sim_program_free(h)
+
+
+def test_outcome_parametric_matches_per_string_compilation():
+    # larger circuits: sampled strings against compiling each string on its own
+    for seed in range(4):
+        rng = wl.SplitMix64(720, seed)
+        n = 10 + 2 * seed
+        c = wl.random_clifford_t(rng, n, 150 + 40 * seed, 10 + 2 * seed)
+        text = wl.circuit_text(c)
+        h = zx.sim_compile(text, zx.outcomes_query(n), p_cap=40)
+        try:
+            info = zx.sim_program_info(h)
+            ys = ["".join("1" if rng.bernoulli(0.5) else "0" for _ in range(n)) for _ in range(12)]
+            say("outcomes vs per-string", seed, n, info["n_params"], info["n_outer"])
+            got = zx.sim_eval_outcomes(h, ys)
+            for y, g in zip(ys, got):
+                assert g == gpu_compiled(text, zx.amplitude_query(y), p_cap=40)[0], (seed, y)
+        finally:
+            zx.sim_program_free(h)
+
+
+def test_outcome_parametric_rejects_plain_programs():
+    c, y = wl.tiny_circuit(1)
+    h = zx.sim_compile(wl.circuit_text(c), zx.amplitude_query(y))
+    try:
+        with pytest.raises(zx.SimError):
+            zx.sim_eval_outcomes(h, [y])
+    finally:
+        zx.sim_program_free(h)
