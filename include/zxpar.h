@@ -126,7 +126,8 @@ typedef struct {
 /* launch shape of the evaluation kernels; zero fields take the library's choice */
 typedef struct {
     uint32_t block_threads;   /* 64..1024, multiple of 64 */
-    uint32_t blocks_per_cu;   /* resident blocks per compute unit in the persistent grid */
+    uint32_t blocks_per_cu;   /* single-program grid: blocks per compute unit (0: as many as
+                                 are resident at once); batches: unused */
     uint32_t walk_bits;       /* upper bound on the Gray-walk length log2 */
     uint32_t chunk_log2;      /* batch: log2 of terms per work item */
 } sim_tuning;
@@ -201,13 +202,15 @@ SIM_API int sim_eval_range(const sim_program *prog, uint64_t first_slice, uint64
  * the device). */
 SIM_API int sim_finalize(const sim_program *prog, const sim_zomega *raw, void *stream, sim_zomega *out);
 
-/* Many programs of uneven size in one persistent launch: work items of 2^chunk_log2 terms
- * are pulled from a device queue; per-item partials are summed per program in a fixed
- * order, so each result is bit-identical to sim_eval_amplitude.  t may be NULL. */
+/* Many programs of uneven size in one launch per kernel variant (variants run concurrently):
+ * work items of 2^chunk_log2 terms (default: at least 2^20), one workgroup each; programs of
+ * 2^26 terms or more get a single-program launch of their own beside them.  Per-item partials
+ * are summed per program in a fixed order, so each result is bit-identical to
+ * sim_eval_amplitude.  t may be NULL. */
 SIM_API int sim_eval_batch(const sim_program *const *progs, size_t n, void *stream,
                    const sim_tuning *t, sim_zomega *out);
 
-/* Same as sim_eval_batch, but the launch sequence (queue reset, persistent kernel,
+/* Same as sim_eval_batch, but the launch sequence (evaluation kernels on forked streams,
  * finaliser, result copy) is captured once into a hipGraph held by the plan and replayed
  * by sim_batch_plan_run.  The plan keeps the programs' device images referenced; the
  * programs must outlive the plan. */

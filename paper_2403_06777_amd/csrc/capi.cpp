@@ -58,7 +58,7 @@ struct DeviceState {
     bool ready = false;
     int cus = 0;
     std::mutex mu;
-    DevBuf partials, result, queue, stage;
+    DevBuf partials, result, stage;
     void *host_result = nullptr;  // pinned
     size_t host_cap = 0;
     void *host_stage = nullptr;   // pinned staging of batch layouts
@@ -535,6 +535,7 @@ constexpr uint64_t kBigTerms = (uint64_t)1 << 26;
 constexpr uint32_t kBigThreads = 256;
 
 constexpr uint64_t kMaxItemsPerProgram = 4096;
+constexpr uint32_t kMinItemLog2 = 20;
 
 int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const uint64_t *first_slice,
                  const uint64_t *n_slices, bool raw, const sim_tuning *t, BatchLayout *L) {
@@ -599,13 +600,17 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
         if (H.g > g.h0.g) g.h0.g = H.g;  // flush interval follows the longest walk of the group
         uint64_t s0 = first_slice ? first_slice[i] : 0;
         uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;
-        // slices per item: with an explicit chunk, 2^chunk_log2 terms; by default about one
-        // slice per thread of a workgroup, and at most kMaxItemsPerProgram items per program
+        // slices per item: with an explicit chunk, 2^chunk_log2 terms; by default at least one
+        // slice per thread of a workgroup and 2^kMinItemLog2 terms (the per-item costs of the
+        // queue, the LDS set-up and the reduction stay small), and at most kMaxItemsPerProgram
+        // items per program
         uint64_t per;
         if (t && t->chunk_log2) {
             per = t->chunk_log2 > H.g ? ((uint64_t)1 << std::min<uint32_t>(62, t->chunk_log2 - H.g)) : 1;
         } else {
-            per = std::max<uint64_t>(256, (cnt + kMaxItemsPerProgram - 1) / kMaxItemsPerProgram);
+            const uint64_t min_terms = H.g < kMinItemLog2 ? (uint64_t)1 << (kMinItemLog2 - H.g) : 1;
+            per = std::max<uint64_t>(std::max<uint64_t>(256, min_terms),
+                                     (cnt + kMaxItemsPerProgram - 1) / kMaxItemsPerProgram);
         }
         L->firsts[i] = (uint32_t)L->items.size();
         for (uint64_t s = 0; s < cnt; s += per) {
@@ -634,11 +639,10 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
 
 // enqueues the batch on `stream` (no host synchronisation); buffers must be uploaded
 int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuning *t, hipStream_t stream,
-                  const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items, uint32_t *d_queue,
+                  const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items,
                   Partial *d_parts, const uint32_t *d_firsts, const uint32_t *d_counts, const FinalArgs *d_args,
                   DevResult *d_out) {
     const uint32_t threads = pick_threads(t);
-    const uint32_t bpc = t && t->blocks_per_cu ? t->blocks_per_cu : 8u;
     const size_t ng = L.groups.size();
     // kernel variants run concurrently: group k on auxiliary stream k % kAux, forked from and
     // joined back into `stream` with events (also valid under stream capture)
@@ -652,15 +656,11 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
     uint32_t gi = 0;
     for (const auto &g : L.groups) {
         hipStream_t s = fork ? D.aux[gi % kAux] : stream;
-        uint32_t share = fork ? std::max<uint32_t>(1, (uint32_t)((uint64_t)std::max(1, D.cus) * bpc)) : 0;
-        uint32_t blocks = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>(g.n_items, share ? share : (uint64_t)std::max(1, D.cus) * bpc));
-        HIP_TRY(launch_reset_queue(d_queue + gi, s));
-        HIP_TRY(launch_eval_batch(g.h0, d_hdrs, d_imgs, d_items + g.item_first, g.n_items, d_queue + gi, d_parts,
-                                  blocks, threads, g.lds_bytes, s));
+        HIP_TRY(launch_eval_batch(g.h0, d_hdrs, d_imgs, d_items + g.item_first, g.n_items, d_parts, threads,
+                                  g.lds_bytes, s));
         ++gi;
     }
-    // the large programs one after another on the caller's stream, beside the queued groups
+    // the large programs one after another on the caller's stream, beside the item groups
     for (const auto &b : L.big)
         HIP_TRY(launch_eval(L.hdrs[b.prog], (const void *)(uintptr_t)L.imgs[b.prog], b.s0, b.count,
                             d_parts + b.slot, b.blocks, kBigThreads, stream));
@@ -715,7 +715,6 @@ int upload_layout(DeviceState &D, const BatchLayout &L, size_t n, hipStream_t st
     if (!L.items.empty()) memcpy(h + o_items, L.items.data(), L.items.size() * sizeof(WorkItem));
     if ((rc = ensure(D.partials, std::max<size_t>(1, L.n_partials) * sizeof(Partial)))) return rc;
     if ((rc = ensure(D.result, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
-    if ((rc = ensure(D.queue, std::max<size_t>(1, L.groups.size()) * 4))) return rc;
     if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
     HIP_TRY(hipMemcpyAsync(D.stage.ptr, h, total, hipMemcpyHostToDevice, st));
     char *d = (char *)D.stage.ptr;
@@ -759,7 +758,7 @@ int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, con
     LayoutPtrs LP;
     if ((rc = upload_layout(D, L, n, st, &LP))) return rc;
     if (!L.live.empty()) {
-        if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items, (uint32_t *)D.queue.ptr,
+        if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items,
                                 (Partial *)D.partials.ptr, LP.firsts, LP.counts, LP.args,
                                 (DevResult *)D.result.ptr)))
             return rc;
@@ -791,7 +790,7 @@ struct sim_batch_plan {
     BatchLayout L;
     sim_tuning tuning;
     bool has_tuning = false;
-    DevBuf hdrs, imgs, items, parts, firsts, counts, args, result, queue;
+    DevBuf hdrs, imgs, items, parts, firsts, counts, args, result;
     void *host_result = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -885,7 +884,7 @@ void sim_batch_plan_free(sim_batch_plan *plan) {
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     for (DevBuf *b : {&plan->hdrs, &plan->imgs, &plan->items, &plan->parts, &plan->firsts, &plan->counts,
-                      &plan->args, &plan->result, &plan->queue})
+                      &plan->args, &plan->result})
         if (b->ptr) (void)hipFree(b->ptr);
     if (plan->host_result) (void)hipHostFree(plan->host_result);
     (void)hipSetDevice(cur);
@@ -916,7 +915,7 @@ int sim_batch_plan_create(const sim_program *const *ps, size_t n, const sim_tuni
         (rc = alloc(plan->items, L.items.size() * sizeof(WorkItem))) ||
         (rc = alloc(plan->parts, L.n_partials * sizeof(Partial))) || (rc = alloc(plan->firsts, n * 4)) ||
         (rc = alloc(plan->counts, n * 4)) || (rc = alloc(plan->args, n * sizeof(FinalArgs))) ||
-        (rc = alloc(plan->result, n * sizeof(DevResult))) || (rc = alloc(plan->queue, L.groups.size() * 4 + 4)))
+        (rc = alloc(plan->result, n * sizeof(DevResult))))
         return rc;
     HIP_TRY(hipHostMalloc(&plan->host_result, std::max<size_t>(1, n) * sizeof(DevResult), hipHostMallocDefault));
     if (n) {
@@ -937,7 +936,7 @@ int sim_batch_plan_create(const sim_program *const *ps, size_t n, const sim_tuni
         if (e == hipSuccess) {
             rc = enqueue_batch(D, L, n, plan->has_tuning ? &plan->tuning : nullptr, cap,
                                (const ImgHeader *)plan->hdrs.ptr, (const uint64_t *)plan->imgs.ptr,
-                               (const WorkItem *)plan->items.ptr, (uint32_t *)plan->queue.ptr,
+                               (const WorkItem *)plan->items.ptr,
                                (Partial *)plan->parts.ptr, (const uint32_t *)plan->firsts.ptr,
                                (const uint32_t *)plan->counts.ptr, (const FinalArgs *)plan->args.ptr,
                                (DevResult *)plan->result.ptr);

@@ -755,38 +755,30 @@ __global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t
     block_reduce_store(out, partials + blockIdx.x);
 }
 
+// One workgroup per work item (slices [s_begin, s_end) of one program): the hardware dispatcher
+// balances the items, and the kernel keeps the live state of the single-program kernel (a
+// persistent item loop would cost registers, and with them resident waves).
 template <int W, bool MONO, int ACC, uint32_t SET>
 __global__ __launch_bounds__(kMaxThreads) void k_eval_batch(const ImgHeader *__restrict__ hdrs,
                                                             const uint64_t *__restrict__ imgs,
                                                             const WorkItem *__restrict__ items, uint32_t n_items,
-                                                            uint32_t *__restrict__ queue, uint64_t chunk_units,
-                                                            Partial *__restrict__ partials) {
+                                                            uint64_t chunk_units, Partial *__restrict__ partials) {
     extern __shared__ int64_t s_dyn[];
     __shared__ uint4 s_queue[kCompact<W> ? kMaxThreads / 64 * kQueueCap * kQueueWords<W> / 4 : 1];
-    __shared__ uint32_t s_item;
-    uint32_t loaded = 0xffffffffu;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
-        __syncthreads();
-        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (it >= n_items) break;
-        const WorkItem wi = items[it];
-        const uint32_t prog = __builtin_amdgcn_readfirstlane(wi.prog);
-        const ImgHeader H = hdrs[prog];
-        const uint8_t *img = reinterpret_cast<const uint8_t *>(imgs[prog]);
-        const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
-        if (prog != loaded || ACC == ACC_CLASS) {
-            prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
-            loaded = prog;
-        }
-        i128 out[4] = {0, 0, 0, 0};
-        run_range<W, MONO, ACC, SET>(H, img, wi.s_begin, wi.s_end - wi.s_begin,
-                                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), blockDim.x >> 6,
-                                     chunk_units, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
-                                     reinterpret_cast<uint32_t *>(s_queue), out);
-        block_reduce_store(out, partials + wi.out_slot);
-    }
+    const uint32_t it = blockIdx.x;
+    if (it >= n_items) return;
+    const WorkItem wi = items[it];
+    const uint32_t prog = __builtin_amdgcn_readfirstlane(wi.prog);
+    const ImgHeader H = hdrs[prog];
+    const uint8_t *img = reinterpret_cast<const uint8_t *>(imgs[prog]);
+    const int64_t *gtab = reinterpret_cast<const int64_t *>(img + H.table_byte_off);
+    prepare_lds<ACC>(H, gtab, s_dyn, reinterpret_cast<unsigned long long *>(s_dyn));
+    i128 out[4] = {0, 0, 0, 0};
+    run_range<W, MONO, ACC, SET>(H, img, wi.s_begin, wi.s_end - wi.s_begin,
+                                 __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), blockDim.x >> 6, chunk_units,
+                                 s_dyn, reinterpret_cast<unsigned long long *>(s_dyn),
+                                 reinterpret_cast<uint32_t *>(s_queue), out);
+    block_reduce_store(out, partials + wi.out_slot);
 }
 
 template <typename K>
@@ -810,13 +802,13 @@ hipError_t launch_eval_t(const ImgHeader &H, const void *dimg, uint64_t s_begin,
 
 template <int W, bool MONO, int ACC, uint32_t SET>
 hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                          const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
-                          uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream) {
+                          const WorkItem *d_items, uint32_t n_items, Partial *partials, uint32_t threads,
+                          uint32_t lds_bytes, hipStream_t stream) {
     auto kern = k_eval_batch<W, MONO, ACC, SET>;
     hipError_t e = set_lds(kern, lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds_bytes, stream, d_hdrs, d_imgs, d_items, n_items,
-                       d_queue, chunk_units_for(H0, threads), partials);
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(threads), lds_bytes, stream, d_hdrs, d_imgs, d_items, n_items,
+                       chunk_units_for(H0, threads), partials);
     return hipGetLastError();
 }
 
@@ -886,11 +878,10 @@ hipError_t occupancy_wm(const ImgHeader &H, uint32_t threads, int *blocks_per_cu
 
 template <int W, bool MONO>
 hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                           const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
-                           uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream) {
+                           const WorkItem *d_items, uint32_t n_items, Partial *partials, uint32_t threads,
+                           uint32_t lds_bytes, hipStream_t stream) {
 #define CALL_BATCH(w, m, a, set) \
-    launch_batch_t<w, m, a, set>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, \
-                                 lds_bytes, stream)
+    launch_batch_t<w, m, a, set>(H0, d_hdrs, d_imgs, d_items, n_items, partials, threads, lds_bytes, stream)
     const bool N0_ = H0.node_word0 != 0;
     DISPATCH_WM(W, MONO, H0.acc, H0.slot_menu, CALL_BATCH);
 #undef CALL_BATCH
@@ -901,5 +892,5 @@ hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const u
     template hipError_t launch_eval_wm<w, m>(const ImgHeader &, const void *, uint64_t, uint64_t,     \
                                              Partial *, uint32_t, uint32_t, hipStream_t);             \
     template hipError_t launch_batch_wm<w, m>(const ImgHeader &, const ImgHeader *, const uint64_t *, \
-                                              const WorkItem *, uint32_t, uint32_t *, Partial *,      \
-                                              uint32_t, uint32_t, uint32_t, hipStream_t);
+                                              const WorkItem *, uint32_t, Partial *, uint32_t, uint32_t, \
+                                              hipStream_t);

@@ -43,14 +43,11 @@ hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, u
 hipError_t launch_finalize(const Partial *partials, uint32_t n, const FinalArgs &args, DevResult *out,
                            hipStream_t stream);
 
-// persistent multi-program launch; all programs share W, the monomial flag and the
-// accumulation mode of `H0`; lds_bytes is the largest dyn_lds_bytes of the programs
+// multi-program launch, one workgroup per work item; all programs share W, the monomial flag,
+// the accumulation mode and the slot set of `H0`; lds_bytes is the largest dyn_lds_bytes of them
 hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                             const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue,
-                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t lds_bytes,
-                             hipStream_t stream);
-
-hipError_t launch_reset_queue(uint32_t *d_queue, hipStream_t stream);
+                             const WorkItem *d_items, uint32_t n_items, Partial *partials, uint32_t threads,
+                             uint32_t lds_bytes, hipStream_t stream);
 
 // per-program finaliser: program k sums partials [item_first[k], item_first[k] + item_count[k])
 hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item_first,
@@ -69,5 +66,5 @@ hipError_t launch_eval_wm(const ImgHeader &H, const void *dimg, uint64_t s_begin
                           Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
 template <int W, bool MONO>
 hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                           const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue, Partial *partials,
-                           uint32_t blocks, uint32_t threads, uint32_t lds_bytes, hipStream_t stream);
+                           const WorkItem *d_items, uint32_t n_items, Partial *partials, uint32_t threads,
+                           uint32_t lds_bytes, hipStream_t stream);

@@ -1,4 +1,4 @@
-// HIP kernels for gfx950 shared by every program: work-queue reset and the finalisers that
+// HIP kernels for gfx950 shared by every program: the finalisers that
 // add per-block partial sums, apply the program's constant and reduce to canonical form; and
 // the width dispatch of the evaluation launches (the evaluation kernels themselves are
 // instantiated per form-vector width in eval_w*.hip).
@@ -13,10 +13,6 @@ namespace {
 
 __device__ __forceinline__ i128 load_i128(const uint64_t *w) {
     return (i128)((unsigned __int128)w[0] | ((unsigned __int128)w[1] << 64));
-}
-
-__global__ void k_reset_queue(uint32_t *queue) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
 }
 
 // sums partials [first, first + n), then applies the constant and canonicalises (thread 0)
@@ -122,21 +118,15 @@ hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, u
 }
 
 hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
-                             const WorkItem *d_items, uint32_t n_items, uint32_t *d_queue,
-                             Partial *partials, uint32_t blocks, uint32_t threads, uint32_t lds_bytes,
-                             hipStream_t stream) {
-    if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
+                             const WorkItem *d_items, uint32_t n_items, Partial *partials, uint32_t threads,
+                             uint32_t lds_bytes, hipStream_t stream) {
+    if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || n_items == 0)
         return hipErrorInvalidValue;
     if (lds_bytes > MAX_TABLE_BYTES) return hipErrorInvalidValue;
 #define CALL_BATCH(w, m) \
-    launch_batch_wm<w, m>(H0, d_hdrs, d_imgs, d_items, n_items, d_queue, partials, blocks, threads, lds_bytes, stream)
+    launch_batch_wm<w, m>(H0, d_hdrs, d_imgs, d_items, n_items, partials, threads, lds_bytes, stream)
     SWITCH_WM(H0, CALL_BATCH);
 #undef CALL_BATCH
-}
-
-hipError_t launch_reset_queue(uint32_t *d_queue, hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, stream, d_queue);
-    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Partial *partials, uint32_t n, const FinalArgs &args, DevResult *out,

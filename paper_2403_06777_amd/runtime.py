@@ -15,12 +15,12 @@ from typing import Dict, List, Optional, Sequence
 from . import binding as B
 
 DEFAULT_CANDIDATES = [
-    {"block_threads": 256, "blocks_per_cu": 8, "chunk_log2": 22},
-    {"block_threads": 256, "blocks_per_cu": 8, "chunk_log2": 20},
-    {"block_threads": 256, "blocks_per_cu": 8, "chunk_log2": 24},
-    {"block_threads": 256, "blocks_per_cu": 4, "chunk_log2": 22},
-    {"block_threads": 128, "blocks_per_cu": 16, "chunk_log2": 21},
-    {"block_threads": 256, "blocks_per_cu": 8, "chunk_log2": 18},
+    {"block_threads": 256, "chunk_log2": 20},
+    {"block_threads": 256, "chunk_log2": 22},
+    {"block_threads": 256, "chunk_log2": 24},
+    {"block_threads": 128, "chunk_log2": 20},
+    {"block_threads": 128, "chunk_log2": 22},
+    {"block_threads": 256, "chunk_log2": 18},
 ]
 
 _CACHE: Dict[str, dict] = {}
