@@ -174,11 +174,13 @@ class ProgramCache:
 
 class Server:
     def __init__(self, backend, mem_budget: int = 64 << 20, max_active: int = 256, tick_terms: int = 1 << 27,
-                 compile_workers: int = 4, scratch_per_request: int = 4096):
+                 compile_workers: int = 4, scratch_per_request: int = 4096, alone_terms: int = 1 << 30):
         self.backend = backend
         self.cache = ProgramCache(backend, mem_budget)
         self.max_active = max_active
         self.tick_terms = tick_terms
+        # a request alone on the device up to this many terms runs as one launch of its own
+        self.alone_terms = alone_terms
         self.pool = cf.ThreadPoolExecutor(max_workers=compile_workers)
         self.scratch_per_request = scratch_per_request
 
@@ -229,7 +231,8 @@ class Server:
 
         while pending or compiling or held or waiting or active:
             t = now()
-            # arrivals: resident programs are pinned and wait for a slot, others compile
+            # arrivals: resident programs are pinned and wait for a slot, others compile (in the
+            # loop itself when nothing else is in flight: no hand-off to the pool)
             while pending and (pending[0].arrival <= t or not realtime):
                 req = pending.popleft()
                 key = req.key()
@@ -241,7 +244,15 @@ class Server:
                     continue
                 fut = inflight.get(key)
                 if fut is None:
-                    fut = self.pool.submit(self._compile, req)
+                    idle = not (active or waiting or compiling or held)
+                    if idle and not (pending and (pending[0].arrival <= t or not realtime)):
+                        fut = cf.Future()
+                        try:
+                            fut.set_result(self._compile(req))
+                        except B.SimError as e:
+                            fut.set_exception(e)
+                    else:
+                        fut = self.pool.submit(self._compile, req)
                     inflight[key] = fut
                 compiling[req.rid] = (req, fut)
             # finished compilations become resident when the memory budget allows
@@ -287,7 +298,7 @@ class Server:
                     time.sleep(wait)
                 continue
             if (len(active) == 1 and not waiting and not compiling and not held and active[0].next_slice == 0
-                    and active[0].req.terms <= self.tick_terms):
+                    and active[0].req.terms <= self.alone_terms):
                 # a lone small request: one launch of its own, as fast as a dedicated queue
                 a = active[0]
                 a.req.result = self.backend.evaluate(a.entry.handle)
@@ -295,8 +306,9 @@ class Server:
                 self._finish(a.req, a.entry, stats, now())
                 active = []
                 continue
-            # one tick: the next chunk of every active request in a single launch
-            share = max(1, self.tick_terms // len(active))
+            # one tick: the next chunk of every active request in a single launch (a request alone
+            # takes larger chunks: fewer launches, while a new arrival still waits at most one)
+            share = self.alone_terms if len(active) == 1 else max(1, self.tick_terms // len(active))
             handles, firsts, counts = [], [], []
             for a in active:
                 info = a.entry.info
