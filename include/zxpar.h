@@ -79,8 +79,14 @@ typedef struct {
  * OUTCOMES: the amplitude with every output bit y_i a Boolean parameter of the program (the
  * output effects become polar-phase spiders, Section 3.2), so one compilation serves every
  * output string (the repeated strong simulation of Section 4); out_bits is ignored and the
- * program's last n_qubits parameters are y_0 .. y_{n-1} (see sim_eval_outcomes). */
-enum { SIM_QUERY_AMPLITUDE = 0, SIM_QUERY_MARGINAL = 1, SIM_QUERY_OUTCOMES = 2 };
+ * program's last n_qubits parameters are y_0 .. y_{n-1} (see sim_eval_outcomes).
+ * PREFIX: the marginal of the first k = qubit qubits, P(y_0 .. y_{k-1}) =
+ * <0^n| C^dag (|y><y|_{0..k-1} (x) I) C |0^n> (the doubled diagram of Fig. 3 right, the
+ * k-th step of the repeated weak simulation of Appendix E), 1 <= k <= n_qubits.  With
+ * out_bits NULL the k outcomes are query parameters (the program's last k parameters are
+ * y_0 .. y_{k-1}, k <= 62; evaluate with sim_eval_outcomes or sim_sample); otherwise y_i =
+ * out_bits[i] for i < k and the program is a plain scalar. */
+enum { SIM_QUERY_AMPLITUDE = 0, SIM_QUERY_MARGINAL = 1, SIM_QUERY_OUTCOMES = 2, SIM_QUERY_PREFIX = 3 };
 typedef struct {
     uint32_t kind;
     uint32_t n_qubits;
@@ -236,6 +242,21 @@ SIM_API int sim_eval_ranges(const sim_program *const *progs, const uint64_t *fir
  * sim_eval_batch).  SIM_EINVAL if prog has no query parameters or a byte is not 0/1. */
 SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *bits, void *stream,
                               const sim_tuning *t, sim_zomega *out);
+
+/* Repeated weak simulation (Appendix E's algorithm, with the conditional probabilities of
+ * the product rule of Section 2.3).  progs[k-1] is the PREFIX program of the first k qubits
+ * of one circuit, compiled with the outcomes as parameters (k = 1 .. K, K <= 62); the caller
+ * guarantees they come from the same circuit.  uniforms holds n rows of K integers below
+ * 2^53; sample i draws its bits in qubit order, bit k being 0 iff
+ *     uniforms[i*K + k] / 2^53 < P(B || 0) / P(B),
+ * B its bits 0 .. k-1 (P of the empty prefix = 1), decided exactly (no rounding).  Step k
+ * evaluates P(B || 0) once per distinct prefix B among the samples, as one batch (the
+ * kernels of sim_eval_outcomes).  Writes n rows of K bytes (0/1) to out_bits and, if
+ * out_prob is not NULL, each sample's probability P(y_0 .. y_{K-1}) in canonical form.
+ * Blocks until done.  SIM_EINVAL on bad arguments or if a program does not have k query
+ * parameters or yields a non-real probability; other codes as sim_eval_outcomes. */
+SIM_API int sim_sample(const sim_program *const *progs, size_t K, size_t n, const uint64_t *uniforms,
+                       void *stream, const sim_tuning *t, uint8_t *out_bits, sim_zomega *out_prob);
 
 /* sim_finalize for n programs in one launch: out[i] = finalised raws[i] of progs[i]. */
 SIM_API int sim_finalize_batch(const sim_program *const *progs, const sim_zomega *raws, size_t n,

@@ -137,6 +137,20 @@ def exact_marginal(text: str, qubit: int, value: int) -> Tuple[zw.ZW, int]:
     return zw.canonical(acc, -2 * st.k)
 
 
+def exact_prefix_marginal(text: str, prefix: str) -> Tuple[zw.ZW, int]:
+    """P(y_0 .. y_{k-1} = prefix), k = len(prefix): the sum of |amp|^2 over every basis state
+    whose first k bits are the prefix (the summing form of a marginal, Fig. 3 left), exactly"""
+    n, gates = parse_circuit(text)
+    st = ExactState(n).run(gates)
+    k = len(prefix)
+    want = index_of(prefix)
+    acc = zw.ZERO
+    for i, z in enumerate(st.vec):
+        if i & ((1 << k) - 1) == want:
+            acc = zw.add(acc, zw.mul(z, zw.conj(z)))
+    return zw.canonical(acc, -2 * st.k)
+
+
 def exact_state(text: str) -> ExactState:
     n, gates = parse_circuit(text)
     return ExactState(n).run(gates)

@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     amplitude_query,
     marginal_query,
     outcomes_query,
+    prefix_query,
     sim_batch_plan_create,
     sim_batch_plan_free,
     sim_batch_plan_run,
@@ -34,6 +35,7 @@ from .binding import (  # noqa: F401
     sim_program_ir,
     sim_program_layout,
     sim_raw_add,
+    sim_sample,
 )
 
 

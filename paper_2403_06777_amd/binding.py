@@ -26,6 +26,7 @@ SIM_ZOMEGA_RAW = 1
 SIM_QUERY_AMPLITUDE = 0
 SIM_QUERY_MARGINAL = 1
 SIM_QUERY_OUTCOMES = 2
+SIM_QUERY_PREFIX = 3
 
 _CODES = {SIM_EINVAL: "SIM_EINVAL", SIM_ERANGE: "SIM_ERANGE", SIM_ENOMEM: "SIM_ENOMEM",
           SIM_EDEVICE: "SIM_EDEVICE", SIM_EBUSY: "SIM_EBUSY"}
@@ -116,6 +117,10 @@ SIGNATURES = [
     ("sim_batch_plan_free", None, [_P]),
     ("sim_eval_outcomes", ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint8), _P,
                                          ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_sample", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_size_t,
+                                  ctypes.POINTER(ctypes.c_uint64), _P, ctypes.POINTER(sim_tuning),
+                                  ctypes.POINTER(ctypes.c_uint8),
+                                  ctypes.POINTER(sim_zomega)]),
     ("sim_eval_ranges", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                        ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
@@ -196,6 +201,17 @@ def marginal_query(n_qubits: int, qubit: int, value: int):
 def outcomes_query(n_qubits: int):
     """Every output bit a parameter: one compilation for all output strings."""
     return _query(SIM_QUERY_OUTCOMES, n_qubits, None)
+
+
+def prefix_query(n_qubits: int, k: int, prefix_bits: Optional[str] = None):
+    """P(y_0 .. y_{k-1}) over the first k qubits: with the outcomes as parameters (default)
+    or for the fixed string prefix_bits (k characters)."""
+    bits = None
+    if prefix_bits is not None:
+        if len(prefix_bits) != k:
+            raise ValueError("prefix_bits must have k characters")
+        bits = [1 if ch == "1" else 0 for ch in prefix_bits]
+    return _query(SIM_QUERY_PREFIX, n_qubits, bits, k)
 
 
 def _opts(p_cap: int = 0, eliminate_constraints: bool = True):
@@ -356,6 +372,23 @@ def sim_eval_outcomes(prog: int, out_strings: Sequence[str], stream=None, tuning
     outs = (sim_zomega * max(1, n))()
     _check(lib().sim_eval_outcomes(prog, n, bits, _stream(stream), _tuning(tuning), outs))
     return [_scalar(outs[i]) for i in range(n)]
+
+
+def sim_sample(progs: Sequence[int], uniforms, stream=None, tuning: Optional[dict] = None):
+    """Repeated weak simulation: progs[k-1] is the prefix program of the first k qubits
+    (k = 1 .. K), uniforms an (n, K) array of 53-bit integers.  Returns the (n, K) uint8 array
+    of sampled bits and each sample's probability as (coefficients, sqrt2 exponent)."""
+    import numpy as np
+    u = np.ascontiguousarray(uniforms, dtype=np.uint64)
+    if u.ndim != 2 or u.shape[1] != len(progs):
+        raise ValueError("uniforms must be an (n, K) array with K = len(progs)")
+    n, K = u.shape
+    bits = np.zeros((n, K), dtype=np.uint8)
+    probs = (sim_zomega * max(1, n))()
+    _check(lib().sim_sample(_prog_array(progs), K, n, u.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                            _stream(stream), _tuning(tuning), bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            probs))
+    return bits, [_scalar(probs[i]) for i in range(n)]
 
 
 def sim_batch_plan_create(progs: Sequence[int], tuning: Optional[dict] = None, stream=None) -> int:

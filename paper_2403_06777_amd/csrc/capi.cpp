@@ -18,6 +18,7 @@
 #include "compiler.h"
 #include "kernels.h"
 #include "program.h"
+#include "zreal.h"
 
 struct sim_program {
     int device = 0;
@@ -822,6 +823,114 @@ int sim_eval_outcomes(const sim_program *P, size_t n, const uint8_t *bits, void 
         first[r] = y << low;
     }
     return run_batch(ps.data(), n, first.data(), count.data(), false, stream, t, out);
+}
+
+namespace {
+
+// a * sqrt2 with overflow detection
+bool times_sqrt2_checked(const Zw &z, Zw *out) {
+    Zw r;
+    if (__builtin_sub_overflow(z.c[1], z.c[3], &r.c[0]) || __builtin_add_overflow(z.c[0], z.c[2], &r.c[1]) ||
+        __builtin_add_overflow(z.c[1], z.c[3], &r.c[2]) || __builtin_sub_overflow(z.c[2], z.c[0], &r.c[3]))
+        return false;
+    *out = r;
+    return true;
+}
+
+// a sqrt2^ea - b sqrt2^eb, canonical; false on int128 overflow
+bool sub_scaled(Zw a, int32_t ea, Zw b, int32_t eb, Zw *out, int32_t *eo) {
+    if (zw_is_zero(b)) eb = ea;
+    if (zw_is_zero(a)) ea = eb;
+    for (; ea > eb; --ea)
+        if (!times_sqrt2_checked(a, &a)) return false;
+    for (; eb > ea; --eb)
+        if (!times_sqrt2_checked(b, &b)) return false;
+    Zw r;
+    for (int i = 0; i < 4; ++i)
+        if (__builtin_sub_overflow(a.c[i], b.c[i], &r.c[i])) return false;
+    int32_t e = ea;
+    zw_canonicalise(&r, &e);
+    *out = r;
+    *eo = e;
+    return true;
+}
+
+Zw zw_of(const sim_zomega &v) {
+    Zw z;
+    for (int k = 0; k < 4; ++k) z.c[k] = (i128)(((unsigned __int128)(uint64_t)v.c[k].hi << 64) | v.c[k].lo);
+    return z;
+}
+
+sim_zomega zomega_of(const Zw &z, int32_t e) {
+    sim_zomega v;
+    memset(&v, 0, sizeof v);
+    for (int k = 0; k < 4; ++k) {
+        v.c[k].lo = (uint64_t)z.c[k];
+        v.c[k].hi = (int64_t)((unsigned __int128)z.c[k] >> 64);
+    }
+    v.sqrt2_exp = e;
+    return v;
+}
+
+}  // namespace
+
+int sim_sample(const sim_program *const *progs, size_t K, size_t n, const uint64_t *uniforms, void *stream,
+               const sim_tuning *t, uint8_t *out_bits, sim_zomega *out_prob) {
+    if (!progs || (n && (!uniforms || !out_bits))) return fail(SIM_EINVAL, "null argument");
+    if (K < 1 || K > 62) return fail(SIM_EINVAL, "the number of sampled qubits must be 1 .. 62");
+    for (size_t k = 1; k <= K; ++k)
+        if (!progs[k - 1] || progs[k - 1]->pk.outer != (int)k)
+            return fail(SIM_EINVAL, "progs[" + std::to_string(k - 1) + "] must have " + std::to_string(k) +
+                                        " query parameters (the prefix program of the first " +
+                                        std::to_string(k) + " qubits)");
+    for (size_t i = 0; i < n * K; ++i)
+        if (uniforms[i] >> 53) return fail(SIM_EINVAL, "uniforms must be below 2^53");
+    // per sample: the bits drawn so far and their probability P(B) (canonical)
+    std::vector<uint64_t> pre(n, 0);
+    std::vector<Zw> pz(n, zw_one());
+    std::vector<int32_t> pe(n, 0);
+    std::vector<uint64_t> keys;
+    std::vector<uint8_t> rows;
+    std::vector<sim_zomega> res;
+    std::vector<zreal::Real> p0;
+    for (size_t k = 0; k < K; ++k) {
+        // every distinct prefix is evaluated once: P(B || 0) for B = bits 0 .. k-1
+        keys = pre;
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        const size_t nr = keys.size(), w = k + 1;
+        rows.assign(nr * w, 0);
+        for (size_t r = 0; r < nr; ++r)
+            for (size_t j = 0; j < k; ++j) rows[r * w + j] = (uint8_t)((keys[r] >> j) & 1);
+        res.resize(nr);
+        int rc = sim_eval_outcomes(progs[k], nr, rows.data(), stream, t, res.data());
+        if (rc) return rc;
+        p0.resize(nr);
+        for (size_t r = 0; r < nr; ++r)
+            if (!zreal::real_of(zw_of(res[r]), res[r].sqrt2_exp, &p0[r]))
+                return fail(SIM_EINVAL, "a prefix probability is not real: progs[" + std::to_string(k) +
+                                            "] is not a prefix program");
+        for (size_t i = 0; i < n; ++i) {
+            const size_t r = (size_t)(std::lower_bound(keys.begin(), keys.end(), pre[i]) - keys.begin());
+            zreal::Real pb;
+            zreal::real_of(pz[i], pe[i], &pb);
+            // bit k is 0 iff U / 2^53 < P(B || 0) / P(B), i.e. 2^53 P(B || 0) - U P(B) > 0
+            const bool zero = zreal::sign_diff((uint64_t)1 << 53, p0[r], uniforms[i * K + k], pb) > 0;
+            const Zw z0 = zw_of(res[r]);
+            if (zero) {
+                pz[i] = z0;
+                pe[i] = res[r].sqrt2_exp;
+            } else {
+                pre[i] |= (uint64_t)1 << k;
+                if (!sub_scaled(pz[i], pe[i], z0, res[r].sqrt2_exp, &pz[i], &pe[i]))
+                    return fail(SIM_ERANGE, "a prefix probability exceeds int128");
+            }
+            out_bits[i * K + k] = zero ? 0 : 1;
+        }
+    }
+    if (out_prob)
+        for (size_t i = 0; i < n; ++i) out_prob[i] = zomega_of(pz[i], pe[i]);
+    return SIM_OK;
 }
 
 int sim_eval_ranges(const sim_program *const *ps, const uint64_t *first_slice, const uint64_t *n_slices, size_t n,

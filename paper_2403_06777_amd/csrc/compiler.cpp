@@ -30,7 +30,11 @@
 // 5. Outcome-parametric queries.  With every output bit y_i a parameter, the effect <y_i| is a
 //    spider of polar phase pi (c xor y_i) (Section 3.2), the simplification runs unchanged, and
 //    the y_i are never solved for: the program's last n parameters are y_0 .. y_{n-1}, so one
-//    compilation answers every output string.
+//    compilation answers every output string.  A prefix query (the marginal of the first k
+//    qubits, the doubled diagram of Fig. 3 right) does the same with the projector
+//    |y_i><y_i| on each measured qubit: the effect <y_i| and a fresh spider z_i held equal to
+//    y_i by a second polar effect, so the first k outcomes are the program's parameters
+//    (the repeated weak simulation of Appendix E).
 // The scalar is tracked exactly in Z[w] with a power of sqrt2 throughout.
 
 #include "compiler.h"
@@ -644,7 +648,9 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
             throw CompileError{SIM_EINVAL, "query has " + std::to_string(q.n_qubits) + " qubits, circuit has " +
                                                std::to_string(n)};
         std::vector<Gate> seq;
-        int proj_q = -1, proj_v = 0;
+        // doubled diagrams: the measured qubits, each with a fixed value (0/1) or, as a
+        // projector |y_i><y_i| with y_i a query parameter, -1
+        std::vector<std::pair<int, int>> proj;
         size_t proj_at = 0;
         int n_outer = 0;
         if (q.kind == SIM_QUERY_AMPLITUDE) {
@@ -656,12 +662,24 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
             if (n > 62) throw CompileError{SIM_ERANGE, "more than 62 output parameters"};
             n_outer = n;
             seq = gates;
-        } else if (q.kind == SIM_QUERY_MARGINAL) {
-            if (q.qubit >= (uint32_t)n || q.value > 1) throw CompileError{SIM_EINVAL, "bad marginal query"};
-            // <0| C^dag P C |0>: gates outside the backward light cone of the measured qubit
+        } else if (q.kind == SIM_QUERY_MARGINAL || q.kind == SIM_QUERY_PREFIX) {
+            if (q.kind == SIM_QUERY_MARGINAL) {
+                if (q.qubit >= (uint32_t)n || q.value > 1) throw CompileError{SIM_EINVAL, "bad marginal query"};
+                proj.push_back({(int)q.qubit, (int)q.value});
+            } else {
+                const int k = (int)q.qubit;
+                if (k < 1 || k > n) throw CompileError{SIM_EINVAL, "prefix length must be 1 .. n_qubits"};
+                if (!q.out_bits && k > 62) throw CompileError{SIM_ERANGE, "more than 62 prefix parameters"};
+                for (int i = 0; i < k; ++i) {
+                    if (q.out_bits && q.out_bits[i] > 1) throw CompileError{SIM_EINVAL, "prefix bits must be 0 or 1"};
+                    proj.push_back({i, q.out_bits ? (int)q.out_bits[i] : -1});
+                }
+                if (!q.out_bits) n_outer = k;
+            }
+            // <0| C^dag P C |0>: gates outside the backward light cone of the measured qubits
             // cancel against their adjoints, so only the light cone is doubled
             std::vector<char> rel(n, 0);
-            rel[q.qubit] = 1;
+            for (const auto &pq : proj) rel[pq.first] = 1;
             std::vector<Gate> cone;
             for (size_t i = gates.size(); i-- > 0;) {
                 const Gate &G = gates[i];
@@ -674,8 +692,6 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
             std::reverse(cone.begin(), cone.end());
             seq = cone;
             proj_at = seq.size();
-            proj_q = (int)q.qubit;
-            proj_v = (int)q.value;
             for (size_t i = cone.size(); i-- > 0;) {
                 Gate G = cone[i];
                 if (G.kind == 1) G.k = m8(-G.k);
@@ -688,9 +704,21 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
         Builder B;
         std::vector<Label> wire(n);
         for (size_t i = 0; i <= seq.size(); ++i) {
-            if (proj_q >= 0 && i == proj_at) {
-                B.constrain(wire[proj_q], proj_v);
-                wire[proj_q] = Label{{}, proj_v};
+            if (!proj.empty() && i == proj_at) {
+                for (const auto &pq : proj) {
+                    const int w = pq.first;
+                    if (pq.second >= 0) {
+                        B.constrain(wire[w], pq.second);
+                        wire[w] = Label{{}, pq.second};
+                    } else {
+                        // |y><y| with y = parameter w: the effect <y|, then |y> as a fresh
+                        // spider z held equal to y by a second polar effect
+                        B.constrain_param(wire[w], w);
+                        const int z = B.new_spider(0);
+                        wire[w] = Label{{z}, 0};
+                        B.constrain_param(wire[w], w);
+                    }
+                }
             }
             if (i == seq.size()) break;
             const Gate &G = seq[i];

@@ -225,3 +225,59 @@ def test_outcome_parametric_query_parameters_are_reported():
     assert info["n_outer"] == outer == c.n_qubits and info["n_params"] == p
     # the IR round-trips with its query parameters
     assert zx.sim_ir_info(ir)["n_slices"] >= 1 << outer
+
+
+def _prefix_value(o2, ir, prefix):
+    return _outcome_value(o2, ir, prefix)
+
+
+def test_prefix_programs_equal_exact_marginals(o2):
+    # the doubled diagram with the first k outcomes as parameters (Fig. 3 right, Appendix E):
+    # every prefix of every length equals the exact marginal of the state vector, and the
+    # program compiled for one fixed prefix gives the same value
+    for seed in range(6):
+        c, _ = wl.tiny_circuit(seed)
+        text = wl.circuit_text(c)
+        n = c.n_qubits
+        for k in range(1, n + 1):
+            ir, info = zx.sim_compile_to_ir(text, zx.prefix_query(n, k))
+            p, outer, _, _ = _ir_header(ir)
+            assert outer == k == info["n_outer"] and p >= k
+            for idx in range(1 << k):
+                pre = "".join("1" if idx >> i & 1 else "0" for i in range(k))
+                want = sv.exact_prefix_marginal(text, pre)
+                assert _prefix_value(o2, ir, pre) == want, (seed, k, pre)
+                if idx % 5 == 0:
+                    fixed, finfo = zx.sim_compile_to_ir(text, zx.prefix_query(n, k, pre))
+                    assert finfo["n_outer"] == 0
+                    assert o2.evaluate(fixed)["canonical"] == want, (seed, k, pre)
+
+
+def test_prefix_programs_random_circuits(o2):
+    for seed in range(16):
+        n = 2 + seed % 6
+        c = _rand_circuit(500 + seed, n, 14 + 3 * seed, 2 + seed % 9)
+        text = wl.circuit_text(c)
+        for k in sorted({1, (n + 1) // 2, n}):
+            ir, _ = zx.sim_compile_to_ir(text, zx.prefix_query(n, k), eliminate_constraints=bool(seed % 2))
+            for idx in range(1 << k):
+                pre = "".join("1" if idx >> i & 1 else "0" for i in range(k))
+                assert _prefix_value(o2, ir, pre) == sv.exact_prefix_marginal(text, pre), (seed, k, pre)
+
+
+def test_prefix_of_one_qubit_is_the_single_qubit_marginal(o2):
+    for seed in range(4):
+        c, _ = wl.tiny_circuit(seed)
+        text = wl.circuit_text(c)
+        for v in (0, 1):
+            a, _ = zx.sim_compile_to_ir(text, zx.prefix_query(c.n_qubits, 1, str(v)))
+            b, _ = zx.sim_compile_to_ir(text, zx.marginal_query(c.n_qubits, 0, v))
+            assert o2.evaluate(a)["canonical"] == o2.evaluate(b)["canonical"] == sv.exact_marginal(text, 0, v)
+
+
+@pytest.mark.parametrize("k", [0, 7])
+def test_prefix_query_length_is_checked(k):
+    c, _ = wl.tiny_circuit(0)
+    with pytest.raises(zx.SimError) as ei:
+        zx.sim_compile_to_ir(wl.circuit_text(c), zx.prefix_query(6, k))
+    assert ei.value.code == -1 and "prefix length" in str(ei.value)

@@ -389,3 +389,128 @@ def test_born_rule_normalisation_exact(seed):
         p0 = sv.exact_marginal(text, q, 0)
         p1 = sv.exact_marginal(text, q, 1)
         assert zw.add_scalar(*p0, *p1) == ((1, 0, 0, 0), 0)
+
+
+# ----------------------------------------------------------------- marginals and weak sampling
+
+def _bits(idx, k):
+    return "".join("1" if idx >> i & 1 else "0" for i in range(k))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_prefix_marginals_are_consistent(seed):
+    # P over all prefixes of one length sums to 1, the one-qubit prefix is the single-qubit
+    # marginal, the full-length prefix is |amp|^2, and P(B) = P(B0) + P(B1) (product rule)
+    c, _ = wl.tiny_circuit(seed)
+    text = wl.circuit_text(c)
+    n = c.n_qubits
+    for k in (1, 3, n):
+        total = (zw.ZERO, 0)
+        for idx in range(1 << k):
+            total = zw.add_scalar(*total, *sv.exact_prefix_marginal(text, _bits(idx, k)))
+        assert zw.canonical(*total) == (zw.ONE, 0)
+    for v in (0, 1):
+        assert sv.exact_prefix_marginal(text, str(v)) == sv.exact_marginal(text, 0, v)
+    for idx in range(0, 1 << n, 7):
+        y = _bits(idx, n)
+        amp = sv.complex_amplitude(text, y)
+        got = zw.to_complex(*sv.exact_prefix_marginal(text, y))
+        assert abs(got - abs(amp) ** 2) < 1e-12
+    for idx in range(1 << 3):
+        b = _bits(idx, 3)
+        whole = sv.exact_prefix_marginal(text, b)
+        split = zw.add_scalar(*sv.exact_prefix_marginal(text, b + "0"), *sv.exact_prefix_marginal(text, b + "1"))
+        assert zw.canonical(*split) == whole
+
+
+def test_sign_of_a_plus_b_sqrt2_against_high_precision():
+    import mpmath
+    from oracle.sampling import sign_zsqrt2
+    mpmath.mp.dps = 200
+    r2 = mpmath.sqrt(2)
+    rng = wl.SplitMix64(901, 0)
+    cases = [(0, 0), (1, 0), (0, -1), (3, -2), (-3, 2), (7, -5), (-17, 12)]
+    # Pell pairs: p^2 - 2 q^2 = +-1, so p - q sqrt2 is within 1/p of zero
+    p, q = 1, 1
+    for _ in range(60):
+        cases += [(p, -q), (-p, q)]
+        p, q = p + 2 * q, p + q
+    def big(bits):  # uniform magnitude below 2^bits, random sign
+        v = sum(rng.next_u64() << (64 * j) for j in range(3)) >> (192 - bits)
+        return -v if rng.next_u64() & 1 else v
+    for _ in range(300):
+        bits = rng.randint(1, 190)
+        cases.append((big(bits), big(bits)))
+    for a, b in cases:
+        want = mpmath.sign(mpmath.mpf(a) + mpmath.mpf(b) * r2)
+        assert sign_zsqrt2(a, b) == int(want), (a, b)
+
+
+def test_weak_samples_uniform_superposition():
+    # H on every qubit: every conditional probability is 1/2, so bit k is 0 iff U < 2^52, and
+    # every K-bit string has probability 2^-K
+    from oracle.sampling import weak_samples
+    n = 5
+    text = "qubits 5\n" + "".join(f"h {q}\n" for q in range(n))
+    u = wl.sampling_uniforms(0, 64, n)
+    u[0, :] = (1 << 52) - 1
+    u[1, :] = 1 << 52
+    got, probs = weak_samples(text, u.tolist())
+    for i, s in enumerate(got):
+        assert s == "".join("0" if int(x) < (1 << 52) else "1" for x in u[i])
+    assert all(pr == (zw.ONE, -2 * n) for pr in probs)
+
+
+def test_weak_samples_basis_state():
+    # a basis state is sampled with certainty, whatever the uniforms
+    from oracle.sampling import weak_samples
+    text = "qubits 4\nx 1\nh 2\nt 2\nh 2\nh 2\ntdg 2\nh 2\ncx 1 3\n"
+    u = wl.sampling_uniforms(1, 50, 4)
+    u[0, :] = (1 << 53) - 1
+    u[1, :] = 0
+    got, probs = weak_samples(text, u.tolist())
+    assert set(got) == {"0101"} and all(p == (zw.ONE, 0) for p in probs)
+
+
+def test_weak_samples_first_bit_is_the_marginal_threshold():
+    # bit 0 is 0 exactly when U / 2^53 < P(y_0 = 0), computed here at high precision
+    import mpmath
+    from oracle.sampling import weak_samples
+    mpmath.mp.dps = 100
+    for seed in range(3):
+        c, _ = wl.tiny_circuit(seed)
+        text = wl.circuit_text(c)
+        z, e = sv.exact_marginal(text, 0, 0)
+        w = mpmath.exp(1j * mpmath.pi / 4)
+        p0 = mpmath.re(sum(z[i] * w ** i for i in range(4)) * mpmath.sqrt(2) ** e)
+        u = wl.sampling_uniforms(10 + seed, 200, 1)
+        # two uniforms straddling the threshold as closely as 53 bits allow
+        t = int(mpmath.floor(p0 * 2 ** 53))
+        u[0, 0], u[1, 0] = t, min(t + 1, (1 << 53) - 1)
+        got, _ = weak_samples(text, u.tolist(), 1)
+        for i, s in enumerate(got):
+            assert s == ("0" if mpmath.mpf(int(u[i, 0])) / 2 ** 53 < p0 else "1")
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_weak_samples_follow_the_exact_distribution(seed):
+    # the chain rule samples each string with its Born probability: a chi-square test of 6000
+    # samples against |amp|^2 (complex128 state vector); the threshold is the 0.999 quantile
+    # for 63 degrees of freedom, and the inputs are fixed, so the outcome is deterministic
+    from oracle.sampling import weak_samples
+    c, _ = wl.tiny_circuit(seed)
+    text = wl.circuit_text(c)
+    n = c.n_qubits
+    N = 6000
+    got, probs = weak_samples(text, wl.sampling_uniforms(20 + seed, N, n).tolist())
+    counts = np.zeros(1 << n)
+    for s in got:
+        counts[sv.index_of(s)] += 1
+    p = np.abs(sv.complex_state(text)) ** 2
+    keep = p * N >= 5
+    chi2 = float(np.sum((counts[keep] - N * p[keep]) ** 2 / (N * p[keep])))
+    assert counts[~keep].sum() <= max(20.0, 3 * N * p[~keep].sum())
+    assert chi2 < 103.4, chi2
+    # and each sample's reported probability is its own |amp|^2
+    for s, pr in zip(got[:50], probs[:50]):
+        assert abs(zw.to_complex(*pr) - p[sv.index_of(s)]) < 1e-12

@@ -15,6 +15,8 @@ from .circuits import (
     circuit_scale,
     batch_queries,
     serving_pool,
+    sampling_circuit,
+    sampling_uniforms,
 )
 from .programs import (
     ProgramSpec,
@@ -32,6 +34,8 @@ __all__ = [
     "circuit_scale",
     "batch_queries",
     "serving_pool",
+    "sampling_circuit",
+    "sampling_uniforms",
     "ProgramSpec",
     "kernel_sized_program",
     "random_program",

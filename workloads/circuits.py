@@ -27,6 +27,7 @@ STREAM_TINY = 0
 STREAM_CIRCUIT_SCALE = 2
 STREAM_BATCH = 3
 STREAM_SERVING = 4
+STREAM_SAMPLING = 5
 
 
 @dataclass
@@ -108,3 +109,16 @@ def serving_pool(n_circuits: int = 64, base_seed: int = 0):
         ng = rng.randint(200, 1000)
         pool.append(random_clifford_t(rng, nq, ng, nt))
     return pool
+
+
+def sampling_circuit(seed: int, n_qubits: int = 16, n_clifford: int = 160, n_t: int = 12) -> Circuit:
+    """Circuit for repeated weak simulation (every qubit measured, one bit at a time)."""
+    return random_clifford_t(SplitMix64(STREAM_SAMPLING, seed), n_qubits, n_clifford, n_t)
+
+
+def sampling_uniforms(seed: int, n_samples: int, k: int):
+    """n_samples x k table of 53-bit integers U (the uniform u = U / 2^53 in [0, 1)), row i
+    for sample i; uint64 numpy array, equal to drawing SplitMix64(STREAM_SAMPLING + 100, seed)
+    row by row and taking the top 53 bits of each output."""
+    from .rng import splitmix64_array
+    return (splitmix64_array(STREAM_SAMPLING + 100, seed, n_samples * k) >> 11).reshape(n_samples, k)

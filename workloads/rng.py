@@ -54,3 +54,16 @@ class SplitMix64:
                 seen.add(v)
                 out.append(v)
         return out
+
+
+def splitmix64_array(stream: int, seed: int, count: int):
+    """The first `count` outputs of SplitMix64(stream, seed) as a uint64 numpy array (the
+    generator is counter-based: output j comes from state key + (j + 2) * increment, the +1
+    being the mixing draw of the constructor)."""
+    import numpy as np
+    key = np.uint64(((stream & 0xFFFFFFFF) << 32 | (seed & 0xFFFFFFFF)) & MASK64)
+    with np.errstate(over="ignore"):
+        z = key + np.uint64(0x9E3779B97F4A7C15) * np.arange(2, count + 2, dtype=np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
