@@ -152,6 +152,78 @@ def outcomes_section(stream, seed: int = 1, n_max: int = 1000) -> dict:
     }
 
 
+def sampling_section(stream, seed: int = 0, n_max: int = 1000) -> dict:
+    """Repeated weak simulation (Appendix E): the prefix programs of the first k qubits
+    (doubled diagram, the k outcomes as parameters) compiled once for k = 1 .. n, then N
+    samples drawn bit by bit, each step evaluating every distinct prefix once in one batch;
+    against compiling and evaluating each of those prefixes as a fixed-string program."""
+    import numpy as np
+    import paper_2403_06777_amd as zx
+    import workloads as wl
+
+    c = wl.sampling_circuit(seed)
+    text = wl.circuit_text(c)
+    n = c.n_qubits
+    t0 = time.perf_counter()
+    hs = [zx.sim_compile(text, zx.prefix_query(n, k), p_cap=48) for k in range(1, n + 1)]
+    tc_param = time.perf_counter() - t0
+    inner = [zx.sim_program_info(h)["n_params"] - k for k, h in enumerate(hs, start=1)]
+    u = wl.sampling_uniforms(seed, n_max, n)
+    try:
+        zx.sim_sample(hs, u[:4], stream)
+        ts, bits = {}, None
+        for N in (1, 10, 100, n_max):
+            best = None
+            for _ in range(3 if N < n_max else 1):
+                t0 = time.perf_counter()
+                b, _ = zx.sim_sample(hs, u[:N], stream)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            ts[N] = best
+            if N == n_max:
+                bits = b
+        # the distinct prefixes each step evaluates, per N
+        weights = (1 << np.arange(n, dtype=np.uint64)).astype(np.uint64)
+        codes = np.cumsum(bits.astype(np.uint64) * weights, axis=1)  # codes[i, k] = bits 0..k
+
+        def distinct(N, k):  # prefixes B of length k (k = 0: the empty one)
+            return 1 if k == 0 else len(np.unique(codes[:N, k - 1]))
+
+        # the baseline: a fixed-string program per evaluation, timed on up to 3 prefixes per step
+        per_eval, same = [], True
+        for k in range(1, n + 1):
+            pres = np.unique(codes[:, k - 2]) if k > 1 else np.array([0], dtype=np.uint64)
+            dts = []
+            for code in pres[:3]:
+                b = "".join("1" if int(code) >> j & 1 else "0" for j in range(k - 1)) + "0"
+                t0 = time.perf_counter()
+                h1 = zx.sim_compile(text, zx.prefix_query(n, k, b), p_cap=48)
+                try:
+                    v = zx.sim_eval_amplitude(h1, stream)
+                finally:
+                    zx.sim_program_free(h1)
+                dts.append(time.perf_counter() - t0)
+                same = same and v == zx.sim_eval_outcomes(hs[k - 1], [b], stream)[0]
+            per_eval.append(sum(dts) / len(dts))
+    finally:
+        for h in hs:
+            zx.sim_program_free(h)
+    rows = []
+    for N, t in sorted(ts.items()):
+        evals = [distinct(N, k) for k in range(n)]
+        terms = sum(e << p for e, p in zip(evals, inner))
+        base = sum(e * pe for e, pe in zip(evals, per_eval))
+        rows.append({"N": N, "sample_s": t, "samples_per_s": N / t, "evaluations": sum(evals), "terms": terms,
+                     "terms_per_s": terms / t, "param_total_s": tc_param + t, "per_evaluation_total_s": base,
+                     "S_N": base / (tc_param + t)})
+    return {
+        "workload": f"sampling seed {seed}: {n} qubits, 400 Clifford + 32 T gates; N samples of all {n} qubits",
+        "inner_params_per_k": inner, "compile_prefix_programs_s": tc_param,
+        "per_evaluation_compile_eval_s": per_eval,
+        "rows": rows, "results_identical": same,
+    }
+
+
 def batch_section(stream, p_cap: int) -> dict:
     """512 amplitude queries of uneven size: one autotuned, graph-captured persistent launch
     versus one launch per query on the same stream; every result must agree exactly."""
@@ -265,6 +337,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-outcomes", action="store_true")
+    ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--p-cap", type=int, default=36)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -371,6 +444,8 @@ def main():
         out["batch"] = batch_section(stream, args.p_cap)
     if not args.no_outcomes:
         out["outcomes"] = outcomes_section(stream)
+    if not args.no_sampling:
+        out["sampling"] = sampling_section(stream)
     if not args.no_serve:
         out["serving"] = serve_section(stream, args.serve_requests, min(args.p_cap, 32))
     if not args.no_cpu_baseline:
