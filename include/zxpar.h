@@ -258,6 +258,16 @@ SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *
 SIM_API int sim_sample(const sim_program *const *progs, size_t K, size_t n, const uint64_t *uniforms,
                        void *stream, const sim_tuning *t, uint8_t *out_bits, sim_zomega *out_prob);
 
+/* Marginal by summing (Fig. 3 left): prog is an OUTCOMES program (k = n_outer query
+ * parameters); pattern holds k bytes, 0 or 1 fixing y_i and 2 leaving it free.  out = the sum
+ * of |<y|C|0^n>|^2 over the 2^m strings y that match (m = number of free outcomes, at most
+ * 20), exactly (products and sum in Z[sqrt2], no rounding), canonical.  The 2^m amplitudes
+ * are one batch (the kernels of sim_eval_outcomes); the squares and the sum are taken on the
+ * host.  Blocks until done.  SIM_EINVAL on bad arguments, SIM_ERANGE if m > 20 or the exact
+ * sum exceeds int128 coefficients. */
+SIM_API int sim_marginal_sum(const sim_program *prog, const uint8_t *pattern, void *stream,
+                             const sim_tuning *t, sim_zomega *out);
+
 /* sim_finalize for n programs in one launch: out[i] = finalised raws[i] of progs[i]. */
 SIM_API int sim_finalize_batch(const sim_program *const *progs, const sim_zomega *raws, size_t n,
                                void *stream, sim_zomega *out);

@@ -151,6 +151,20 @@ def exact_prefix_marginal(text: str, prefix: str) -> Tuple[zw.ZW, int]:
     return zw.canonical(acc, -2 * st.k)
 
 
+def exact_marginal_pattern(text: str, pattern: str) -> Tuple[zw.ZW, int]:
+    """P(y_i = pattern[i] wherever pattern[i] is '0' or '1'): the sum of |amp|^2 over every
+    basis state that agrees with the pattern, a '*' leaving its qubit free (Fig. 3 left)"""
+    n, gates = parse_circuit(text)
+    if len(pattern) != n:
+        raise ValueError("pattern length != qubit count")
+    st = ExactState(n).run(gates)
+    acc = zw.ZERO
+    for i, z in enumerate(st.vec):
+        if all(ch == "*" or (i >> q & 1) == int(ch) for q, ch in enumerate(pattern)):
+            acc = zw.add(acc, zw.mul(z, zw.conj(z)))
+    return zw.canonical(acc, -2 * st.k)
+
+
 def exact_state(text: str) -> ExactState:
     n, gates = parse_circuit(text)
     return ExactState(n).run(gates)

@@ -29,6 +29,7 @@ from .binding import (  # noqa: F401
     sim_init,
     sim_ir_info,
     sim_last_error,
+    sim_marginal_sum,
     sim_program_free,
     sim_program_from_ir,
     sim_program_info,

@@ -117,6 +117,8 @@ SIGNATURES = [
     ("sim_batch_plan_free", None, [_P]),
     ("sim_eval_outcomes", ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint8), _P,
                                          ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_marginal_sum", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint8), _P, ctypes.POINTER(sim_tuning),
+                                        ctypes.POINTER(sim_zomega)]),
     ("sim_sample", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_uint64), _P, ctypes.POINTER(sim_tuning),
                                   ctypes.POINTER(ctypes.c_uint8),
@@ -372,6 +374,16 @@ def sim_eval_outcomes(prog: int, out_strings: Sequence[str], stream=None, tuning
     outs = (sim_zomega * max(1, n))()
     _check(lib().sim_eval_outcomes(prog, n, bits, _stream(stream), _tuning(tuning), outs))
     return [_scalar(outs[i]) for i in range(n)]
+
+
+def sim_marginal_sum(prog: int, pattern: str, stream=None, tuning: Optional[dict] = None):
+    """Sum of |amplitude|^2 over the output strings matching pattern ('0', '1' fixed, '*'
+    free) of an OUTCOMES program."""
+    code = {"0": 0, "1": 1, "*": 2}
+    bits = (ctypes.c_uint8 * max(1, len(pattern)))(*[code[ch] for ch in pattern])
+    out = sim_zomega()
+    _check(lib().sim_marginal_sum(prog, bits, _stream(stream), _tuning(tuning), ctypes.byref(out)))
+    return _scalar(out)
 
 
 def sim_sample(progs: Sequence[int], uniforms, stream=None, tuning: Optional[dict] = None):

@@ -885,6 +885,7 @@ int sim_sample(const sim_program *const *progs, size_t K, size_t n, const uint64
                                         std::to_string(k) + " qubits)");
     for (size_t i = 0; i < n * K; ++i)
         if (uniforms[i] >> 53) return fail(SIM_EINVAL, "uniforms must be below 2^53");
+    if (!n) return SIM_OK;
     // per sample: the bits drawn so far and their probability P(B) (canonical)
     std::vector<uint64_t> pre(n, 0);
     std::vector<Zw> pz(n, zw_one());
@@ -930,6 +931,117 @@ int sim_sample(const sim_program *const *progs, size_t K, size_t n, const uint64
     }
     if (out_prob)
         for (size_t i = 0; i < n; ++i) out_prob[i] = zomega_of(pz[i], pe[i]);
+    return SIM_OK;
+}
+
+namespace {
+
+// |z|^2 = z conj(z) = (c0^2 + c1^2 + c2^2 + c3^2) + (c0 c1 + c1 c2 + c2 c3 - c3 c0) sqrt2: the
+// products z_i z_j w^{i-j} pair up as w + w^-1 = sqrt2, w^3 + w^-3 = -sqrt2, w^2 + w^-2 = 0
+zreal::Real norm2(const Zw &z, int32_t e) {
+    using namespace zreal;
+    BigInt c[4];
+    for (int i = 0; i < 4; ++i) c[i] = BigInt::of(z.c[i]);
+    Real r;
+    r.a = add(add(mul(c[0], c[0]), mul(c[1], c[1])), add(mul(c[2], c[2]), mul(c[3], c[3])));
+    r.b = add(add(mul(c[0], c[1]), mul(c[1], c[2])), add(mul(c[2], c[3]), neg(mul(c[3], c[0]))));
+    r.e = 2 * e;
+    return r;
+}
+
+// canonical (a + b sqrt2) sqrt2^e as a Z[w] element (a, b, 0, -b); false if it exceeds int128
+bool canonical_of(zreal::Real r, Zw *z, int32_t *e) {
+    using namespace zreal;
+    if (r.a.zero() && r.b.zero()) {
+        *z = zw_zero();
+        *e = 0;
+        return true;
+    }
+    auto even = [](const BigInt &v) { return v.zero() || !(v.m[0] & 1); };
+    auto half = [](const BigInt &v) {  // exact v / 2 of an even v
+        BigInt h;
+        h.neg = v.neg;
+        h.m.assign(v.m.size(), 0);
+        for (size_t i = 0; i < v.m.size(); ++i)
+            h.m[i] = (v.m[i] >> 1) | (i + 1 < v.m.size() ? v.m[i + 1] << 31 : 0);
+        h.trim();
+        return h;
+    };
+    while (even(r.a) && even(r.b)) {  // divide by 2 = sqrt2^2
+        r.a = half(r.a);
+        r.b = half(r.b);
+        r.e += 2;
+    }
+    if (even(r.a)) {  // (a + b sqrt2) / sqrt2 = b + (a / 2) sqrt2
+        BigInt t = half(r.a);
+        r.a = r.b;
+        r.b = t;
+        r.e += 1;
+    }
+    auto fits = [](const BigInt &v, i128 *out) {
+        if (v.m.size() > 4 || (v.m.size() == 4 && (v.m[3] >> 31))) return false;
+        unsigned __int128 u = 0;
+        for (size_t i = v.m.size(); i-- > 0;) u = (u << 32) | v.m[i];
+        *out = v.neg ? -(i128)u : (i128)u;
+        return true;
+    };
+    i128 a, b;
+    if (!fits(r.a, &a) || !fits(r.b, &b)) return false;
+    *z = zw_make(a, b, 0, -b);
+    *e = r.e;
+    return true;
+}
+
+}  // namespace
+
+int sim_marginal_sum(const sim_program *P, const uint8_t *pattern, void *stream, const sim_tuning *t,
+                     sim_zomega *out) {
+    if (!P || !pattern || !out) return fail(SIM_EINVAL, "null argument");
+    const int k = P->pk.outer;
+    if (k <= 0) return fail(SIM_EINVAL, "the program has no query parameters (compile an OUTCOMES query)");
+    uint64_t fixed = 0;
+    std::vector<int> free_pos;
+    for (int i = 0; i < k; ++i) {
+        if (pattern[i] == 2) free_pos.push_back(i);
+        else if (pattern[i] <= 1) fixed |= (uint64_t)pattern[i] << i;
+        else return fail(SIM_EINVAL, "pattern bytes must be 0, 1 or 2");
+    }
+    const size_t m = free_pos.size();
+    if (m > 20) return fail(SIM_ERANGE, "at most 20 summed outcomes");
+    // one slice range per string that matches the pattern (the outcomes are the top bits)
+    const uint32_t low = (uint32_t)(P->pk.hdr.pe - P->pk.hdr.g) - (uint32_t)k;
+    const size_t n = (size_t)1 << m;
+    std::vector<const sim_program *> ps(n, P);
+    std::vector<uint64_t> first(n), count(n, (uint64_t)1 << low);
+    for (size_t r = 0; r < n; ++r) {
+        uint64_t y = fixed;
+        for (size_t j = 0; j < m; ++j) y |= (uint64_t)((r >> j) & 1) << free_pos[j];
+        first[r] = y << low;
+    }
+    std::vector<sim_zomega> amps(n);
+    int rc = run_batch(ps.data(), n, first.data(), count.data(), false, stream, t, amps.data());
+    if (rc) return rc;
+    // the exact sum of |A|^2, at the lowest power of sqrt2 met so far
+    zreal::Real acc;
+    bool any = false;
+    for (size_t r = 0; r < n; ++r) {
+        if (zw_is_zero(zw_of(amps[r]))) continue;
+        zreal::Real v = norm2(zw_of(amps[r]), amps[r].sqrt2_exp);
+        if (!any) {
+            acc = v;
+            any = true;
+            continue;
+        }
+        const int32_t E = std::min(acc.e, v.e);
+        acc = zreal::lower_to(acc, E);
+        v = zreal::lower_to(v, E);
+        acc.a = zreal::add(acc.a, v.a);
+        acc.b = zreal::add(acc.b, v.b);
+    }
+    Zw z = zw_zero();
+    int32_t e = 0;
+    if (any && !canonical_of(acc, &z, &e)) return fail(SIM_ERANGE, "the marginal exceeds int128");
+    *out = zomega_of(z, e);
     return SIM_OK;
 }
 

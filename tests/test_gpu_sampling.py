@@ -141,3 +141,68 @@ def test_sample_arguments_are_checked():
         assert bits.shape == (0, 2) and probs == []
     finally:
         free_all(hs + [odd])
+
+
+def _random_pattern(rng, n):
+    return "".join("*01"[rng.randint(0, 2)] for _ in range(n))
+
+
+def test_marginals_by_summing_match_the_oracle():
+    # Fig. 3 left: squares of the outcome-parametric amplitudes, summed exactly
+    for seed in range(8):
+        rng = wl.SplitMix64(740, seed)
+        if seed < 4:
+            c, _ = wl.tiny_circuit(seed)
+        else:
+            c = wl.random_clifford_t(rng, 4 + seed, 120 + 20 * seed, 10 + seed)
+        text = wl.circuit_text(c)
+        n = c.n_qubits
+        h = zx.sim_compile(text, zx.outcomes_query(n), p_cap=40)
+        try:
+            say("marginal by summing", seed, n, zx.sim_program_info(h)["n_params"])
+            assert zx.sim_marginal_sum(h, "*" * n) == ((1, 0, 0, 0), 0)
+            pats = [_random_pattern(rng, n) for _ in range(6)] + ["1" + "*" * (n - 1), "0" * n]
+            for pat in pats:
+                assert zx.sim_marginal_sum(h, pat) == sv.exact_marginal_pattern(text, pat), (seed, pat)
+        finally:
+            zx.sim_program_free(h)
+
+
+def test_summing_equals_doubling():
+    # the two forms of a marginal (Fig. 3): summed squares of amplitudes and the doubled
+    # diagram's prefix program give the same exact value
+    for seed in range(4):
+        rng = wl.SplitMix64(750, seed)
+        n = 10
+        c = wl.random_clifford_t(rng, n, 160, 14)
+        text = wl.circuit_text(c)
+        h = zx.sim_compile(text, zx.outcomes_query(n), p_cap=40)
+        hp = zx.sim_compile(text, zx.prefix_query(n, 4), p_cap=40)
+        try:
+            for idx in range(16):
+                pre = _bits(idx, 4)
+                assert zx.sim_marginal_sum(h, pre + "*" * (n - 4)) == zx.sim_eval_outcomes(hp, [pre])[0]
+        finally:
+            zx.sim_program_free(h)
+            zx.sim_program_free(hp)
+
+
+def test_marginal_sum_arguments_are_checked():
+    n = 22
+    text = f"qubits {n}\n" + "".join(f"h {q}\n" for q in range(n)) + "t 0\nh 0\n"
+    h = zx.sim_compile(text, zx.outcomes_query(n))
+    c, _ = wl.tiny_circuit(0)
+    plain = zx.sim_compile(wl.circuit_text(c), zx.amplitude_query("0" * 6))
+    try:
+        with pytest.raises(zx.SimError) as ei:
+            zx.sim_marginal_sum(h, "*" * n)
+        assert ei.value.code == -2 and "20 summed" in str(ei.value)
+        with pytest.raises(zx.SimError) as ei:
+            zx.sim_marginal_sum(plain, "*" * 6)
+        assert ei.value.code == -1
+        # 20 free outcomes is the limit.  Qubit 0 is in HTH|0> = ((1 + w)|0> + (1 - w)|1>) / 2,
+        # the others in |+>: P(y_0 = 0, y_21 = 1) = (2 + sqrt2) / 8 = (1 + sqrt2) sqrt2^-5
+        assert zx.sim_marginal_sum(h, "0" + "*" * 20 + "1") == ((1, 1, 0, -1), -5)
+    finally:
+        zx.sim_program_free(h)
+        zx.sim_program_free(plain)

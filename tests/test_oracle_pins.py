@@ -514,3 +514,26 @@ def test_weak_samples_follow_the_exact_distribution(seed):
     # and each sample's reported probability is its own |amp|^2
     for s, pr in zip(got[:50], probs[:50]):
         assert abs(zw.to_complex(*pr) - p[sv.index_of(s)]) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pattern_marginals(seed):
+    # a pattern of fixed and free qubits: all free is 1, one fixed qubit is the single-qubit
+    # marginal, a fixed prefix is the prefix marginal, all fixed is |amp|^2, and freeing a
+    # qubit adds its two values
+    c, _ = wl.tiny_circuit(seed)
+    text = wl.circuit_text(c)
+    n = c.n_qubits
+    assert sv.exact_marginal_pattern(text, "*" * n) == (zw.ONE, 0)
+    for q in range(n):
+        for v in (0, 1):
+            pat = "*" * q + str(v) + "*" * (n - q - 1)
+            assert sv.exact_marginal_pattern(text, pat) == sv.exact_marginal(text, q, v)
+    assert sv.exact_marginal_pattern(text, "101" + "*" * (n - 3)) == sv.exact_prefix_marginal(text, "101")
+    y = "011010"[:n]
+    amp = sv.complex_amplitude(text, y)
+    assert abs(zw.to_complex(*sv.exact_marginal_pattern(text, y)) - abs(amp) ** 2) < 1e-12
+    pat = "1*0*1*"[:n]
+    both = zw.add_scalar(*sv.exact_marginal_pattern(text, pat.replace("*", "0", 1)),
+                         *sv.exact_marginal_pattern(text, pat.replace("*", "1", 1)))
+    assert zw.canonical(*both) == sv.exact_marginal_pattern(text, pat)
