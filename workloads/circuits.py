@@ -111,7 +111,7 @@ def serving_pool(n_circuits: int = 64, base_seed: int = 0):
     return pool
 
 
-def sampling_circuit(seed: int, n_qubits: int = 16, n_clifford: int = 160, n_t: int = 12) -> Circuit:
+def sampling_circuit(seed: int, n_qubits: int = 20, n_clifford: int = 400, n_t: int = 32) -> Circuit:
     """Circuit for repeated weak simulation (every qubit measured, one bit at a time)."""
     return random_clifford_t(SplitMix64(STREAM_SAMPLING, seed), n_qubits, n_clifford, n_t)
 
