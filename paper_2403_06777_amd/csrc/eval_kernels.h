@@ -30,6 +30,11 @@
 namespace {
 
 typedef const __attribute__((address_space(4))) uint32_t CU32;
+// whole-entry reads of the image: one scalar load each, which the compiler cannot split
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+typedef const __attribute__((address_space(4))) u32x4 CV4;
+typedef const __attribute__((address_space(4))) u32x8 CV8;
 
 __device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__builtin_popcount(x); }
 
@@ -331,30 +336,60 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             }
         }
     }
+    // What the flip at the start of the next block reads (its column and its position record)
+    // is loaded one block ahead, so that the scalar loads overlap the current block's work
+    // instead of stalling the flip.
+    CV8 *recs = reinterpret_cast<CV8 *>(wd + H.off_pos);
+    uint32_t cn[W];
+    u32x8 rn = {0, 0, 0, 0, 0, 0, 0, 0};  // ui, flip entries [rn[1], rn[2]), inner-vector entries [rn[3], rn[4])
+    if (b0 + 1 < b1) {
+        const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b0 + 1);
+#pragma unroll
+        for (int w = 0; w < W; ++w) cn[w] = col[i * W + w];
+        if (MONO) rn = recs[i];
+    }
     for (uint32_t b = b0; b < b1; ++b) {
         if (b != b0) {
             const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b);
             gray ^= 1u << i;
 #pragma unroll
-            for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
+            for (int w = 0; w < W; ++w) L[w] ^= cn[w];
+            const u32x8 r = rn;
+            if (b + 1 < b1) {
+                const uint32_t in = kInnerBits + (uint32_t)__builtin_ctz(b + 1);
+#pragma unroll
+                for (int w = 0; w < W; ++w) cn[w] = col[in * W + w];
+                if (MONO) rn = recs[in];
+            }
             if (MONO) {
-                phi += flip_phase(H, wd, i, gray, dal, s);
+                // the phase change of the flip: uniform and always-firing parts, then the
+                // entries that depend on walk bits above i
+                int dd = (int)r[0] + (int)((dal >> (4 * i)) & 7u);
+                CV4 *de = reinterpret_cast<CV4 *>(wd + H.off_delta);
+                for (uint32_t e = r[1]; e < r[2]; ++e) {
+                    const u32x4 d = de[e];  // c, walk mask, slice mask lo, hi
+                    const uint32_t c = d[0], wm = d[1], hl = d[2], hh = d[3];
+                    if ((gray & wm) != wm) continue;
+                    const uint64_t hm = (uint64_t)hl | ((uint64_t)hh << 32);
+                    dd += ((s & hm) == hm) ? (int)c : 0;
+                }
+                phi += ((gray >> i) & 1u) ? dd : -dd;
                 // inner vectors of the monomials that also need outer bits: those of position i
                 // whose other outer bits are set switch on (bit i now 1) or off
-                CU32 *c3idx = wd + H.off_c3idx;
                 const bool on = (gray >> i) & 1u;
-                CU32 *e3 = wd + H.off_c3 + 7 * c3idx[i];
-                for (uint32_t e = c3idx[i]; e < c3idx[i + 1]; ++e, e3 += 7) {
-                    const uint32_t om = e3[4];
+                CV8 *e3 = reinterpret_cast<CV8 *>(wd + H.off_c3);
+                for (uint32_t e = r[3]; e < r[4]; ++e) {
+                    const u32x8 v = e3[e];  // even lo, hi, odd lo, hi, other outer bits, slice mask lo, hi
+                    uint32_t p0l = v[0], p0h = v[1], p1l = v[2], p1h = v[3];
+                    const uint32_t om = v[4], hl = v[5], hh = v[6];
                     if ((gray & om) != om) continue;
-                    uint32_t p0l = e3[0], p0h = e3[1], p1l = e3[2], p1h = e3[3];
                     if (!on) {
                         p0l = field_neg(p0l);
                         p0h = field_neg(p0h);
                         p1l = field_neg(p1l);
                         p1h = field_neg(p1h);
                     }
-                    const uint64_t hm = (uint64_t)e3[5] | ((uint64_t)e3[6] << 32);
+                    const uint64_t hm = (uint64_t)hl | ((uint64_t)hh << 32);
                     if ((s & hm) == hm) {
                         v0lo = field_add(v0lo, p0l);
                         v0hi = field_add(v0hi, p0h);
@@ -386,8 +421,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             uint32_t y = 0;
             CU32 *bs = wd + H.off_ibasis;
 #pragma unroll
-            for (int i = 0; i < kInnerBits; ++i) {
-                if ((uint32_t)i >= H.inner_rank) break;
+            for (int i = 0; i < kInnerBits; ++i) {  // padded with all-zero entries past the rank
                 CU32 *e = bs + i * (3 + W);
                 const uint32_t pw = e[0], pb = e[1], cm = e[2];
                 uint32_t aw = a[0];

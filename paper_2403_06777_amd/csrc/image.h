@@ -89,7 +89,8 @@ struct ImgHeader {
     uint32_t off_never; // W words: a value of L & zmask that no block's surviving terms have
     uint32_t inner_rank;  // rank r of the inner columns on the vanishing bits (walks of at least
     uint32_t off_ibasis;  //   kInnerBits positions): r entries of 3 + W words (pivot word, pivot
-                          //   bit, inner columns making it up, reduced basis vector), then at
+                          //   bit, inner columns making it up, reduced basis vector) and
+                          //   kInnerBits - r all-zero entries (they change nothing), then at
     uint32_t off_ikern;   //   off_ikern the 4 - r null-space combinations of the inner columns
     uint32_t off_slots; // kSlots entries of (W + 1) words: weight (0 = unused), mask[W]
     int32_t stat_base[N_STATS];
@@ -102,8 +103,8 @@ struct ImgHeader {
     uint32_t off_aidx;    // g + 1 words: slice-dependent always-firing entries of position i are
     uint32_t off_al;      //   [aidx[i], aidx[i+1]) at off_al, 3 words each: c, slice mask lo, hi
     uint32_t off_didx;    // g + 1 words: walk-state-dependent entries of position i are
-    uint32_t off_delta;   //   [didx[i], didx[i+1]) at off_delta, 4 words each: c, walk mask
-                          //   (positions above i), slice mask lo, slice mask hi
+    uint32_t off_delta;   //   [didx[i], didx[i+1]) at off_delta, 4 words each (16-byte
+                          //   aligned): c, walk mask (positions above i), slice mask lo, hi
     // Inner-block phase vectors.  Field k (bits 4k .. 4k+3) of a vector holds, mod 8, the phase
     // of step k of a block minus that of step 0; the walk state of step k inside the block is
     // gray(k) on the inner positions, with the top inner bit inverted in odd blocks, so every
@@ -113,9 +114,13 @@ struct ImgHeader {
     uint32_t off_c2;      // n_c2 entries, 6 words: even lo, hi, odd lo, hi, slice mask lo, hi
     uint32_t n_c2;        //   (other variables: slice bits only)
     uint32_t off_c3idx;   // g + 1 words: entries of outer walk position i (some other variable
-    uint32_t off_c3;      //   is an outer walk bit) are [c3idx[i], c3idx[i+1]) at off_c3, 7 words
-    uint32_t n_c3;        //   each: even lo, hi, odd lo, hi, its other outer walk bits, slice mask
-                          //   lo, hi; at a flip of i with the other bits set it toggles on or off
+    uint32_t off_c3;      //   is an outer walk bit) are [c3idx[i], c3idx[i+1]) at off_c3, 8 words
+    uint32_t n_c3;        //   each (32-byte aligned): even lo, hi, odd lo, hi, its other outer walk
+                          //   bits, slice mask lo, hi, 0; at a flip of i with the other bits set
+                          //   it toggles on or off
+    uint32_t off_pos;     // g records of 8 words (32-byte aligned), one per walk position i:
+                          //   ui[i], didx[i], didx[i+1], c3idx[i], c3idx[i+1], 0, 0, 0 (what a
+                          //   flip of i reads, in one load)
     // A walk may start at any block of a slice (the work of a wave is a contiguous range of
     // blocks); its start state then needs:
     uint32_t off_c3all;   // n_c3all entries, 7 words: the inner-and-outer monomials once each

@@ -696,6 +696,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             img.push_back(comb[i]);
             img.insert(img.end(), basis[i].begin(), basis[i].end());
         }
+        // padded to kInnerBits entries with zero entries (they change nothing), so the kernel
+        // reads all of them at once without testing the rank
+        for (size_t i = basis.size(); i < (size_t)kInnerBits; ++i) img.insert(img.end(), 3 + W, 0u);
         H.off_ikern = (uint32_t)img.size();
         img.insert(img.end(), kern.begin(), kern.end());
     }
@@ -815,6 +818,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         img.push_back(acc);
         if (i < g) acc += (uint32_t)(per[i].size() / 4);
     }
+    while (img.size() % 4) img.push_back(0);  // entries are read as one 16-byte load
     H.off_delta = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), per[i].begin(), per[i].end());
 
@@ -879,6 +883,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 dst.push_back(other);
                 dst.push_back((uint32_t)hm);
                 dst.push_back((uint32_t)(hm >> 32));
+                dst.push_back(0);
             }
         }
     }
@@ -891,16 +896,27 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.n_c2 = (uint32_t)(c2.size() / 6);
     img.insert(img.end(), c2.begin(), c2.end());
     H.off_c3idx = (uint32_t)img.size();
+    std::vector<uint32_t> c3start(g + 1, 0);
     {
         uint32_t n = 0;
         for (int i = 0; i <= g; ++i) {
             img.push_back(n);
-            if (i < g) n += (uint32_t)(c3pos[i].size() / 7);
+            c3start[i] = n;
+            if (i < g) n += (uint32_t)(c3pos[i].size() / 8);
         }
         H.n_c3 = n;
     }
+    while (img.size() % 8) img.push_back(0);  // entries are read as one 32-byte load
     H.off_c3 = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), c3pos[i].begin(), c3pos[i].end());
+    // one record per walk position: everything a flip of it reads first
+    while (img.size() % 8) img.push_back(0);
+    H.off_pos = (uint32_t)img.size();
+    for (int i = 0; i < g; ++i) {
+        const uint32_t *didx = img.data() + H.off_didx;
+        const uint32_t rec[8] = {(uint32_t)ui[i], didx[i], didx[i + 1], c3start[i], c3start[i + 1], 0, 0, 0};
+        img.insert(img.end(), rec, rec + 8);
+    }
     // for a walk that starts inside a slice: each inner-and-outer monomial once, with its whole
     // outer mask, and every monomial with a walk part (c, walk mask, slice mask lo, hi)
     H.off_c3all = (uint32_t)img.size();
@@ -1037,7 +1053,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 walk += W + flip_cost(i, gray);
                 if (!mono) continue;
                 for (uint32_t e = c3idx[i]; e < c3idx[i + 1]; ++e) {
-                    const uint32_t other = c3[7 * e + 4];
+                    const uint32_t other = c3[8 * e + 4];
                     if ((gray & other) == other) walk += 12;
                 }
             }
