@@ -167,7 +167,7 @@ uint32_t pick_threads(const sim_tuning *t) {
 // Grid of the single-program kernel over `count` slices: by default what the chip holds at
 // once (every block resident), so that the kernel's own split of the work into per-wave runs of
 // blocks, not a second wave of workgroups, balances it; never more waves than work units (one
-// 2^kInnerBits-term block of 64 slices, or one whole short walk of 64 slices).
+// 2^KB-term block of 64 slices, or one whole short walk of 64 slices).
 int eval_grid(DeviceState &D, const sim_program *P, uint64_t count, uint32_t threads, const sim_tuning *t,
               uint32_t *blocks) {
     const ImgHeader &H = P->pk.hdr;
@@ -182,7 +182,8 @@ int eval_grid(DeviceState &D, const sim_program *P, uint64_t count, uint32_t thr
         }
         bpc = (uint32_t)Pm->occ_blocks;
     }
-    const uint32_t lg_units = H.g >= (uint32_t)kInnerBits ? H.g - kInnerBits : 0u;
+    const uint32_t kb = (uint32_t)inner_bits_for(H.W);
+    const uint32_t lg_units = H.g >= kb ? H.g - kb : 0u;
     const uint64_t units = ((count + 63) / 64) << std::min<uint32_t>(lg_units, 40);
     const uint64_t waves_per_block = threads / 64;
     const uint64_t want = (units + waves_per_block - 1) / waves_per_block;

@@ -268,7 +268,21 @@ __device__ __forceinline__ bool words_equal(const uint32_t (&a)[W], const uint32
     return x == 0u;
 }
 
-// The blocks of a slice: 2^(g - kInnerBits) blocks of kInnerSteps terms.  Between blocks one
+// field k of a block's phase vector (NF = 2 or 4 words of 4-bit fields), for a per-lane k: a
+// 64-bit half picked by bit 4 of k, then a shift (a select chain over the words would be
+// turned into a stack array)
+template <int NF>
+__device__ __forceinline__ uint32_t field_at(const uint32_t (&fv)[NF], uint32_t k) {
+    static_assert(NF == 2 || NF == 4, "16 or 32 fields");
+    uint64_t x = (uint64_t)fv[0] | ((uint64_t)fv[1] << 32);
+    if (NF == 4) {
+        const uint64_t h = (uint64_t)fv[2 % NF] | ((uint64_t)fv[3 % NF] << 32);
+        x = (k & 16u) ? h : x;
+    }
+    return (uint32_t)(x >> (4 * (k & 15u))) & 7u;
+}
+
+// The blocks of a slice: 2^(g - KB) blocks of 2^KB terms.  Between blocks one
 // outer walk position flips (column XOR, phase change from the position's lists); inside a
 // block the flip positions are compile-time constants, the inner columns sit in registers and
 // the phase of each term is read from the block's vector of 4-bit fields.
@@ -281,16 +295,18 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                                             unsigned long long *cnt, uint64_t s, bool valid, uint32_t b0,
                                             uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, WaveQueue *Q,
                                             Acc<ACC> &acc) {
-    static_assert(kInnerBits == 4, "one 64-bit vector of 4-bit fields per block");
+    constexpr int KB = inner_bits_for(W);  // inner bits of a block
+    constexpr int KS = 1 << KB;             // its terms
+    constexpr int NF = KS / 8;              // words of its 4-bit phase fields
     CU32 *col = wd + H.off_col;
-    uint32_t ck[kInnerBits][W];
+    uint32_t ck[KB][W];
 #pragma unroll
-    for (int j = 0; j < kInnerBits; ++j)
+    for (int j = 0; j < KB; ++j)
 #pragma unroll
         for (int w = 0; w < W; ++w) ck[j][w] = col[j * W + w];
-    uint32_t cz[kInnerBits][W];  // the inner columns on the vanishing bits
+    uint32_t cz[KB][W];  // the inner columns on the vanishing bits
 #pragma unroll
-    for (int j = 0; j < kInnerBits; ++j)
+    for (int j = 0; j < KB; ++j)
 #pragma unroll
         for (int w = 0; w < W; ++w) cz[j][w] = ck[j][w] & S.zm[w];
     // per lane: the masked start vector of a block is (L & zmv) | nvv, the never-matching
@@ -302,37 +318,42 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
         nvv[w] = valid ? 0u : wd[H.off_never + w];
     }
     // the inner phase vectors of the current outer state (even and odd blocks)
-    uint32_t v0lo = 0, v0hi = 0, v1lo = 0, v1hi = 0;
+    uint32_t v0[NF], v1[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) v0[j] = v1[j] = 0;
     if (MONO) {
         CU32 *ci = wd + H.off_inner;
-        v0lo = ci[0];
-        v0hi = ci[1];
-        v1lo = ci[2];
-        v1hi = ci[3];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            v0[j] = ci[j];
+            v1[j] = ci[NF + j];
+        }
         CU32 *e2 = wd + H.off_c2;
-        for (uint32_t e = 0; e < H.n_c2; ++e, e2 += 6) {
-            const uint64_t hm = (uint64_t)e2[4] | ((uint64_t)e2[5] << 32);
+        for (uint32_t e = 0; e < H.n_c2; ++e, e2 += 2 * NF + 2) {
+            const uint64_t hm = (uint64_t)e2[2 * NF] | ((uint64_t)e2[2 * NF + 1] << 32);
             if ((s & hm) == hm) {
-                v0lo = field_add(v0lo, e2[0]);
-                v0hi = field_add(v0hi, e2[1]);
-                v1lo = field_add(v1lo, e2[2]);
-                v1hi = field_add(v1hi, e2[3]);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    v0[j] = field_add(v0[j], e2[j]);
+                    v1[j] = field_add(v1[j], e2[NF + j]);
+                }
             }
         }
     }
-    uint32_t gray = (b0 ^ (b0 >> 1)) << kInnerBits;  // walk bits at or above kInnerBits
+    uint32_t gray = (b0 ^ (b0 >> 1)) << KB;  // walk bits at or above KB
     if (MONO && b0) {
         // inner-and-outer monomials already switched on at the start state
         CU32 *e3 = wd + H.off_c3all;
-        for (uint32_t e = 0; e < H.n_c3all; ++e, e3 += 7) {
-            const uint32_t om = e3[4];
+        for (uint32_t e = 0; e < H.n_c3all; ++e, e3 += 2 * NF + 3) {
+            const uint32_t om = e3[2 * NF];
             if ((gray & om) != om) continue;
-            const uint64_t hm = (uint64_t)e3[5] | ((uint64_t)e3[6] << 32);
+            const uint64_t hm = (uint64_t)e3[2 * NF + 1] | ((uint64_t)e3[2 * NF + 2] << 32);
             if ((s & hm) == hm) {
-                v0lo = field_add(v0lo, e3[0]);
-                v0hi = field_add(v0hi, e3[1]);
-                v1lo = field_add(v1lo, e3[2]);
-                v1hi = field_add(v1hi, e3[3]);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    v0[j] = field_add(v0[j], e3[j]);
+                    v1[j] = field_add(v1[j], e3[NF + j]);
+                }
             }
         }
     }
@@ -343,20 +364,20 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     uint32_t cn[W];
     u32x8 rn = {0, 0, 0, 0, 0, 0, 0, 0};  // ui, flip entries [rn[1], rn[2]), inner-vector entries [rn[3], rn[4])
     if (b0 + 1 < b1) {
-        const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b0 + 1);
+        const uint32_t i = KB + (uint32_t)__builtin_ctz(b0 + 1);
 #pragma unroll
         for (int w = 0; w < W; ++w) cn[w] = col[i * W + w];
         if (MONO) rn = recs[i];
     }
     for (uint32_t b = b0; b < b1; ++b) {
         if (b != b0) {
-            const uint32_t i = kInnerBits + (uint32_t)__builtin_ctz(b);
+            const uint32_t i = KB + (uint32_t)__builtin_ctz(b);
             gray ^= 1u << i;
 #pragma unroll
             for (int w = 0; w < W; ++w) L[w] ^= cn[w];
             const u32x8 r = rn;
             if (b + 1 < b1) {
-                const uint32_t in = kInnerBits + (uint32_t)__builtin_ctz(b + 1);
+                const uint32_t in = KB + (uint32_t)__builtin_ctz(b + 1);
 #pragma unroll
                 for (int w = 0; w < W; ++w) cn[w] = col[in * W + w];
                 if (MONO) rn = recs[in];
@@ -379,31 +400,38 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                 const bool on = (gray >> i) & 1u;
                 CV8 *e3 = reinterpret_cast<CV8 *>(wd + H.off_c3);
                 for (uint32_t e = r[3]; e < r[4]; ++e) {
-                    const u32x8 v = e3[e];  // even lo, hi, odd lo, hi, other outer bits, slice mask lo, hi
-                    uint32_t p0l = v[0], p0h = v[1], p1l = v[2], p1h = v[3];
-                    const uint32_t om = v[4], hl = v[5], hh = v[6];
+                    // even[NF], odd[NF], other outer bits, slice mask lo, hi (4 NF words)
+                    uint32_t v[4 * NF];
+#pragma unroll
+                    for (int h = 0; h < NF / 2; ++h) {
+                        const u32x8 part = e3[(NF / 2) * e + h];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) v[8 * h + j] = part[j];
+                    }
+                    const uint32_t om = v[2 * NF], hl = v[2 * NF + 1], hh = v[2 * NF + 2];
                     if ((gray & om) != om) continue;
                     if (!on) {
-                        p0l = field_neg(p0l);
-                        p0h = field_neg(p0h);
-                        p1l = field_neg(p1l);
-                        p1h = field_neg(p1h);
+#pragma unroll
+                        for (int j = 0; j < 2 * NF; ++j) v[j] = field_neg(v[j]);
                     }
                     const uint64_t hm = (uint64_t)hl | ((uint64_t)hh << 32);
                     if ((s & hm) == hm) {
-                        v0lo = field_add(v0lo, p0l);
-                        v0hi = field_add(v0hi, p0h);
-                        v1lo = field_add(v1lo, p1l);
-                        v1hi = field_add(v1hi, p1h);
+#pragma unroll
+                        for (int j = 0; j < NF; ++j) {
+                            v0[j] = field_add(v0[j], v[j]);
+                            v1[j] = field_add(v1[j], v[NF + j]);
+                        }
                     }
                 }
             }
         }
-        uint32_t flo = 0, fhi = 0;
+        uint32_t fv[NF];  // the phase fields of this block's terms
+#pragma unroll
+        for (int j = 0; j < NF; ++j) fv[j] = 0;
         if (MONO) {
             const bool odd = b & 1u;
-            flo = odd ? v1lo : v0lo;
-            fhi = odd ? v1hi : v0hi;
+#pragma unroll
+            for (int j = 0; j < NF; ++j) fv[j] = odd ? v1[j] : v0[j];
         }
         if (ZERO && CQ) {
             // Term k of the block has L0 ^ P(gray(k)), P the XOR of the inner columns of the set
@@ -421,7 +449,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             uint32_t y = 0;
             CU32 *bs = wd + H.off_ibasis;
 #pragma unroll
-            for (int i = 0; i < kInnerBits; ++i) {  // padded with all-zero entries past the rank
+            for (int i = 0; i < KB; ++i) {  // padded with all-zero entries past the rank
                 CU32 *e = bs + i * (3 + W);
                 const uint32_t pw = e[0], pb = e[1], cm = e[2];
                 uint32_t aw = a[0];
@@ -441,24 +469,27 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                 // pass 2: append each lane's surviving terms (L0 ^ P(gray(k)), phase) to the queue
                 const uint32_t below =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                const uint32_t n_kern = kInnerBits - H.inner_rank;
+                const uint32_t n_kern = KB - H.inner_rank;
                 CU32 *kn = wd + H.off_ikern;
                 for (uint32_t z = 0; z < (1u << n_kern); ++z) {
                     uint32_t yz = y;
                     for (uint32_t t = 0; t < n_kern; ++t)
                         if ((z >> t) & 1u) yz ^= kn[t];
                     if (hit) {
-                        const uint32_t k = yz ^ (yz >> 1) ^ (yz >> 2) ^ (yz >> 3);  // gray(k) = yz
+                        uint32_t k = yz;  // the step with gray(k) = yz (prefix XOR of its bits)
+                        k ^= k >> 1;
+                        k ^= k >> 2;
+                        k ^= k >> 4;
                         uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
                         for (int w = 0; w < W; ++w) words[w] = L[w];
 #pragma unroll
-                        for (int j = 0; j < kInnerBits; ++j) {
+                        for (int j = 0; j < KB; ++j) {
                             const uint32_t mj = 0u - ((yz >> j) & 1u);
 #pragma unroll
                             for (int w = 0; w < W; ++w) words[w] ^= ck[j][w] & mj;
                         }
-                        const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                        const int f = MONO ? (int)field_at<NF>(fv, k) : 0;
                         words[W] = (uint32_t)(phi + f);
                         uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
                         e[0] = make_uint4(words[0], words[1], words[2], words[3]);
@@ -468,9 +499,9 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                     if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, wd, tab, cnt, *Q, 64u, acc);
                 }
             }
-            // the block's last state: gray(kInnerSteps - 1) has only the top inner bit set
+            // the block's last state: gray(KS - 1) has only the top inner bit set
 #pragma unroll
-            for (int w = 0; w < W; ++w) L[w] ^= ck[kInnerBits - 1][w];
+            for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
         } else if (ZERO) {
             // wide form vectors: compare with each step's value, evaluate the survivors in place
             uint32_t a[W];
@@ -481,7 +512,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             for (int w = 0; w < W; ++w) d[w] = opaque_zero();
             uint64_t any = 0;
 #pragma unroll
-            for (int k = 0; k < kInnerSteps; ++k) {
+            for (int k = 0; k < KS; ++k) {
                 if (k) {
 #pragma unroll
                     for (int w = 0; w < W; ++w) d[w] ^= cz[__builtin_ctz(k)][w];
@@ -496,7 +527,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                     d[w] = 0;
                 }
 #pragma unroll
-                for (int k = 0; k < kInnerSteps; ++k) {
+                for (int k = 0; k < KS; ++k) {
                     if (k) {
                         const int j = __builtin_ctz(k);
 #pragma unroll
@@ -506,32 +537,32 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                         }
                     }
                     if (words_equal<W>(a, d)) {
-                        const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                        const int f = MONO ? (int)((fv[k >> 3] >> (4 * (k & 7))) & 7u) : 0;
                         add_term<W, ACC, SET, false>(H, S, tab, cnt, Lk, phi + f, acc);
                     }
                 }
             }
-            // the block's last state: gray(kInnerSteps - 1) has only the top inner bit set
+            // the block's last state: gray(KS - 1) has only the top inner bit set
 #pragma unroll
-            for (int w = 0; w < W; ++w) L[w] ^= ck[kInnerBits - 1][w];
+            for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
         } else {
             add_term<W, ACC, SET, false>(H, S, tab, cnt, L, phi, acc);
 #pragma unroll
-            for (int k = 1; k < kInnerSteps; ++k) {
+            for (int k = 1; k < KS; ++k) {
                 const int j = __builtin_ctz(k);
 #pragma unroll
                 for (int w = 0; w < W; ++w) L[w] ^= ck[j][w];
-                const int f = MONO ? (int)(((k < 8 ? flo : fhi) >> (4 * (k & 7))) & 7u) : 0;
+                const int f = MONO ? (int)((fv[k >> 3] >> (4 * (k & 7))) & 7u) : 0;
                 add_term<W, ACC, SET, false>(H, S, tab, cnt, L, phi + f, acc);
             }
         }
-        if (MONO) phi += (int)(fhi >> 28);  // the block's last state
+        if (MONO) phi += (int)(fv[NF - 1] >> 28);  // the block's last state
     }
 }
 
 // Assignments of slice s (high parameters = bits of s): blocks [b0, b1) of its walk, or with
-// fewer than kInnerBits walk bits the whole walk (b0 = 0, b1 = 1).  CQ: the compacting walk of a
-// program with vanishing factors and at least kInnerBits walk bits (called by the whole wave,
+// fewer than KB walk bits the whole walk (b0 = 0, b1 = 1).  CQ: the compacting walk of a
+// program with vanishing factors and at least KB walk bits (called by the whole wave,
 // valid marks the lanes with a slice); otherwise every other kind of program.
 template <int W, bool MONO, int ACC, uint32_t SET, bool CQ>
 __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const int64_t *tab, unsigned long long *cnt,
@@ -576,7 +607,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
     }
     if (b0) {
         // the walk starts at block b0: its first state has the walk bits of gray(b0 * 2^K)
-        const uint32_t t0 = b0 << kInnerBits;
+        const uint32_t t0 = b0 << inner_bits_for(W);
         const uint32_t g0 = t0 ^ (t0 >> 1);
         for (uint32_t bits = g0; bits; bits &= bits - 1u) {
             const uint32_t j = (uint32_t)__builtin_ctz(bits);
@@ -597,7 +628,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         walk_blocks<W, MONO, ACC, SET, true, true>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q, acc);
         return;
     }
-    if (H.g >= (uint32_t)kInnerBits) {
+    if (H.g >= (uint32_t)inner_bits_for(W)) {
         if (!H.has_zero)
             walk_blocks<W, MONO, ACC, SET, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
         else if (!kCompact<W>)
@@ -716,7 +747,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 }
 
 // Work of one range of slices.  The unit is one block of the walks of a group of 64
-// consecutive slices (one slice per lane; with fewer than kInnerBits walk bits a whole walk),
+// consecutive slices (one slice per lane; with fewer than KB walk bits a whole walk),
 // and wave w of the nw waves that share the range takes a contiguous run of units, so the waves
 // differ by at most one unit and every lane of a wave is at the same block.  Lanes whose slice
 // is past the end of the range do nothing (or, in the compacting walk, walk without results).
@@ -731,9 +762,9 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
     Acc<ACC> acc;
     acc.clear();
     WaveQueue Q{s_queue + (threadIdx.x >> 6) * kQueueCap * kQueueWords<W>, 0u};
-    const bool blocks = H.g >= (uint32_t)kInnerBits;
+    const bool blocks = H.g >= (uint32_t)inner_bits_for(W);
     const bool compact = kCompact<W> && H.has_zero && blocks;
-    const uint32_t lg_nb = blocks ? H.g - kInnerBits : 0u;  // units per slice group = 2^lg_nb
+    const uint32_t lg_nb = blocks ? H.g - inner_bits_for(W) : 0u;  // units per slice group = 2^lg_nb
     const uint64_t n_units = ((s_count + 63) >> 6) << lg_nb;
     const uint64_t q = uniform64(n_units / n_waves), r = uniform64(n_units % n_waves);
     const uint64_t u_begin = uniform64(wave * q + (wave < r ? wave : r));

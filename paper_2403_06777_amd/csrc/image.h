@@ -53,12 +53,18 @@ IMG_HD constexpr int slot_words(uint32_t set, int slot, int W) {
     return (set & kSlotsNodeWord0) && slot_stat(slot) != STAT_R ? 1 : W;
 }
 
-// Walk positions 0 .. kInnerBits-1 are stepped in unrolled blocks of 2^kInnerBits terms: the
+// Walk positions 0 .. KB-1 (the inner bits) are stepped in unrolled blocks of 2^KB terms: the
 // flip positions inside a block are compile-time constants, and the phase of every term of a
-// block relative to its first term is one 4-bit field (mod 8) of a per-lane 64-bit vector built
-// once per block.  Programs with fewer walk bits use the plain step loop.
-constexpr int kInnerBits = 4;
-constexpr int kInnerSteps = 1 << kInnerBits;  // one 64-bit vector of 4-bit fields per block
+// block relative to its first term is one 4-bit field (mod 8) of a per-lane vector of
+// 2^KB / 8 words built once per block.  Everything done once per block (the flip between
+// blocks, the vanishing test) is spread over 2^KB terms: 32 for form vectors of up to 4
+// words, 16 for wider ones (whose unrolled block keeps 2^KB columns of W words in registers).
+// Programs with fewer walk bits use the plain step loop.
+constexpr int kMaxInnerBits = 5;
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+constexpr int inner_bits_for(uint32_t W) { return W <= 4 ? 5 : 4; }
 
 // how the terms of a lane are summed
 enum {
@@ -88,10 +94,10 @@ struct ImgHeader {
                         // where its factor vanishes (the form, complemented if that is at l = 0)
     uint32_t off_never; // W words: a value of L & zmask that no block's surviving terms have
     uint32_t inner_rank;  // rank r of the inner columns on the vanishing bits (walks of at least
-    uint32_t off_ibasis;  //   kInnerBits positions): r entries of 3 + W words (pivot word, pivot
-                          //   bit, inner columns making it up, reduced basis vector) and
-                          //   kInnerBits - r all-zero entries (they change nothing), then at
-    uint32_t off_ikern;   //   off_ikern the 4 - r null-space combinations of the inner columns
+    uint32_t off_ibasis;  //   KB positions): r entries of 3 + W words (pivot word, pivot bit,
+                          //   inner columns making it up, reduced basis vector) and KB - r
+                          //   all-zero entries (they change nothing), then at
+    uint32_t off_ikern;   //   off_ikern the KB - r null-space combinations of the inner columns
     uint32_t off_slots; // kSlots entries of (W + 1) words: weight (0 = unused), mask[W]
     int32_t stat_base[N_STATS];
     uint32_t off_monohi;  // monomials over high positions only: c, mask_lo, mask_hi (slice bits)
@@ -105,26 +111,27 @@ struct ImgHeader {
     uint32_t off_didx;    // g + 1 words: walk-state-dependent entries of position i are
     uint32_t off_delta;   //   [didx[i], didx[i+1]) at off_delta, 4 words each (16-byte
                           //   aligned): c, walk mask (positions above i), slice mask lo, hi
-    // Inner-block phase vectors.  Field k (bits 4k .. 4k+3) of a vector holds, mod 8, the phase
-    // of step k of a block minus that of step 0; the walk state of step k inside the block is
-    // gray(k) on the inner positions, with the top inner bit inverted in odd blocks, so every
-    // vector comes as an (even, odd) pair, each as (lo, hi) words.  Only monomials with an inner
-    // variable contribute; one is active when its other variables are all 1:
-    uint32_t off_inner;   // 4 words: sum over monomials whose other variables are all inner
-    uint32_t off_c2;      // n_c2 entries, 6 words: even lo, hi, odd lo, hi, slice mask lo, hi
+    // Inner-block phase vectors, NF = 2^KB / 8 words each.  Field k (bits 4(k mod 8) .. +3 of
+    // word k / 8) of a vector holds, mod 8, the phase of step k of a block minus that of step 0;
+    // the walk state of step k inside the block is gray(k) on the inner positions, with the top
+    // inner bit inverted in odd blocks, so every vector comes as an (even, odd) pair.  Only
+    // monomials with an inner variable contribute; one is active when its other variables are
+    // all 1:
+    uint32_t off_inner;   // 2 NF words: sum over monomials whose other variables are all inner
+    uint32_t off_c2;      // n_c2 entries, 2 NF + 2 words: even[NF], odd[NF], slice mask lo, hi
     uint32_t n_c2;        //   (other variables: slice bits only)
     uint32_t off_c3idx;   // g + 1 words: entries of outer walk position i (some other variable
-    uint32_t off_c3;      //   is an outer walk bit) are [c3idx[i], c3idx[i+1]) at off_c3, 8 words
-    uint32_t n_c3;        //   each (32-byte aligned): even lo, hi, odd lo, hi, its other outer walk
-                          //   bits, slice mask lo, hi, 0; at a flip of i with the other bits set
-                          //   it toggles on or off
+    uint32_t off_c3;      //   is an outer walk bit) are [c3idx[i], c3idx[i+1]) at off_c3, each
+    uint32_t n_c3;        //   4 NF words (aligned): even[NF], odd[NF], its other outer walk bits,
+                          //   slice mask lo, hi, zeros; at a flip of i with the other bits set it
+                          //   toggles on or off
     uint32_t off_pos;     // g records of 8 words (32-byte aligned), one per walk position i:
                           //   ui[i], didx[i], didx[i+1], c3idx[i], c3idx[i+1], 0, 0, 0 (what a
                           //   flip of i reads, in one load)
     // A walk may start at any block of a slice (the work of a wave is a contiguous range of
     // blocks); its start state then needs:
-    uint32_t off_c3all;   // n_c3all entries, 7 words: the inner-and-outer monomials once each
-    uint32_t n_c3all;     //   (even lo, hi, odd lo, hi, outer walk mask, slice mask lo, hi)
+    uint32_t off_c3all;   // n_c3all entries, 2 NF + 3 words: the inner-and-outer monomials once
+    uint32_t n_c3all;     //   each (even[NF], odd[NF], outer walk mask, slice mask lo, hi)
     uint32_t off_monowalk;  // n_monowalk entries, 4 words: every monomial with a walk part
     uint32_t n_monowalk;    //   (c, walk mask, slice mask lo, hi)
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry

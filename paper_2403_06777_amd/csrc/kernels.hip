@@ -80,8 +80,9 @@ size_t dyn_lds_bytes(const ImgHeader &H) {
 }
 
 uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads) {
-    // a unit is one block (2^kInnerBits terms) of 64 lanes, or one whole walk of 2^g terms
-    const uint32_t lg_terms = H.g >= (uint32_t)kInnerBits ? (uint32_t)kInnerBits : H.g;
+    // a unit is one block (2^KB terms) of 64 lanes, or one whole walk of 2^g terms
+    const uint32_t kb = (uint32_t)inner_bits_for(H.W);
+    const uint32_t lg_terms = H.g >= kb ? kb : H.g;
     const uint64_t per_unit = (uint64_t)(threads ? threads : 64) << lg_terms;  // terms per unit in a workgroup
     const uint64_t c = ((uint64_t)1 << 32) / per_unit;
     return c ? c : 1;

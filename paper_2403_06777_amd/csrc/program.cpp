@@ -419,7 +419,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     const int want = w.mono.empty() ? 8 : 12;
     const int inner_p = p - ir.outer;  // query parameters are never walked
     int g_orig = std::min(inner_p, std::min(max_walk_bits, want));
-    if (p - g_orig < 6) g_orig = std::max(std::min(inner_p, kInnerBits), p - 6);
+    if (p - g_orig < 6) g_orig = std::max(std::min(inner_p, kMaxInnerBits), p - 6);
     g_orig = std::min(g_orig, inner_p);
     if (!w.mono.empty()) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
     if (p - g_orig > 62) g_orig = p - 62;
@@ -500,6 +500,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         return SIM_ERANGE;
     }
     P.W = W;
+    const int KB = inner_bits_for((uint32_t)W);  // inner bits of a block
+    const int KS = 1 << KB;                      // terms of a block
+    const int NF = KS / 8;                       // words of a block's 4-bit phase fields
     P.n_forms = F;
     P.n_factors = (int)w.nodes.size();
     P.n_mono = (int)w.mono.size();
@@ -617,7 +620,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.off_zmask = (uint32_t)img.size();
     img.insert(img.end(), zmask.begin(), zmask.end());
     // a pattern no block can match: the masked start vector of a surviving term is one of the
-    // 16 combinations of the inner columns on the vanishing bits, all inside zmask
+    // 2^KB combinations of the inner columns on the vanishing bits, all inside zmask
     H.off_never = (uint32_t)img.size();
     {
         std::vector<uint32_t> nv(W, 0);
@@ -626,11 +629,11 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             nv[k] = ~zmask[k];
             outside = outside || nv[k] != 0;
         }
-        if (!outside && g >= kInnerBits) {
+        if (!outside && g >= KB) {
             std::vector<std::vector<uint32_t>> combos;
-            for (int y = 0; y < (1 << kInnerBits); ++y) {
+            for (int y = 0; y < KS; ++y) {
                 std::vector<uint32_t> c(W, 0);
-                for (int j = 0; j < kInnerBits; ++j)
+                for (int j = 0; j < KB; ++j)
                     if (y >> j & 1)
                         for (int f = 0; f < F; ++f)
                             if (used[f].mask >> j & 1) c[f / 32] ^= 1u << (f % 32);
@@ -658,9 +661,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         std::vector<std::vector<uint32_t>> basis;  // reduced basis vectors
         std::vector<int> pivot;                    // their pivot bits
         std::vector<uint32_t> comb;                // inner columns making up each
-        std::vector<uint32_t> kern;                // null-space basis (4-bit combinations)
-        if (g >= kInnerBits) {
-            for (int j = 0; j < kInnerBits; ++j) {
+        std::vector<uint32_t> kern;                // null-space basis (KB-bit combinations)
+        if (g >= KB) {
+            for (int j = 0; j < KB; ++j) {
                 std::vector<uint32_t> v(W, 0);
                 for (int f = 0; f < F; ++f)
                     if (used[f].mask >> j & 1) v[f / 32] |= 1u << (f % 32);
@@ -696,9 +699,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             img.push_back(comb[i]);
             img.insert(img.end(), basis[i].begin(), basis[i].end());
         }
-        // padded to kInnerBits entries with zero entries (they change nothing), so the kernel
-        // reads all of them at once without testing the rank
-        for (size_t i = basis.size(); i < (size_t)kInnerBits; ++i) img.insert(img.end(), 3 + W, 0u);
+        // padded to KB entries with zero entries (they change nothing), so the kernel reads all
+        // of them at once without testing the rank
+        for (size_t i = basis.size(); i < (size_t)KB; ++i) img.insert(img.end(), 3 + W, 0u);
         H.off_ikern = (uint32_t)img.size();
         img.insert(img.end(), kern.begin(), kern.end());
     }
@@ -822,78 +825,65 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.off_delta = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), per[i].begin(), per[i].end());
 
-    // inner-block phase vectors (walks of at least kInnerBits positions): for each monomial
-    // with an inner variable, field k of the (even, odd) vector is c * ([inner part set at
-    // step k] - [... at step 0]) mod 8; grouped by what else the monomial needs
-    uint64_t inner_vec[2] = {0, 0};
+    // inner-block phase vectors (walks of at least KB positions): for each monomial with an
+    // inner variable, field k of the (even, odd) vector is c * ([inner part set at step k] -
+    // [... at step 0]) mod 8; grouped by what else the monomial needs
+    const int C3S = 4 * NF;  // words per inner-vector entry of a flip (aligned, one load)
+    std::vector<uint32_t> inner_vec(2 * NF, 0);
     std::vector<uint32_t> c2, c3all;
     std::vector<std::vector<uint32_t>> c3pos(g);  // per outer walk position
-    if (g >= kInnerBits) {
-        const uint64_t inner_mask = ((uint64_t)1 << kInnerBits) - 1;
-        auto field_add = [](uint64_t a, uint64_t b) { return (a + b) & 0x7777777777777777ull; };
+    if (g >= KB) {
+        const uint64_t inner_mask = ((uint64_t)1 << KB) - 1;
+        auto field_add = [](uint32_t a, uint32_t b) { return (a + b) & 0x77777777u; };
         for (const auto &m : monos) {
             const uint64_t I = m.second & inner_mask;
             if (!I) continue;
-            uint64_t vec[2] = {0, 0};
+            std::vector<uint32_t> vec(2 * NF, 0);  // even[NF], odd[NF]
             for (int odd = 0; odd < 2; ++odd) {
-                const uint64_t y0 = (uint64_t)odd << (kInnerBits - 1);
+                const uint64_t y0 = (uint64_t)odd << (KB - 1);
                 const int f0 = (I & y0) == I;
-                for (int k = 1; k < kInnerSteps; ++k) {
+                for (int k = 1; k < KS; ++k) {
                     const uint64_t y = (uint64_t)(k ^ (k >> 1)) ^ y0;
                     const int f = (I & y) == I;
-                    vec[odd] |= (uint64_t)mod8((long long)m.first * (f - f0)) << (4 * k);
+                    vec[odd * NF + k / 8] |= (uint32_t)mod8((long long)m.first * (f - f0)) << (4 * (k % 8));
                 }
             }
             const uint32_t om = (uint32_t)(m.second & walk_mask & ~inner_mask);
             const uint64_t hm = m.second >> g;
             if (!om && !hm) {
-                inner_vec[0] = field_add(inner_vec[0], vec[0]);
-                inner_vec[1] = field_add(inner_vec[1], vec[1]);
+                for (int k = 0; k < 2 * NF; ++k) inner_vec[k] = field_add(inner_vec[k], vec[k]);
                 continue;
             }
             if (!om) {
-                c2.push_back((uint32_t)vec[0]);
-                c2.push_back((uint32_t)(vec[0] >> 32));
-                c2.push_back((uint32_t)vec[1]);
-                c2.push_back((uint32_t)(vec[1] >> 32));
+                c2.insert(c2.end(), vec.begin(), vec.end());
                 c2.push_back((uint32_t)hm);
                 c2.push_back((uint32_t)(hm >> 32));
                 continue;
             }
-            c3all.push_back((uint32_t)vec[0]);
-            c3all.push_back((uint32_t)(vec[0] >> 32));
-            c3all.push_back((uint32_t)vec[1]);
-            c3all.push_back((uint32_t)(vec[1] >> 32));
+            c3all.insert(c3all.end(), vec.begin(), vec.end());
             c3all.push_back(om);
             c3all.push_back((uint32_t)hm);
             c3all.push_back((uint32_t)(hm >> 32));
             // needs outer walk bits: its activation toggles when one of them flips while the
             // others are set; at a flip of outer position i the outer bits below i - 1 are clear
-            for (int i = kInnerBits; i < g; ++i) {
+            for (int i = KB; i < g; ++i) {
                 if (!(om >> i & 1)) continue;
                 const uint32_t other = om & ~(1u << i);
-                const uint32_t clear_below =
-                    i - 1 > kInnerBits ? ((1u << (i - 1)) - 1) & ~((1u << kInnerBits) - 1) : 0u;
+                const uint32_t clear_below = i - 1 > KB ? ((1u << (i - 1)) - 1) & ~((1u << KB) - 1) : 0u;
                 if (other & clear_below) continue;
                 std::vector<uint32_t> &dst = c3pos[i];
-                dst.push_back((uint32_t)vec[0]);
-                dst.push_back((uint32_t)(vec[0] >> 32));
-                dst.push_back((uint32_t)vec[1]);
-                dst.push_back((uint32_t)(vec[1] >> 32));
+                dst.insert(dst.end(), vec.begin(), vec.end());
                 dst.push_back(other);
                 dst.push_back((uint32_t)hm);
                 dst.push_back((uint32_t)(hm >> 32));
-                dst.push_back(0);
+                while (dst.size() % C3S) dst.push_back(0);
             }
         }
     }
     H.off_inner = (uint32_t)img.size();
-    for (int odd = 0; odd < 2; ++odd) {
-        img.push_back((uint32_t)inner_vec[odd]);
-        img.push_back((uint32_t)(inner_vec[odd] >> 32));
-    }
+    img.insert(img.end(), inner_vec.begin(), inner_vec.end());
     H.off_c2 = (uint32_t)img.size();
-    H.n_c2 = (uint32_t)(c2.size() / 6);
+    H.n_c2 = (uint32_t)(c2.size() / (2 * NF + 2));
     img.insert(img.end(), c2.begin(), c2.end());
     H.off_c3idx = (uint32_t)img.size();
     std::vector<uint32_t> c3start(g + 1, 0);
@@ -902,11 +892,11 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         for (int i = 0; i <= g; ++i) {
             img.push_back(n);
             c3start[i] = n;
-            if (i < g) n += (uint32_t)(c3pos[i].size() / 8);
+            if (i < g) n += (uint32_t)(c3pos[i].size() / C3S);
         }
         H.n_c3 = n;
     }
-    while (img.size() % 8) img.push_back(0);  // entries are read as one 32-byte load
+    while (img.size() % 8) img.push_back(0);  // entries are read with 32-byte loads
     H.off_c3 = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), c3pos[i].begin(), c3pos[i].end());
     // one record per walk position: everything a flip of it reads first
@@ -920,7 +910,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // for a walk that starts inside a slice: each inner-and-outer monomial once, with its whole
     // outer mask, and every monomial with a walk part (c, walk mask, slice mask lo, hi)
     H.off_c3all = (uint32_t)img.size();
-    H.n_c3all = (uint32_t)(c3all.size() / 7);
+    H.n_c3all = (uint32_t)(c3all.size() / (2 * NF + 3));
     img.insert(img.end(), c3all.begin(), c3all.end());
     H.off_monowalk = (uint32_t)img.size();
     for (const auto &m : monos) {
@@ -997,22 +987,22 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // and one popcount-accumulate per word it spans (with the node table: one AND and one LDS
     // read for all node factors), the table index and shift (8), the accumulation (int64 12,
     // int128 40, class counter 5) and with monomials the term's phase field (2).
-    //  * walks of at least kInnerBits positions: with factors that can vanish, each term's
+    //  * walks of at least KB positions: with factors that can vanish, each term's
     //    vanishing test (a W-word compare) and for a surviving term the rebuild of its form
     //    vector (W); otherwise each term's column XOR (W).  Per block: the outer column XOR (W),
     //    with vanishing factors the masked start vector and the end XOR (2W), with monomials
-    //    the vector-pair selection (2), the flip's own change (5), 5 per firing slice-dependent
-    //    flip entry and 12 per toggling inner-vector entry (slice test, four field adds);
+    //    the vector-pair selection (NF), the flip's own change (5), 5 per firing slice-dependent
+    //    flip entry and 4 + 4 NF per toggling inner-vector entry (slice test, 2 NF field adds);
     //  * shorter walks: per term the column XOR (W), the vanishing test (2W) and the flip
     //    (5 plus 5 per firing slice-dependent entry);
     //  * per slice: the high parameters into L (2W each), 5 per slice-dependent monomial entry,
-    //    4 per walk position for the packed always-firing fields, 12 per inner-vector entry.
+    //    4 per walk position for the packed always-firing fields, 4 + 4 NF per inner-vector entry.
     {
         const double nz = nonzero_fraction(used, w.nodes);
         P.nonzero_fraction = nz;
         const double acc_ops = H.acc == ACC_I64 ? 12.0 : H.acc == ACC_I128 ? 40.0 : 5.0;
         const bool mono = !w.mono.empty();
-        const bool blocks = g >= kInnerBits;
+        const bool blocks = g >= KB;
         double slot_ops = 0;
         const uint32_t set = slot_set_of(H.slot_menu) | (H.node_word0 ? kSlotsNodeWord0 : 0u);
         for (int i = 0; i < kSlots; ++i)
@@ -1023,7 +1013,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         else if (blocks) ops = W + stats;
         else ops = W + (has_zero ? 2.0 * W : 0) + nz * stats;
         double setup = (double)(w.pe - g) * 2.0 * W;
-        if (mono) setup += 5.0 * H.n_monohi + 5.0 * img[H.off_aidx + g] + 4.0 * g + (blocks ? 12.0 * H.n_c2 : 0);
+        if (mono) setup += 5.0 * H.n_monohi + 5.0 * img[H.off_aidx + g] + 4.0 * g + (blocks ? (4.0 + 4.0 * NF) * H.n_c2 : 0);
         const uint64_t steps = (uint64_t)1 << g;
         double walk = 0;
         const uint32_t *didx = img.data() + H.off_didx;
@@ -1043,18 +1033,18 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             for (uint64_t t = 1; t < steps; ++t)
                 walk += flip_cost(__builtin_ctzll(t), (uint32_t)(t ^ (t >> 1)));
         } else {
-            const uint64_t nb = steps >> kInnerBits;
+            const uint64_t nb = steps >> KB;
             const uint32_t *c3idx = img.data() + H.off_c3idx;
             const uint32_t *c3 = img.data() + H.off_c3;
-            walk += (double)nb * ((has_zero ? 2.0 * W : 0) + (mono ? 2 : 0));
+            walk += (double)nb * ((has_zero ? 2.0 * W : 0) + (mono ? NF : 0));
             for (uint64_t b = 1; b < nb; ++b) {
-                const int i = kInnerBits + __builtin_ctzll(b);
-                const uint32_t gray = (uint32_t)((b ^ (b >> 1)) << kInnerBits);
+                const int i = KB + __builtin_ctzll(b);
+                const uint32_t gray = (uint32_t)((b ^ (b >> 1)) << KB);
                 walk += W + flip_cost(i, gray);
                 if (!mono) continue;
                 for (uint32_t e = c3idx[i]; e < c3idx[i + 1]; ++e) {
-                    const uint32_t other = c3[8 * e + 4];
-                    if ((gray & other) == other) walk += 12;
+                    const uint32_t other = c3[C3S * e + 2 * NF];
+                    if ((gray & other) == other) walk += 4 + 4 * NF;
                 }
             }
         }
