@@ -335,6 +335,98 @@ static double nonzero_fraction(const std::vector<IrForm> &forms, const std::vect
     return std::ldexp(1.0, -rank);
 }
 
+// Which parameters are walked, and in what order (walk position q + j for walked[j]), decides
+// the walk's per-block work on variable monomials: a monomial costs work at each flip of one
+// of its outer walk positions i >= KB, an entry of the flip list when it also needs walk bits
+// above i, an inner-vector entry (about three times the work) when it also has an inner
+// variable, and position i flips once every 2^(i - KB + 1) blocks.  Starting from the given
+// order, swaps of two walked parameters, or of a walked and an unwalked one (never a query
+// parameter), are kept while that estimate drops.  The order changes no term's value.
+std::vector<int> refine_walk_order(const Work &w, int p, int q, int inner_p, std::vector<int> walked) {
+    const int g_orig = (int)walked.size();
+    if (w.mono.empty() || g_orig < 2) return walked;
+    // the form-vector width, hence the inner bits, does not depend on the order: every node
+    // factor owns a bit and linear terms share the bits of their forms
+    std::vector<char> node_form(w.forms.size(), 0), lin_bit(w.forms.size(), 0);
+    int F = (int)w.nodes.size();
+    for (const auto &n : w.nodes) node_form[n.first] = 1;
+    for (const auto &l : w.lin)
+        if (!node_form[l.second] && !lin_bit[l.second]) {
+            lin_bit[l.second] = 1;
+            ++F;
+        }
+    int Wd = 1;
+    while (Wd * 32 < F) Wd *= 2;
+    const int KB = inner_bits_for((uint32_t)Wd);
+    if (q + g_orig <= KB) return walked;
+    std::vector<std::vector<int>> mv;
+    for (const auto &m : w.mono) {
+        std::vector<int> vs;
+        for (int v : m.first) vs.push_back(v - q);
+        mv.push_back(vs);
+    }
+    std::vector<int> wpos(p, -1);
+    auto cost = [&](const std::vector<int> &wk) {
+        for (size_t j = 0; j < wk.size(); ++j) wpos[wk[j]] = q + (int)j;
+        const int G = q + (int)wk.size();
+        const uint32_t inner_mask = (1u << KB) - 1;
+        double c = 0;
+        for (const auto &vs : mv) {
+            uint32_t M = 0;
+            for (int v : vs)
+                if (wpos[v] >= 0) M |= 1u << wpos[v];
+            const uint32_t inner = M & inner_mask;
+            for (int i = KB; i < G; ++i) {
+                if (!(M >> i & 1)) continue;
+                const double freq = std::ldexp(1.0, -(i - KB + 1));
+                const uint32_t others = M & ~(1u << i);
+                const uint32_t below = (1u << (i - 1)) - 1;
+                if (!(others & below) && (others >> (i + 1))) c += freq;  // flip-list entry
+                if (inner) {
+                    const uint32_t other = others & ~inner_mask;
+                    const uint32_t clear_below = i - 1 > KB ? ((1u << (i - 1)) - 1) & ~inner_mask : 0u;
+                    if (!(other & clear_below)) c += 3.0 * freq;  // inner-vector entry
+                }
+            }
+        }
+        for (int v : wk) wpos[v] = -1;
+        return c;
+    };
+    std::vector<char> in_walk(p, 0);
+    for (int v : walked) in_walk[v] = 1;
+    std::vector<int> pool;
+    for (int v = 0; v < inner_p; ++v)
+        if (!in_walk[v]) pool.push_back(v);
+    double best = cost(walked);
+    for (int pass = 0; pass < 32; ++pass) {
+        bool improved = false;
+        for (int a = 0; a < g_orig; ++a) {
+            for (int b = a + 1; b < g_orig; ++b) {
+                std::swap(walked[a], walked[b]);
+                const double c = cost(walked);
+                if (c < best - 1e-12) {
+                    best = c;
+                    improved = true;
+                } else {
+                    std::swap(walked[a], walked[b]);
+                }
+            }
+            for (size_t u = 0; u < pool.size(); ++u) {
+                std::swap(walked[a], pool[u]);
+                const double c = cost(walked);
+                if (c < best - 1e-12) {
+                    best = c;
+                    improved = true;
+                } else {
+                    std::swap(walked[a], pool[u]);
+                }
+            }
+        }
+        if (!improved) break;
+    }
+    return walked;
+}
+
 int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err) {
     PackedProgram &P = *out;
     P = PackedProgram();
@@ -436,6 +528,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     std::sort(walked.begin(), walked.end(), [&](int a, int b) {
         return inc[a] != inc[b] ? inc[a] < inc[b] : a < b;
     });
+    walked = refine_walk_order(w, p, q, inner_p, walked);
     std::vector<char> is_walked(p, 0);
     for (int v : walked) is_walked[v] = 1;
     std::vector<int> pos_of(w.pe, -1);  // eval variable -> packed position
