@@ -126,7 +126,9 @@ typedef struct {
                                vanishes (only those terms reach the factor statistics) */
     uint32_t n_outer;       /* query parameters (OUTCOMES programs: n_qubits, else 0); an output
                                string costs 2^(p - n_outer) terms */
-    uint32_t reserved_info;
+    uint32_t vanish_table_bits; /* z > 0: the vanishing factors own the low z bits of the form
+                               vector and a block's surviving terms are read from a 2^z-entry
+                               table; 0: found by the reduced-basis test (or nothing vanishes) */
 } sim_info;
 
 /* launch shape of the evaluation kernels; zero fields take the library's choice */

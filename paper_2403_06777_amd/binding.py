@@ -78,7 +78,7 @@ class sim_info(ctypes.Structure):
                 ("is_zero", ctypes.c_uint32), ("compile_seconds", ctypes.c_double),
                 ("t_count", ctypes.c_uint32), ("n_constraints", ctypes.c_uint32),
                 ("ops_per_term", ctypes.c_double), ("nonzero_fraction", ctypes.c_double),
-                ("n_outer", ctypes.c_uint32), ("reserved_info", ctypes.c_uint32)]
+                ("n_outer", ctypes.c_uint32), ("vanish_table_bits", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -327,6 +327,7 @@ void fill_info(const PackedProgram &pk, double compile_seconds, uint32_t t_count
     out->ops_per_term = pk.ops_per_term;
     out->nonzero_fraction = pk.nonzero_fraction;
     out->n_outer = (uint32_t)pk.outer;
+    out->vanish_table_bits = pk.hdr.ztab_bits;
 }
 }  // namespace
 

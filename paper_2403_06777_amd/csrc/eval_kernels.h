@@ -433,7 +433,39 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
 #pragma unroll
             for (int j = 0; j < NF; ++j) fv[j] = odd ? v1[j] : v0[j];
         }
-        if (ZERO && CQ) {
+        if (ZERO && CQ && H.ztab_bits) {
+            // The vanishing bits are the low z bits of word 0: a = L0 & (2^z - 1) picks from an
+            // LDS table the block's surviving steps (bit k: P(gray(k)) & zm = a), and each round
+            // every lane with a survivor left appends one, while any lane has one.
+            const uint32_t *zt =
+                reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + H.ztab_lds);
+            const uint32_t nz = 1u << H.ztab_bits;
+            uint32_t hits = valid ? zt[L[0] & (nz - 1u)] : 0u;
+            for (;;) {
+                const uint64_t m = __ballot(hits != 0u);
+                if (!m) break;
+                const uint32_t below =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (hits) {
+                    const uint32_t k = (uint32_t)__builtin_ctz(hits);
+                    hits &= hits - 1u;
+                    const uint32_t *pk = zt + nz + k * W;  // P(gray(k))
+                    uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                    for (int w = 0; w < W; ++w) words[w] = L[w] ^ pk[w];
+                    const int f = MONO ? (int)field_at<NF>(fv, k) : 0;
+                    words[W] = (uint32_t)(phi + f);
+                    uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
+                    e[0] = make_uint4(words[0], words[1], words[2], words[3]);
+                    if (kQueueWords<W> == 8) e[1] = make_uint4(words[4], words[5], words[6], words[7]);
+                }
+                Q->n += (uint32_t)__popcll(m);
+                if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, wd, tab, cnt, *Q, 64u, acc);
+            }
+            // the block's last state: gray(KS - 1) has only the top inner bit set
+#pragma unroll
+            for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
+        } else if (ZERO && CQ) {
             // Term k of the block has L0 ^ P(gray(k)), P the XOR of the inner columns of the set
             // bits, and survives iff a = (L0 & zm) equals P(gray(k)) & zm.  The coordinates of a
             // in the reduced basis of those vectors are its pivot bits; a is in their span iff
@@ -730,11 +762,15 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
     } else {
         for (uint32_t i = threadIdx.x; i < H.table_n * 4; i += blockDim.x) s_tab[i] = gtab[i];
     }
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(gtab) - H.table_byte_off);
     if (H.ntab_n) {
-        const uint32_t *g = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(gtab) -
-                                                               H.table_byte_off) + H.off_ntab;
         uint32_t *d = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_tab) + H.ntab_lds);
-        for (uint32_t i = threadIdx.x; i < H.ntab_n; i += blockDim.x) d[i] = g[i];
+        for (uint32_t i = threadIdx.x; i < H.ntab_n; i += blockDim.x) d[i] = words[H.off_ntab + i];
+    }
+    if (H.ztab_bits) {
+        const uint32_t n = (1u << H.ztab_bits) + (1u << inner_bits_for(H.W)) * H.W;
+        uint32_t *d = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_tab) + H.ztab_lds);
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = words[H.off_ztab + i];
     }
     __syncthreads();
 }

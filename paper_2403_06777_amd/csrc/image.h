@@ -86,6 +86,11 @@ struct ImgHeader {
     uint32_t off_ntab;  // ntab_n words: bit 0 vanishes, bits 1-7 A - B + d_off, bits 8-15 E,
                         // bits 16-18 the node part of R (mod 8)
     uint32_t ntab_lds;  // byte offset of the node table in dynamic LDS
+    uint32_t ztab_bits; // z > 0: the vanishing bits are bits 0 .. z-1 of word 0, and at off_ztab
+    uint32_t off_ztab;  //   come 2^z words (bit k of entry a: step k of a block whose first term
+                        //   has L & zmask = a survives) and the 2^KB values of P(gray(k)), W
+    uint32_t ztab_lds;  //   words each, P(y) = XOR of the inner columns picked by y; both are
+                        //   copied to dynamic LDS at byte offset ztab_lds
     uint32_t node_word0;  // the node-factor slot masks are zero beyond word 0
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "image.h"
 #include "kernels.h"
 #include "zw.h"
@@ -76,7 +78,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_finalize_batch(const Partial *_
 
 size_t dyn_lds_bytes(const ImgHeader &H) {
     const size_t base = H.acc == ACC_CLASS ? (size_t)H.zero_entry * H.q_limbs * 8 : (size_t)H.table_n * 32;
-    return H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4 : base;
+    const size_t end = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4 : base;
+    if (!H.ztab_bits) return end;
+    const size_t zwords = ((size_t)1 << H.ztab_bits) + ((size_t)1 << inner_bits_for(H.W)) * H.W;
+    return std::max(end, (size_t)H.ztab_lds + zwords * 4);
 }
 
 uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads) {

@@ -570,6 +570,11 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         node_owned.push_back(0);
         return (int)used.size() - 1;
     };
+    // factors that can vanish (1 + w^4 = 0 at one value of their form) first: their bits of L
+    // are then the lowest ones, which lets a block look its surviving steps up by those bits
+    std::stable_partition(w.nodes.begin(), w.nodes.end(), [](const std::pair<int, std::pair<int, int>> &n) {
+        return n.second.first == 4 || n.second.second == 4;
+    });
     for (auto &n : w.nodes) {
         int f = n.first;
         int b = form_slot[f];
@@ -1051,6 +1056,36 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             img.push_back(e);
         }
     }
+    // Surviving steps of a block by the vanishing bits, when those are the low z <= 11 bits of
+    // word 0 (compacting walks): entry a (z bits) has bit k set iff step k's term survives in a
+    // block whose first term has L & zmask = a, i.e. iff P(gray(k)) & zmask = a, P(y) the XOR of
+    // the inner columns picked by y; then come the KS values P(gray(k)) (W words each).  Both
+    // are copied to LDS after the other tables.
+    H.ztab_bits = 0;
+    H.off_ztab = (uint32_t)img.size();
+    {
+        const size_t end_lds = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4
+                                        : (acc_mode == ACC_CLASS ? (size_t)H.zero_entry * q_limbs * 8
+                                                                 : (size_t)H.table_n * 32);
+        H.ztab_lds = (uint32_t)((end_lds + 15) & ~(size_t)15);
+        const int z = __builtin_popcount(zmask[0]);
+        bool low = has_zero && g >= KB && W <= 4 && z >= 1 && z <= 11 && zmask[0] == (1u << z) - 1u;
+        for (int k = 1; k < W; ++k) low = low && zmask[k] == 0;
+        if (low) {
+            H.ztab_bits = (uint32_t)z;
+            std::vector<uint32_t> pstep((size_t)KS * W, 0);
+            for (int k = 0; k < KS; ++k) {
+                const int y = k ^ (k >> 1);
+                for (int j = 0; j < KB; ++j)
+                    if (y >> j & 1)
+                        for (int w2 = 0; w2 < W; ++w2) pstep[(size_t)k * W + w2] ^= img[H.off_col + j * W + w2];
+            }
+            std::vector<uint32_t> zt((size_t)1 << z, 0);
+            for (int k = 0; k < KS; ++k) zt[pstep[(size_t)k * W] & zmask[0]] |= 1u << k;
+            img.insert(img.end(), zt.begin(), zt.end());
+            img.insert(img.end(), pstep.begin(), pstep.end());
+        }
+    }
     std::vector<int64_t> table((size_t)H.table_n * 4, 0);
     for (int d = (int)dmin; d <= (int)dmax; ++d)
         for (int r = 0; r < 8; ++r)
@@ -1083,7 +1118,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     //  * walks of at least KB positions: with factors that can vanish, each term's
     //    vanishing test (a W-word compare) and for a surviving term the rebuild of its form
     //    vector (W); otherwise each term's column XOR (W).  Per block: the outer column XOR (W),
-    //    with vanishing factors the masked start vector and the end XOR (2W), with monomials
+    //    with vanishing factors the masked start vector and the end XOR (2W; with the table of
+    //    surviving steps its index and the end XOR, 1 + W), with monomials
     //    the vector-pair selection (NF), the flip's own change (5), 5 per firing slice-dependent
     //    flip entry and 4 + 4 NF per toggling inner-vector entry (slice test, 2 NF field adds);
     //  * shorter walks: per term the column XOR (W), the vanishing test (2W) and the flip
@@ -1129,7 +1165,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             const uint64_t nb = steps >> KB;
             const uint32_t *c3idx = img.data() + H.off_c3idx;
             const uint32_t *c3 = img.data() + H.off_c3;
-            walk += (double)nb * ((has_zero ? 2.0 * W : 0) + (mono ? NF : 0));
+            const double vanish_test = H.ztab_bits ? 1.0 + W : 2.0 * W;  // table index, or masked start
+            walk += (double)nb * ((has_zero ? vanish_test : 0) + (mono ? NF : 0));
             for (uint64_t b = 1; b < nb; ++b) {
                 const int i = KB + __builtin_ctzll(b);
                 const uint32_t gray = (uint32_t)((b ^ (b >> 1)) << KB);

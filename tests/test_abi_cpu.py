@@ -26,6 +26,14 @@ def test_binding_exposes_c_names():
         assert hasattr(zx, name) or name in ("sim_last_error",), name
 
 
+def test_vanishing_step_table_is_reported():
+    # the kernel-sized program of seed 0 has 11 vanishing factors (table path), seed 1 has 12
+    # (reduced-basis path); programs without vanishing factors report 0
+    assert zx.sim_ir_info(wl.kernel_sized_program(0).to_text())["vanish_table_bits"] == 11
+    assert zx.sim_ir_info(wl.kernel_sized_program(1).to_text())["vanish_table_bits"] == 0
+    assert zx.sim_ir_info(wl.random_program(0, 10, n_nodes=0, n_lin=8).to_text())["vanish_table_bits"] == 0
+
+
 def test_ir_info_kernel_sized():
     prog = wl.kernel_sized_program(0)
     info = zx.sim_ir_info(prog.to_text())

@@ -103,6 +103,36 @@ def test_closed_form_with_monomials(o2):
     assert gpu_value(full.to_text()) == zw.canonical(expect, 0)
 
 
+def test_vanishing_step_table_and_basis_paths(o2):
+    # a block's surviving steps come from a table indexed by the vanishing bits (at most 11 of
+    # them) or from the reduced-basis test (more); both against the oracle, exhaustively at
+    # p = 20 and on sampled slices at p = 32
+    seen = set()
+    for seed in range(6):
+        text = wl.kernel_sized_program(seed, p=20, n_factors=64, n_monomials=200).to_text()
+        z = zx.sim_ir_info(text)["vanish_table_bits"]
+        seen.add(z > 0)
+        say("vanishing steps", seed, z)
+        assert gpu_value(text) == oracle_value(o2, text)
+    assert seen == {True, False}
+    for seed in (1, 3):  # p = 32: basis test, table
+        text = wl.kernel_sized_program(seed).to_text()
+        h = zx.sim_program_from_ir(text)
+        try:
+            info = zx.sim_program_info(h)
+            assert (info["vanish_table_bits"] > 0) == (seed == 3)
+            perm = zx.sim_program_layout(h)
+            wb, ns = info["walk_bits"], info["n_slices"]
+            rng = wl.SplitMix64(78, seed)
+            for _ in range(3):
+                s0 = rng.randint(0, ns - 16)
+                say("vanishing steps p32", seed, s0)
+                ref = o2.evaluate(text, first=s0 << wb, count=16 << wb, perm=perm)["raw"]
+                assert zx.sim_eval_range(h, s0, 16) == ref
+        finally:
+            zx.sim_program_free(h)
+
+
 def test_kernel_sized_full_size_sampled_slices(o2):
     # p = 32: the whole sum equals the sum of range partials, and sampled ranges equal the
     # oracle on exactly the same assignments
