@@ -98,11 +98,15 @@ typedef struct {
 /* p_cap: refuse (SIM_ERANGE) programs with more parameters (0 = 48).
  * eliminate_constraints: 1 (default when opts is NULL) substitutes away every parameter
  * fixed by a parity constraint of the simplified diagram (a factor that is 0 or 2), so the
- * program has p' <= p parameters and 2^p' terms; 0 keeps them as 0/2-valued factors. */
+ * program has p' <= p parameters and 2^p' terms; 0 keeps them as 0/2-valued factors.
+ * t_spiders_only: 0 (default) lets the decomposition give a parameter to any spider, taking
+ * the one that removes the most T-like spiders (itself, and its T-like neighbours of degree 1,
+ * which become node factors); 1 parameterises T-like spiders only. */
 typedef struct {
     uint32_t p_cap;
     uint32_t eliminate_constraints;
-    uint32_t reserved[6];
+    uint32_t t_spiders_only;
+    uint32_t reserved[5];
 } sim_compile_opts;
 
 typedef struct {

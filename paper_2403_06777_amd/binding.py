@@ -66,7 +66,7 @@ class sim_query(ctypes.Structure):
 
 class sim_compile_opts(ctypes.Structure):
     _fields_ = [("p_cap", ctypes.c_uint32), ("eliminate_constraints", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("t_spiders_only", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
 
 class sim_info(ctypes.Structure):
@@ -216,10 +216,11 @@ def prefix_query(n_qubits: int, k: int, prefix_bits: Optional[str] = None):
     return _query(SIM_QUERY_PREFIX, n_qubits, bits, k)
 
 
-def _opts(p_cap: int = 0, eliminate_constraints: bool = True):
+def _opts(p_cap: int = 0, eliminate_constraints: bool = True, t_spiders_only: bool = False):
     o = sim_compile_opts()
     o.p_cap = p_cap
     o.eliminate_constraints = 1 if eliminate_constraints else 0
+    o.t_spiders_only = 1 if t_spiders_only else 0
     return o
 
 
@@ -245,11 +246,12 @@ def sim_program_from_ir(ir_text: str) -> int:
     return h.value
 
 
-def sim_compile(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True) -> int:
+def sim_compile(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True,
+                t_spiders_only: bool = False) -> int:
     q, _keep = query
     data = circuit_text.encode()
     h = _P()
-    o = _opts(p_cap, eliminate_constraints)
+    o = _opts(p_cap, eliminate_constraints, t_spiders_only)
     _check(lib().sim_compile(data, len(data), ctypes.byref(q), ctypes.byref(o), ctypes.byref(h)))
     return h.value
 
@@ -267,10 +269,11 @@ def sim_ir_info(ir_text: str) -> dict:
     return out.as_dict()
 
 
-def sim_compile_to_ir(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True):
+def sim_compile_to_ir(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True,
+                      t_spiders_only: bool = False):
     q, _keep = query
     data = circuit_text.encode()
-    o = _opts(p_cap, eliminate_constraints)
+    o = _opts(p_cap, eliminate_constraints, t_spiders_only)
     n = ctypes.c_size_t()
     info = sim_info()
     _check(lib().sim_compile_to_ir(data, len(data), ctypes.byref(q), ctypes.byref(o), None, 0,

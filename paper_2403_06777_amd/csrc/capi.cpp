@@ -290,6 +290,7 @@ int sim_compile(const char *circuit_text, size_t len, const sim_query *q, const 
     if (opts) {
         if (opts->p_cap) co.p_cap = (int)opts->p_cap;
         co.eliminate_constraints = opts->eliminate_constraints != 0;
+        co.hub_params = opts->t_spiders_only == 0;
     }
     CompileStats cs;
     std::string err;
@@ -351,6 +352,7 @@ extern "C" int sim_compile_to_ir(const char *circuit_text, size_t len, const sim
     if (opts) {
         if (opts->p_cap) co.p_cap = (int)opts->p_cap;
         co.eliminate_constraints = opts->eliminate_constraints != 0;
+        co.hub_params = opts->t_spiders_only == 0;
     }
     CompileStats cs;
     std::string err;

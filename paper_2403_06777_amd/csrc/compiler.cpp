@@ -308,6 +308,7 @@ struct Graph {
     std::vector<int> deg;
     int n_params = 0;
     int t_like = 0;
+    bool hub_params = false;  // a parameter may go to a spider whose T-like leaves it isolates
     Scalar *sc = nullptr;
     Emitted *em = nullptr;
 
@@ -516,10 +517,25 @@ struct Graph {
                 rule_fuse(u, N[0], N[1]);
                 return true;
             }
-        // decomposition: parameterise the T-like spider of highest degree
-        int best = -1;
-        for (int v = 0; v < n; ++v)
-            if (alive[v] && (a[v] & 1) && (best < 0 || deg[v] > deg[best])) best = v;
+        // decomposition: parameterise one spider.  Its T-like neighbours of degree 1 are then
+        // isolated, i.e. node factors needing no parameter of their own, so the spider that
+        // removes the most T-like spiders (itself if T-like, plus those neighbours) is taken;
+        // ties go to a T-like spider, then to the highest degree
+        int best = -1, best_gain = 0;
+        for (int v = 0; v < n; ++v) {
+            if (!alive[v]) continue;
+            int gain = a[v] & 1;
+            if (hub_params)
+                for (int u : nbrs(v)) gain += (a[u] & 1) && deg[u] == 1;
+            if (!gain) continue;
+            const bool better = best < 0 || gain > best_gain ||
+                                (gain == best_gain && ((a[v] & 1) > (a[best] & 1) ||
+                                                       ((a[v] & 1) == (a[best] & 1) && deg[v] > deg[best])));
+            if (better) {
+                best = v;
+                best_gain = gain;
+            }
+        }
         if (best >= 0) {
             rule_param(best, p_limit);
             return true;
@@ -765,6 +781,7 @@ int compile_circuit(const char *text, size_t len, const sim_query &q, const Comp
             for (const auto &t : B.toggles) G.toggle(t.first, t.second);
             for (const auto &pv : B.polar) G.l[pv.first].flip(pv.second);
             G.n_params = n_outer;  // parameters 0 .. n_outer-1 are the output bits
+            G.hub_params = opts.hub_params;
             for (int v = 0; v < G.n; ++v) t_like += G.a[v] & 1;
             const int p_limit = kParamWords * 64;
             while (!sc.zero && G.step(p_limit)) {

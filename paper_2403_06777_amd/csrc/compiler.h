@@ -9,6 +9,7 @@
 struct CompileOptions {
     int p_cap = 48;
     bool eliminate_constraints = true;
+    bool hub_params = true;  // a parameter may go to any spider (see sim_compile_opts)
 };
 
 struct CompileStats {

@@ -281,3 +281,22 @@ def test_prefix_query_length_is_checked(k):
     with pytest.raises(zx.SimError) as ei:
         zx.sim_compile_to_ir(wl.circuit_text(c), zx.prefix_query(6, k))
     assert ei.value.code == -1 and "prefix length" in str(ei.value)
+
+
+def test_parameters_on_hub_spiders_keep_values_and_cut_terms(o2):
+    # a parameter on a spider whose T-like leaves it isolates (they become node factors) is a
+    # relabelling of the same sum: both decompositions give the exact amplitude, and over the
+    # batch family the hub choice needs fewer terms in total
+    for seed in range(12):
+        c = _rand_circuit(900 + seed, 3 + seed % 5, 30 + 4 * seed, 4 + seed % 7)
+        text = wl.circuit_text(c)
+        y = "".join("1" if (seed >> i) & 1 else "0" for i in range(c.n_qubits))
+        want = sv.exact_amplitude(text, y)
+        for t_only in (False, True):
+            assert compiled_value(o2, text, zx.amplitude_query(y), t_spiders_only=t_only)[0] == want
+    hub = plain = 0
+    for c, y in wl.batch_queries(48):
+        text = wl.circuit_text(c)
+        hub += 2 ** zx.sim_compile_to_ir(text, zx.amplitude_query(y), p_cap=60)[1]["n_params"]
+        plain += 2 ** zx.sim_compile_to_ir(text, zx.amplitude_query(y), p_cap=60, t_spiders_only=True)[1]["n_params"]
+    assert hub < plain
