@@ -456,6 +456,41 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             w.nodes.push_back({n.form, {v0, v1}});
         }
     }
+    // Two node factors on the same parity (equal masks; a constant of 1 swaps a factor's two
+    // values) whose product is the same at both values of the parity are that constant: the
+    // pairwise cancellation of node subterms whose constants differ by pi that the paper leaves
+    // for future work (Section 5), applied to every program.  1 + w^0 with 1 + w^4 on one parity
+    // makes the whole program zero.
+    {
+        std::vector<char> gone(w.nodes.size(), 0);
+        auto oriented = [&](size_t i) {  // the factor's exponents at <mask, x> = 0 and = 1
+            const auto &n = w.nodes[i];
+            return w.forms[n.first].cst ? std::make_pair(n.second.second, n.second.first) : n.second;
+        };
+        for (size_t i = 0; i < w.nodes.size(); ++i) {
+            if (gone[i]) continue;
+            const uint64_t mi = w.forms[w.nodes[i].first].mask;
+            const auto vi = oriented(i);
+            for (size_t j = i + 1; j < w.nodes.size(); ++j) {
+                if (gone[j] || w.forms[w.nodes[j].first].mask != mi) continue;
+                const auto vj = oriented(j);
+                Zw at0, at1;
+                if (!zw_mul_checked(one_plus_w(vi.first), one_plus_w(vj.first), &at0) ||
+                    !zw_mul_checked(one_plus_w(vi.second), one_plus_w(vj.second), &at1))
+                    continue;
+                bool same = true;
+                for (int k = 0; k < 4; ++k) same = same && at0.c[k] == at1.c[k];
+                if (!same) continue;
+                if (!mul_const(&w, at0, err)) return SIM_ERANGE;
+                gone[i] = gone[j] = 1;
+                break;
+            }
+        }
+        std::vector<std::pair<int, std::pair<int, int>>> kept;
+        for (size_t i = 0; i < w.nodes.size(); ++i)
+            if (!gone[i]) kept.push_back(w.nodes[i]);
+        w.nodes.swap(kept);
+    }
     for (int k = 0; k < q; ++k) {
         const IrPair &pr = ir.pairs[k];
         uint64_t zbit = (uint64_t)1 << k;

@@ -112,3 +112,21 @@ def test_null_arguments_are_rejected():
     out = binding.sim_zomega()
     assert lib.sim_eval_amplitude(None, None, ctypes.byref(out)) == binding.SIM_EINVAL
     assert b"null" in lib.sim_last_error()
+
+
+def test_node_pairs_with_constant_product_are_folded():
+    # (1 + w^{2 + 4l})(1 + w^{6 + 4l}) = 2 for every l (the node cancellation of Section 5):
+    # the pair leaves the packed program; 1 + w^{4l} with 1 + w^{4 + 4l} makes it zero; a pair
+    # whose product does depend on l stays
+    from workloads.programs import ProgramSpec
+    pr = ProgramSpec(4)
+    f = pr.add_form(0, 0b0111)
+    g = pr.add_form(1, 0b0111)  # the complement of f
+    h = pr.add_form(0, 0b1010)
+    pr.nodes += [(f, 2, 4), (f, 6, 4), (g, 1, 4), (f, 5, 4), (h, 3, 4)]
+    info = zx.sim_ir_info(pr.to_text())
+    assert info["n_factors"] == 3 and not info["is_zero"]
+    pr2 = ProgramSpec(3)
+    f2 = pr2.add_form(0, 0b011)
+    pr2.nodes += [(f2, 0, 4), (f2, 4, 4), (pr2.add_form(0, 0b100), 1, 4)]
+    assert zx.sim_ir_info(pr2.to_text())["is_zero"] == 1

@@ -103,6 +103,25 @@ def test_closed_form_with_monomials(o2):
     assert gpu_value(full.to_text()) == zw.canonical(expect, 0)
 
 
+def test_folded_node_pairs_keep_the_sum(o2):
+    # random programs with planted node pairs whose product is constant (some on complemented
+    # forms, some making the program zero): the packed program, without them, has the sum of
+    # the program as written
+    from workloads.programs import ProgramSpec
+    for seed in range(8):
+        prog = wl.random_program(seed, 12, n_nodes=10, n_lin=6, n_mono=12)
+        rng = wl.SplitMix64(79, seed)
+        for _ in range(3):
+            f = rng.randint(0, len(prog.forms) - 1)
+            cst, mask = prog.forms[f]
+            g = prog.add_form(1 - cst, mask)
+            a = rng.choice([1, 2, 3, 5, 6, 7]) if seed % 4 else rng.choice([0, 4])
+            prog.nodes += [(f, a, 4), (g, a, 4)]  # values swapped: product constant
+        text = prog.to_text()
+        say("folded node pairs", seed, zx.sim_ir_info(text)["n_factors"], len(prog.nodes))
+        assert gpu_value(text) == oracle_value(o2, text)
+
+
 def test_vanishing_step_table_and_basis_paths(o2):
     # a block's surviving steps come from a table indexed by the vanishing bits (at most 11 of
     # them) or from the reduced-basis test (more); both against the oracle, exhaustively at
