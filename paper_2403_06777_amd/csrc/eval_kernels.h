@@ -290,7 +290,7 @@ __device__ __forceinline__ uint32_t field_at(const uint32_t (&fv)[NF], uint32_t 
 // (valid = false) and never report a surviving term, so the queue is always operated on by
 // the whole wave.
 // Blocks [b0, b1) of the slice are walked; L and phi hold the state of block b0's first term.
-template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ>
+template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ, bool ZT>
 __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
                                             unsigned long long *cnt, uint64_t s, bool valid, uint32_t b0,
                                             uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, WaveQueue *Q,
@@ -360,9 +360,10 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     // What the flip at the start of the next block reads (its column and its position record)
     // is loaded one block ahead, so that the scalar loads overlap the current block's work
     // instead of stalling the flip.
-    CV8 *recs = reinterpret_cast<CV8 *>(wd + H.off_pos);
+    CV4 *recs = reinterpret_cast<CV4 *>(wd + H.off_pos);
     uint32_t cn[W];
-    u32x8 rn = {0, 0, 0, 0, 0, 0, 0, 0};  // ui, flip entries [rn[1], rn[2]), inner-vector entries [rn[3], rn[4])
+    // ui; flip entries [lo, hi) of word 1 (16 bits each); inner-vector entries [lo, hi) of word 2
+    u32x4 rn = {0, 0, 0, 0};
     if (b0 + 1 < b1) {
         const uint32_t i = KB + (uint32_t)__builtin_ctz(b0 + 1);
 #pragma unroll
@@ -375,7 +376,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             gray ^= 1u << i;
 #pragma unroll
             for (int w = 0; w < W; ++w) L[w] ^= cn[w];
-            const u32x8 r = rn;
+            const u32x4 r = rn;
             if (b + 1 < b1) {
                 const uint32_t in = KB + (uint32_t)__builtin_ctz(b + 1);
 #pragma unroll
@@ -387,7 +388,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                 // entries that depend on walk bits above i
                 int dd = (int)r[0] + (int)((dal >> (4 * i)) & 7u);
                 CV4 *de = reinterpret_cast<CV4 *>(wd + H.off_delta);
-                for (uint32_t e = r[1]; e < r[2]; ++e) {
+                for (uint32_t e = r[1] & 0xFFFFu; e < (r[1] >> 16); ++e) {
                     const u32x4 d = de[e];  // c, walk mask, slice mask lo, hi
                     const uint32_t c = d[0], wm = d[1], hl = d[2], hh = d[3];
                     if ((gray & wm) != wm) continue;
@@ -399,7 +400,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                 // whose other outer bits are set switch on (bit i now 1) or off
                 const bool on = (gray >> i) & 1u;
                 CV8 *e3 = reinterpret_cast<CV8 *>(wd + H.off_c3);
-                for (uint32_t e = r[3]; e < r[4]; ++e) {
+                for (uint32_t e = r[2] & 0xFFFFu; e < (r[2] >> 16); ++e) {
                     // even[NF], odd[NF], other outer bits, slice mask lo, hi (4 NF words)
                     uint32_t v[4 * NF];
 #pragma unroll
@@ -433,7 +434,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
 #pragma unroll
             for (int j = 0; j < NF; ++j) fv[j] = odd ? v1[j] : v0[j];
         }
-        if (ZERO && CQ && H.ztab_bits) {
+        if (ZERO && CQ && ZT) {
             // The vanishing bits are the low z bits of word 0: a = L0 & (2^z - 1) picks from an
             // LDS table the block's surviving steps (bit k: P(gray(k)) & zm = a), and each round
             // every lane with a survivor left appends one, while any lane has one.
@@ -465,7 +466,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             // the block's last state: gray(KS - 1) has only the top inner bit set
 #pragma unroll
             for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
-        } else if (ZERO && CQ) {
+        } else if (ZERO && CQ) {  // !ZT
             // Term k of the block has L0 ^ P(gray(k)), P the XOR of the inner columns of the set
             // bits, and survives iff a = (L0 & zm) equals P(gray(k)) & zm.  The coordinates of a
             // in the reduced basis of those vectors are its pivot bits; a is in their span iff
@@ -657,14 +658,20 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         }
     }
     if (CQ) {
-        walk_blocks<W, MONO, ACC, SET, true, true>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q, acc);
+        // the table of surviving steps or the reduced-basis test, chosen once per slice (two
+        // copies of the loop, so that neither holds the other's registers)
+        if (H.ztab_bits)
+            walk_blocks<W, MONO, ACC, SET, true, true, true>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q, acc);
+        else
+            walk_blocks<W, MONO, ACC, SET, true, true, false>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q,
+                                                               acc);
         return;
     }
     if (H.g >= (uint32_t)inner_bits_for(W)) {
         if (!H.has_zero)
-            walk_blocks<W, MONO, ACC, SET, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
+            walk_blocks<W, MONO, ACC, SET, false, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
         else if (!kCompact<W>)
-            walk_blocks<W, MONO, ACC, SET, true, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
+            walk_blocks<W, MONO, ACC, SET, true, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
         return;
     }
     // short walks: one step at a time

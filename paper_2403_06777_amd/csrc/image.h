@@ -130,9 +130,9 @@ struct ImgHeader {
     uint32_t n_c3;        //   4 NF words (aligned): even[NF], odd[NF], its other outer walk bits,
                           //   slice mask lo, hi, zeros; at a flip of i with the other bits set it
                           //   toggles on or off
-    uint32_t off_pos;     // g records of 8 words (32-byte aligned), one per walk position i:
-                          //   ui[i], didx[i], didx[i+1], c3idx[i], c3idx[i+1], 0, 0, 0 (what a
-                          //   flip of i reads, in one load)
+    uint32_t off_pos;     // g records of 4 words (16-byte aligned), one per walk position i:
+                          //   ui[i], didx[i] | didx[i+1] << 16, c3idx[i] | c3idx[i+1] << 16, 0
+                          //   (what a flip of i reads, in one load)
     // A walk may start at any block of a slice (the work of a wave is a contiguous range of
     // blocks); its start state then needs:
     uint32_t off_c3all;   // n_c3all entries, 2 NF + 3 words: the inner-and-outer monomials once

@@ -1032,13 +1032,18 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     while (img.size() % 8) img.push_back(0);  // entries are read with 32-byte loads
     H.off_c3 = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) img.insert(img.end(), c3pos[i].begin(), c3pos[i].end());
-    // one record per walk position: everything a flip of it reads first
-    while (img.size() % 8) img.push_back(0);
+    // one record per walk position: everything a flip of it reads first (entry ranges as
+    // 16-bit halves)
+    if (img[H.off_didx + g] > 0xFFFFu || c3start[g] > 0xFFFFu) {
+        *err = "more than 65535 walk list entries";
+        return SIM_ERANGE;
+    }
+    while (img.size() % 4) img.push_back(0);
     H.off_pos = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) {
         const uint32_t *didx = img.data() + H.off_didx;
-        const uint32_t rec[8] = {(uint32_t)ui[i], didx[i], didx[i + 1], c3start[i], c3start[i + 1], 0, 0, 0};
-        img.insert(img.end(), rec, rec + 8);
+        const uint32_t rec[4] = {(uint32_t)ui[i], didx[i] | (didx[i + 1] << 16), c3start[i] | (c3start[i + 1] << 16), 0};
+        img.insert(img.end(), rec, rec + 4);
     }
     // for a walk that starts inside a slice: each inner-and-outer monomial once, with its whole
     // outer mask, and every monomial with a walk part (c, walk mask, slice mask lo, hi)
