@@ -72,6 +72,9 @@ typedef struct {
 } sim_zomega;
 
 #define SIM_ZOMEGA_RAW 1u
+/* set by the device in an enqueued result (sim_enqueue_amplitude) whose product with the
+ * program constant left int128: the value is invalid (sim_eval_amplitude returns SIM_ERANGE) */
+#define SIM_ZOMEGA_OVERFLOW 2u
 
 /* A query on a Clifford+T circuit (Section 2.2).  AMPLITUDE: <y|C|0^n> with y_i =
  * out_bits[i] (0/1 bytes, n_qubits of them).  MARGINAL: P(qubit = value) =
@@ -248,6 +251,18 @@ SIM_API int sim_eval_ranges(const sim_program *const *progs, const uint64_t *fir
  * sim_eval_batch).  SIM_EINVAL if prog has no query parameters or a byte is not 0/1. */
 SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *bits, void *stream,
                               const sim_tuning *t, sim_zomega *out);
+
+/* <y|C|0^n> (or the program's sum) like sim_eval_amplitude, but enqueued on stream without
+ * waiting: the device writes the canonical value to dev_out (memory the caller owns and the
+ * device can write, one sim_zomega, 8-byte aligned) when the stream gets there; flags bit
+ * SIM_ZOMEGA_OVERFLOW marks an invalid value.  ev_before and ev_after, if not NULL, are
+ * hipEvent_t recorded on stream right before and after the evaluation kernel (not the
+ * finaliser), for timing.  Calls on one device share its scratch: an enqueued evaluation is
+ * ordered before any later call on the device, on any stream (later enqueues on another
+ * stream wait for it on the device, other calls on the host).  For pipelines of many
+ * evaluations without a host round trip between them. */
+SIM_API int sim_enqueue_amplitude(const sim_program *prog, void *stream, void *ev_before, void *ev_after,
+                                  sim_zomega *dev_out);
 
 /* Repeated weak simulation (Appendix E's algorithm, with the conditional probabilities of
  * the product rule of Section 2.3).  progs[k-1] is the PREFIX program of the first k qubits

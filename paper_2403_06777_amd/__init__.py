@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     sim_compile,
     sim_compile_to_ir,
     sim_device_cus,
+    sim_enqueue_amplitude,
     sim_eval_amplitude,
     sim_eval_batch,
     sim_eval_range,
@@ -37,6 +38,7 @@ from .binding import (  # noqa: F401
     sim_program_layout,
     sim_raw_add,
     sim_sample,
+    zomega_from_bytes,
 )
 
 

@@ -117,6 +117,7 @@ SIGNATURES = [
     ("sim_batch_plan_free", None, [_P]),
     ("sim_eval_outcomes", ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint8), _P,
                                          ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_enqueue_amplitude", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sim_marginal_sum", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint8), _P, ctypes.POINTER(sim_tuning),
                                         ctypes.POINTER(sim_zomega)]),
     ("sim_sample", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_size_t,
@@ -377,6 +378,21 @@ def sim_eval_outcomes(prog: int, out_strings: Sequence[str], stream=None, tuning
     outs = (sim_zomega * max(1, n))()
     _check(lib().sim_eval_outcomes(prog, n, bits, _stream(stream), _tuning(tuning), outs))
     return [_scalar(outs[i]) for i in range(n)]
+
+
+def sim_enqueue_amplitude(prog: int, dev_out: int, stream=None, ev_before: int = 0, ev_after: int = 0):
+    """Enqueues an evaluation whose canonical value the device writes to dev_out (the address of
+    72 bytes of device memory, 8-byte aligned); events (raw handles, 0 = none) bracket the kernel."""
+    _check(lib().sim_enqueue_amplitude(prog, _stream(stream), ev_before or None, ev_after or None, dev_out))
+
+
+def zomega_from_bytes(b: bytes):
+    """(coefficients, sqrt2 exponent) of a 72-byte sim_zomega written by the device; raises on the
+    overflow flag."""
+    z = sim_zomega.from_buffer_copy(bytes(b))
+    if z.flags & 2:
+        raise SimError(-2, "int128 overflow while applying the program constant")
+    return _scalar(z)
 
 
 def sim_marginal_sum(prog: int, pattern: str, stream=None, tuning: Optional[dict] = None):

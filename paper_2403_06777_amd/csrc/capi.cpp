@@ -67,6 +67,11 @@ struct DeviceState {
     bool aux_ready = false;       // auxiliary streams (default priority) for concurrent batch groups
     hipStream_t aux[4];
     hipEvent_t ev_fork, ev_join[4];
+    // evaluations enqueued without waiting (sim_enqueue_amplitude) still use the scratch above
+    // until ev_pending has been reached on pending_stream
+    hipEvent_t ev_pending = nullptr;
+    hipStream_t pending_stream = nullptr;
+    bool pending = false;
 };
 
 constexpr int kAux = 4;
@@ -74,6 +79,14 @@ constexpr int kAux = 4;
 constexpr int kMaxDevices = 64;
 DeviceState g_dev[kMaxDevices];
 std::mutex g_init_mu;
+
+// waits on the host for enqueued work that still uses the device's scratch (caller holds D.mu)
+int settle(DeviceState &D) {
+    if (!D.pending) return SIM_OK;
+    D.pending = false;
+    HIP_TRY(hipEventSynchronize(D.ev_pending));
+    return SIM_OK;
+}
 
 int ensure(DevBuf &b, size_t need) {
     if (b.cap >= need) return SIM_OK;
@@ -412,6 +425,7 @@ int sim_eval_amplitude(const sim_program *P, void *stream, sim_zomega *out) {
     int rc = enter_device(P, &D);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(D->mu);
+    if ((rc = settle(*D))) return rc;
     return eval_range_locked(*D, P, 0, P->pk.n_slices, false, (hipStream_t)stream, nullptr, out);
 }
 
@@ -426,7 +440,45 @@ int sim_eval_timed(const sim_program *P, void *stream, sim_zomega *out, float *k
     int rc = enter_device(P, &D);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(D->mu);
+    if ((rc = settle(*D))) return rc;
     return eval_range_locked(*D, P, 0, P->pk.n_slices, false, (hipStream_t)stream, nullptr, out, kernel_ms);
+}
+
+int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, void *ev_after, sim_zomega *dev_out) {
+    if (!P || !dev_out) return fail(SIM_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(dev_out) % 8) return fail(SIM_EINVAL, "dev_out must be 8-byte aligned");
+    DeviceState *D;
+    int rc = enter_device(P, &D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(D->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (!D->ev_pending) HIP_TRY(hipEventCreateWithFlags(&D->ev_pending, hipEventDisableTiming));
+    if (P->pk.zero) {
+        static const sim_zomega zero = {};
+        if (D->pending && D->pending_stream != st) HIP_TRY(hipStreamWaitEvent(st, D->ev_pending, 0));
+        if (ev_before) HIP_TRY(hipEventRecord((hipEvent_t)ev_before, st));
+        if (ev_after) HIP_TRY(hipEventRecord((hipEvent_t)ev_after, st));
+        HIP_TRY(hipMemcpyAsync(dev_out, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+        return SIM_OK;
+    }
+    const uint32_t threads = pick_threads(nullptr);
+    uint32_t blocks = 1;
+    if ((rc = eval_grid(*D, P, P->pk.n_slices, threads, nullptr, &blocks))) return rc;
+    if (D->partials.cap < (size_t)blocks * sizeof(Partial)) {
+        // growing the scratch frees the old buffer: enqueued work must be done with it
+        if ((rc = settle(*D))) return rc;
+        if ((rc = ensure(D->partials, (size_t)blocks * sizeof(Partial)))) return rc;
+    }
+    if (D->pending && D->pending_stream != st) HIP_TRY(hipStreamWaitEvent(st, D->ev_pending, 0));
+    Partial *parts = (Partial *)D->partials.ptr;
+    if (ev_before) HIP_TRY(hipEventRecord((hipEvent_t)ev_before, st));
+    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, 0, P->pk.n_slices, parts, blocks, threads, st));
+    if (ev_after) HIP_TRY(hipEventRecord((hipEvent_t)ev_after, st));
+    HIP_TRY(launch_finalize(parts, blocks, final_args(P->pk, false), reinterpret_cast<DevResult *>(dev_out), st));
+    HIP_TRY(hipEventRecord(D->ev_pending, st));
+    D->pending = true;
+    D->pending_stream = st;
+    return SIM_OK;
 }
 
 int sim_eval_range(const sim_program *P, uint64_t first_slice, uint64_t n_slices, void *stream, sim_zomega *raw) {
@@ -441,6 +493,7 @@ int sim_eval_range(const sim_program *P, uint64_t first_slice, uint64_t n_slices
     int rc = enter_device(P, &D);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(D->mu);
+    if ((rc = settle(*D))) return rc;
     return eval_range_locked(*D, P, first_slice, n_slices, true, (hipStream_t)stream, nullptr, raw);
 }
 
@@ -471,6 +524,7 @@ int sim_finalize(const sim_program *P, const sim_zomega *raw, void *stream, sim_
     int rc = enter_device(P, &D);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(D->mu);
+    if ((rc = settle(*D))) return rc;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = ensure(D->partials, sizeof(Partial)))) return rc;
     if ((rc = ensure(D->result, sizeof(DevResult)))) return rc;
@@ -757,6 +811,7 @@ int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, con
     HIP_TRY(hipSetDevice(dev));
     DeviceState &D = g_dev[dev];
     std::lock_guard<std::mutex> lk(D.mu);
+    if ((rc = settle(D))) return rc;
     BatchLayout L;
     if ((rc = build_layout(D, ps, n, first, count, raw, t, &L))) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -1064,6 +1119,7 @@ int sim_finalize_batch(const sim_program *const *ps, const sim_zomega *raws, siz
     HIP_TRY(hipSetDevice(dev));
     DeviceState &D = g_dev[dev];
     std::lock_guard<std::mutex> lk(D.mu);
+    if ((rc = settle(D))) return rc;
     hipStream_t st = (hipStream_t)stream;
     // one "item" per program whose partial is the raw sum given by the caller
     BatchLayout L;
@@ -1132,6 +1188,7 @@ int sim_batch_plan_create(const sim_program *const *ps, size_t n, const sim_tuni
     }
     // the device lock covers the layout (occupancy queries) and the capture (auxiliary streams)
     std::lock_guard<std::mutex> lk(g_dev[dev].mu);
+    if ((rc = settle(g_dev[dev]))) return rc;
     if ((rc = build_layout(g_dev[dev], ps, n, nullptr, nullptr, false, t, &plan->L))) return rc;
     const BatchLayout &L = plan->L;
     hipStream_t st = (hipStream_t)stream;

@@ -327,3 +327,42 @@ def test_node_table_programs(o2, n_nodes, n_lin, p):
         text = prog.to_text()
         say("node table", n_nodes, n_lin, p, seed, zx.sim_ir_info(text)["n_forms"])
         assert gpu_value(text) == oracle_value(o2, text)
+
+
+def test_enqueued_evaluations_match_synchronous_ones(o2):
+    # several programs enqueued back to back (one stream, then two streams, then mixed with
+    # synchronous calls that reuse the device's scratch): every device-written value equals the
+    # synchronous one; a zero program writes zero
+    import torch
+    texts = [wl.kernel_sized_program(seed, p=18 + seed, n_factors=32, n_monomials=60).to_text() for seed in range(4)]
+    texts.append(wl.random_program(5, 10, n_nodes=0, n_lin=4).to_text())
+    zero = ProgramSpecZero()
+    hs = [zx.sim_program_from_ir(t) for t in texts + [zero]]
+    try:
+        want = [zx.sim_eval_amplitude(h) for h in hs]
+        assert want[-1] == ((0, 0, 0, 0), 0)
+        say("enqueue", [zx.sim_program_info(h)["n_params"] for h in hs])
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        for streams in ([s1], [s1, s2]):
+            out = torch.zeros(72 * len(hs) * 2, dtype=torch.uint8, device="cuda")
+            for k in range(2 * len(hs)):
+                zx.sim_enqueue_amplitude(hs[k % len(hs)], out.data_ptr() + 72 * k, streams[k % len(streams)])
+                if k == 3:  # a synchronous call in between waits for the enqueued work
+                    assert zx.sim_eval_amplitude(hs[1]) == want[1]
+            torch.cuda.synchronize()
+            host = out.cpu().numpy().tobytes()
+            got = [zx.zomega_from_bytes(host[72 * k:72 * (k + 1)]) for k in range(2 * len(hs))]
+            assert got == want + want
+    finally:
+        for h in hs:
+            zx.sim_program_free(h)
+
+
+def ProgramSpecZero():
+    # 1 + w^4 as a constant factor: the program is zero
+    from workloads.programs import ProgramSpec
+    pr = ProgramSpec(6)
+    f = pr.add_form(1, 0)
+    pr.nodes.append((f, 0, 4))
+    pr.nodes.append((pr.add_form(0, 0b101), 1, 4))
+    return pr.to_text()
