@@ -223,7 +223,7 @@ constexpr uint32_t kQueueCap = 128;  // one append (<= 64) on top of < 64 pendin
 template <int W>
 constexpr bool kCompact = W <= 4;
 template <int W>
-constexpr int kQueueWords = W + 1 <= 4 ? 4 : 8;
+constexpr int kQueueWords = W + 1;  // the form vector and the phase, packed
 struct WaveQueue {
     uint32_t *q;  // this wave's kQueueCap entries in LDS
     uint32_t n;   // pending entries
@@ -240,16 +240,10 @@ __device__ __forceinline__ void queue_drain(const ImgHeader &H, CU32 *wd, const 
     Q.n -= count;
     __builtin_amdgcn_wave_barrier();
     if (lane < count) {
-        const uint4 *e = reinterpret_cast<const uint4 *>(Q.q + (Q.n + lane) * kQueueWords<W>);
-        const uint4 e0 = e[0];
-        uint32_t words[8] = {e0.x, e0.y, e0.z, e0.w, 0, 0, 0, 0};
-        if (kQueueWords<W> == 8) {
-            const uint4 e1 = e[1];
-            words[4] = e1.x;
-            words[5] = e1.y;
-            words[6] = e1.z;
-            words[7] = e1.w;
-        }
+        const uint32_t *e = Q.q + (Q.n + lane) * kQueueWords<W>;
+        uint32_t words[W + 1];
+#pragma unroll
+        for (int j = 0; j <= W; ++j) words[j] = e[j];
         uint32_t L[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) L[w] = words[w];
@@ -456,9 +450,9 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                     for (int w = 0; w < W; ++w) words[w] = L[w] ^ pk[w];
                     const int f = MONO ? (int)field_at<NF>(fv, k) : 0;
                     words[W] = (uint32_t)(phi + f);
-                    uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
-                    e[0] = make_uint4(words[0], words[1], words[2], words[3]);
-                    if (kQueueWords<W> == 8) e[1] = make_uint4(words[4], words[5], words[6], words[7]);
+                    uint32_t *e = Q->q + (Q->n + below) * kQueueWords<W>;
+#pragma unroll
+                    for (int j = 0; j <= W; ++j) e[j] = words[j];
                 }
                 Q->n += (uint32_t)__popcll(m);
                 if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, wd, tab, cnt, *Q, 64u, acc);
@@ -524,9 +518,9 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                         }
                         const int f = MONO ? (int)field_at<NF>(fv, k) : 0;
                         words[W] = (uint32_t)(phi + f);
-                        uint4 *e = reinterpret_cast<uint4 *>(Q->q + (Q->n + below) * kQueueWords<W>);
-                        e[0] = make_uint4(words[0], words[1], words[2], words[3]);
-                        if (kQueueWords<W> == 8) e[1] = make_uint4(words[4], words[5], words[6], words[7]);
+                        uint32_t *e = Q->q + (Q->n + below) * kQueueWords<W>;
+#pragma unroll
+                        for (int j = 0; j <= W; ++j) e[j] = words[j];
                     }
                     Q->n += (uint32_t)__popcll(m);
                     if (Q->n >= 64u) queue_drain<W, ACC, SET>(H, wd, tab, cnt, *Q, 64u, acc);
