@@ -429,13 +429,15 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             for (int j = 0; j < NF; ++j) fv[j] = odd ? v1[j] : v0[j];
         }
         if (ZERO && CQ && ZT) {
-            // The vanishing bits are the low z bits of word 0: a = L0 & (2^z - 1) picks from an
-            // LDS table the block's surviving steps (bit k: P(gray(k)) & zm = a), and each round
-            // every lane with a survivor left appends one, while any lane has one.
+            // The vanishing bits lie in word 0: a = L0 & zm is looked up in a hashed LDS table of
+            // the keys P(gray(k)) & zm with the masks of their steps (no key a: no survivor), and
+            // each round every lane with a survivor left appends one, while any lane has one.
             const uint32_t *zt =
                 reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + H.ztab_lds);
-            const uint32_t nz = 1u << H.ztab_bits;
-            uint32_t hits = valid ? zt[L[0] & (nz - 1u)] : 0u;
+            const uint32_t a = L[0] & S.zm[0];
+            const uint2 ent = reinterpret_cast<const uint2 *>(zt)[(a * H.ztab_mult) >> kZtabShift];
+            uint32_t hits = valid && ent.x == a ? ent.y : 0u;
+            const uint32_t nz = 2 * kZtabSlots;  // words of the hashed table: P(gray(k)) follow
             for (;;) {
                 const uint64_t m = __ballot(hits != 0u);
                 if (!m) break;
@@ -769,7 +771,7 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
         for (uint32_t i = threadIdx.x; i < H.ntab_n; i += blockDim.x) d[i] = words[H.off_ntab + i];
     }
     if (H.ztab_bits) {
-        const uint32_t n = (1u << H.ztab_bits) + (1u << inner_bits_for(H.W)) * H.W;
+        const uint32_t n = 2 * kZtabSlots + (1u << inner_bits_for(H.W)) * H.W;
         uint32_t *d = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_tab) + H.ztab_lds);
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = words[H.off_ztab + i];
     }

@@ -61,6 +61,8 @@ IMG_HD constexpr int slot_words(uint32_t set, int slot, int W) {
 // words, 16 for wider ones (whose unrolled block keeps 2^KB columns of W words in registers).
 // Programs with fewer walk bits use the plain step loop.
 constexpr int kMaxInnerBits = 5;
+constexpr uint32_t kZtabSlots = 256;  // slots of the table of surviving steps
+constexpr uint32_t kZtabShift = 24;   // 32 - log2(kZtabSlots)
 #ifdef __HIPCC__
 __host__ __device__
 #endif
@@ -86,11 +88,15 @@ struct ImgHeader {
     uint32_t off_ntab;  // ntab_n words: bit 0 vanishes, bits 1-7 A - B + d_off, bits 8-15 E,
                         // bits 16-18 the node part of R (mod 8)
     uint32_t ntab_lds;  // byte offset of the node table in dynamic LDS
-    uint32_t ztab_bits; // z > 0: the vanishing bits are bits 0 .. z-1 of word 0, and at off_ztab
-    uint32_t off_ztab;  //   come 2^z words (bit k of entry a: step k of a block whose first term
-                        //   has L & zmask = a survives) and the 2^KB values of P(gray(k)), W
-    uint32_t ztab_lds;  //   words each, P(y) = XOR of the inner columns picked by y; both are
-                        //   copied to dynamic LDS at byte offset ztab_lds
+    uint32_t ztab_bits; // z > 0: the z vanishing bits all lie in word 0, and at off_ztab come a
+    uint32_t ztab_mult; //   table of kZtabSlots (key, mask) pairs and the 2^KB values of
+    uint32_t off_ztab;  //   P(gray(k)), W words each, P(y) = XOR of the inner columns picked by y.
+    uint32_t ztab_lds;  //   A block whose first term has a = L & zmask reads the pair at slot
+                        //   (a * ztab_mult) >> (32 - log2 kZtabSlots): if its key is a, bit k
+                        //   of its mask says whether step k survives, else none does (the
+                        //   multiplier maps the at most 2^KB values P(gray(k)) & zmask to
+                        //   distinct slots).  Both tables are copied to dynamic LDS at byte
+                        //   offset ztab_lds.
     uint32_t node_word0;  // the node-factor slot masks are zero beyond word 0
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j

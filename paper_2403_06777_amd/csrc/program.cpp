@@ -1096,23 +1096,24 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             img.push_back(e);
         }
     }
-    // Surviving steps of a block by the vanishing bits, when those are the low z <= 11 bits of
-    // word 0 (compacting walks): entry a (z bits) has bit k set iff step k's term survives in a
-    // block whose first term has L & zmask = a, i.e. iff P(gray(k)) & zmask = a, P(y) the XOR of
-    // the inner columns picked by y; then come the KS values P(gray(k)) (W words each).  Both
-    // are copied to LDS after the other tables.
+    // Surviving steps of a block by the vanishing bits, when those all lie in word 0 (compacting
+    // walks): step k of a block survives iff P(gray(k)) & zmask = a, a = L & zmask at the block's
+    // first term, P(y) the XOR of the inner columns picked by y.  The at most 2^KB keys
+    // P(gray(k)) & zmask, each with the mask of its steps, go to a hashed table of kZtabSlots
+    // (key, mask) pairs; the multiplier is the first of a fixed sequence that maps the keys to
+    // distinct slots.  Then come the KS values P(gray(k)) (W words each).  Both are copied to
+    // LDS after the other tables.
     H.ztab_bits = 0;
+    H.ztab_mult = 0;
     H.off_ztab = (uint32_t)img.size();
     {
         const size_t end_lds = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4
                                         : (acc_mode == ACC_CLASS ? (size_t)H.zero_entry * q_limbs * 8
                                                                  : (size_t)H.table_n * 32);
         H.ztab_lds = (uint32_t)((end_lds + 15) & ~(size_t)15);
-        const int z = __builtin_popcount(zmask[0]);
-        bool low = has_zero && g >= KB && W <= 4 && z >= 1 && z <= 11 && zmask[0] == (1u << z) - 1u;
-        for (int k = 1; k < W; ++k) low = low && zmask[k] == 0;
-        if (low) {
-            H.ztab_bits = (uint32_t)z;
+        bool word0 = has_zero && g >= KB && W <= 4 && zmask[0] != 0;
+        for (int k = 1; k < W; ++k) word0 = word0 && zmask[k] == 0;
+        if (word0) {
             std::vector<uint32_t> pstep((size_t)KS * W, 0);
             for (int k = 0; k < KS; ++k) {
                 const int y = k ^ (k >> 1);
@@ -1120,10 +1121,38 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                     if (y >> j & 1)
                         for (int w2 = 0; w2 < W; ++w2) pstep[(size_t)k * W + w2] ^= img[H.off_col + j * W + w2];
             }
-            std::vector<uint32_t> zt((size_t)1 << z, 0);
-            for (int k = 0; k < KS; ++k) zt[pstep[(size_t)k * W] & zmask[0]] |= 1u << k;
-            img.insert(img.end(), zt.begin(), zt.end());
-            img.insert(img.end(), pstep.begin(), pstep.end());
+            std::map<uint32_t, uint32_t> steps;  // key -> mask of its steps
+            for (int k = 0; k < KS; ++k) steps[pstep[(size_t)k * W] & zmask[0]] |= 1u << k;
+            uint64_t state = 0x243F6A8885A308D3ull;  // a fixed sequence of odd multipliers
+            for (int attempt = 0; attempt < 4096 && !H.ztab_mult; ++attempt) {
+                state += 0x9E3779B97F4A7C15ull;
+                uint64_t x = state;
+                x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+                x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+                const uint32_t mult = (uint32_t)(x ^ (x >> 31)) | 1u;
+                std::vector<char> used_slot(kZtabSlots, 0);
+                bool ok = true;
+                for (const auto &kv : steps) {
+                    const uint32_t slot = (kv.first * mult) >> kZtabShift;
+                    if (used_slot[slot]) {
+                        ok = false;
+                        break;
+                    }
+                    used_slot[slot] = 1;
+                }
+                if (ok) H.ztab_mult = mult;
+            }
+            if (H.ztab_mult) {
+                H.ztab_bits = (uint32_t)__builtin_popcount(zmask[0]);
+                std::vector<uint32_t> zt(2 * kZtabSlots, 0);  // (key, mask); empty slots have mask 0
+                for (const auto &kv : steps) {
+                    const uint32_t slot = (kv.first * H.ztab_mult) >> kZtabShift;
+                    zt[2 * slot] = kv.first;
+                    zt[2 * slot + 1] = kv.second;
+                }
+                img.insert(img.end(), zt.begin(), zt.end());
+                img.insert(img.end(), pstep.begin(), pstep.end());
+            }
         }
     }
     std::vector<int64_t> table((size_t)H.table_n * 4, 0);

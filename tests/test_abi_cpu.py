@@ -26,11 +26,36 @@ def test_binding_exposes_c_names():
         assert hasattr(zx, name) or name in ("sim_last_error",), name
 
 
+def wide_vanishing_program(seed, p=24, n_vanish=36, basis=6):
+    # more than 32 factors that can vanish (their bits of L span two words), on forms from a
+    # small subspace so that a fraction 2^-basis of the terms survives
+    from workloads.programs import ProgramSpec
+    rng = wl.SplitMix64(80, seed)
+    base = [rng.randint(1, (1 << p) - 1) for _ in range(basis)]
+    star = rng.randint(0, (1 << p) - 1)  # every vanishing form is 0 (factor 2) here
+    prog = ProgramSpec(p)
+    for _ in range(n_vanish):
+        m = 0
+        while m == 0:
+            m = 0
+            for b in base:
+                if rng.bernoulli(0.5):
+                    m ^= b
+        prog.nodes.append((prog.add_form(bin(m & star).count("1") & 1, m), 0, 4))
+    for _ in range(12):
+        prog.nodes.append((prog.add_form(rng.randint(0, 1), rng.randint(1, (1 << p) - 1)), rng.randint(0, 7), rng.randint(1, 7)))
+    for _ in range(20):
+        prog.mono.append((rng.randint(1, 7), sorted(rng.sample_distinct(p, rng.randint(1, 3)))))
+    return prog
+
+
 def test_vanishing_step_table_is_reported():
-    # the kernel-sized program of seed 0 has 11 vanishing factors (table path), seed 1 has 12
-    # (reduced-basis path); programs without vanishing factors report 0
+    # vanishing factors whose bits all lie in word 0 use the table of surviving steps (the
+    # kernel-sized programs: 11 and 12 of them); more than 32 use the reduced-basis test;
+    # programs without vanishing factors report 0
     assert zx.sim_ir_info(wl.kernel_sized_program(0).to_text())["vanish_table_bits"] == 11
-    assert zx.sim_ir_info(wl.kernel_sized_program(1).to_text())["vanish_table_bits"] == 0
+    assert zx.sim_ir_info(wl.kernel_sized_program(1).to_text())["vanish_table_bits"] == 12
+    assert zx.sim_ir_info(wide_vanishing_program(0).to_text())["vanish_table_bits"] == 0
     assert zx.sim_ir_info(wl.random_program(0, 10, n_nodes=0, n_lin=8).to_text())["vanish_table_bits"] == 0
 
 

@@ -123,23 +123,28 @@ def test_folded_node_pairs_keep_the_sum(o2):
 
 
 def test_vanishing_step_table_and_basis_paths(o2):
-    # a block's surviving steps come from a table indexed by the vanishing bits (at most 11 of
-    # them) or from the reduced-basis test (more); both against the oracle, exhaustively at
-    # p = 20 and on sampled slices at p = 32
-    seen = set()
-    for seed in range(6):
+    # a block's surviving steps come from the hashed table when the vanishing bits lie in word
+    # 0 (kernel-sized programs), else from the reduced-basis test (more than 32 vanishing
+    # factors); both against the oracle, exhaustively at p = 20 and 24, and on sampled slices
+    # of two p = 32 programs
+    from tests.test_abi_cpu import wide_vanishing_program
+    for seed in range(4):
         text = wl.kernel_sized_program(seed, p=20, n_factors=64, n_monomials=200).to_text()
-        z = zx.sim_ir_info(text)["vanish_table_bits"]
-        seen.add(z > 0)
-        say("vanishing steps", seed, z)
+        assert zx.sim_ir_info(text)["vanish_table_bits"] > 0
+        say("vanishing steps, table", seed)
         assert gpu_value(text) == oracle_value(o2, text)
-    assert seen == {True, False}
-    for seed in (1, 3):  # p = 32: basis test, table
+    for seed in range(3):
+        text = wide_vanishing_program(seed).to_text()
+        info = zx.sim_ir_info(text)
+        assert info["vanish_table_bits"] == 0 and info["nonzero_fraction"] > 0
+        say("vanishing steps, basis", seed, info["nonzero_fraction"])
+        assert gpu_value(text) == oracle_value(o2, text)
+    for seed in (1, 3):
         text = wl.kernel_sized_program(seed).to_text()
         h = zx.sim_program_from_ir(text)
         try:
             info = zx.sim_program_info(h)
-            assert (info["vanish_table_bits"] > 0) == (seed == 3)
+            assert info["vanish_table_bits"] > 0
             perm = zx.sim_program_layout(h)
             wb, ns = info["walk_bits"], info["n_slices"]
             rng = wl.SplitMix64(78, seed)
