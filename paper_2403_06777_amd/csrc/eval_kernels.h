@@ -267,11 +267,17 @@ __device__ __forceinline__ bool words_equal(const uint32_t (&a)[W], const uint32
 // turned into a stack array)
 template <int NF>
 __device__ __forceinline__ uint32_t field_at(const uint32_t (&fv)[NF], uint32_t k) {
-    static_assert(NF == 2 || NF == 4, "16 or 32 fields");
+    static_assert(NF == 2 || NF == 4 || NF == 8, "16, 32 or 64 fields");
     uint64_t x = (uint64_t)fv[0] | ((uint64_t)fv[1] << 32);
-    if (NF == 4) {
+    if (NF >= 4) {
         const uint64_t h = (uint64_t)fv[2 % NF] | ((uint64_t)fv[3 % NF] << 32);
         x = (k & 16u) ? h : x;
+    }
+    if (NF == 8) {
+        const uint64_t h2 = (uint64_t)fv[4 % NF] | ((uint64_t)fv[5 % NF] << 32);
+        const uint64_t h3 = (uint64_t)fv[6 % NF] | ((uint64_t)fv[7 % NF] << 32);
+        const uint64_t y = (k & 16u) ? h3 : h2;
+        x = (k & 32u) ? y : x;
     }
     return (uint32_t)(x >> (4 * (k & 15u))) & 7u;
 }
@@ -435,16 +441,16 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             const uint32_t *zt =
                 reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + H.ztab_lds);
             const uint32_t a = L[0] & S.zm[0];
-            const uint2 ent = reinterpret_cast<const uint2 *>(zt)[(a * H.ztab_mult) >> kZtabShift];
-            uint32_t hits = valid && ent.x == a ? ent.y : 0u;
-            const uint32_t nz = 2 * kZtabSlots;  // words of the hashed table: P(gray(k)) follow
+            const uint4 ent = reinterpret_cast<const uint4 *>(zt)[(a * H.ztab_mult) >> H.ztab_shift];
+            uint64_t hits = valid && ent.x == a ? ((uint64_t)ent.z << 32) | ent.y : 0ull;
+            const uint32_t nz = 4 * ztab_slots_for(KB);  // words of the hashed table: P(gray(k)) follow
             for (;;) {
                 const uint64_t m = __ballot(hits != 0u);
                 if (!m) break;
                 const uint32_t below =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 if (hits) {
-                    const uint32_t k = (uint32_t)__builtin_ctz(hits);
+                    const uint32_t k = (uint32_t)__builtin_ctzll(hits);
                     hits &= hits - 1u;
                     const uint32_t *pk = zt + nz + k * W;  // P(gray(k))
                     uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -771,7 +777,7 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
         for (uint32_t i = threadIdx.x; i < H.ntab_n; i += blockDim.x) d[i] = words[H.off_ntab + i];
     }
     if (H.ztab_bits) {
-        const uint32_t n = 2 * kZtabSlots + (1u << inner_bits_for(H.W)) * H.W;
+        const uint32_t n = 4 * ztab_slots_for(inner_bits_for(H.W)) + (1u << inner_bits_for(H.W)) * H.W;
         uint32_t *d = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_tab) + H.ztab_lds);
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = words[H.off_ztab + i];
     }

@@ -60,13 +60,17 @@ IMG_HD constexpr int slot_words(uint32_t set, int slot, int W) {
 // blocks, the vanishing test) is spread over 2^KB terms: 32 for form vectors of up to 4
 // words, 16 for wider ones (whose unrolled block keeps 2^KB columns of W words in registers).
 // Programs with fewer walk bits use the plain step loop.
-constexpr int kMaxInnerBits = 5;
-constexpr uint32_t kZtabSlots = 256;  // slots of the table of surviving steps
-constexpr uint32_t kZtabShift = 24;   // 32 - log2(kZtabSlots)
+constexpr int kMaxInnerBits = 6;
+// slots of the table of surviving steps (4 words each: key, 64-bit step mask, 0), for blocks of
+// 2^KB steps: enough that a collision-free multiplier is found quickly for 2^KB keys
 #ifdef __HIPCC__
 __host__ __device__
 #endif
-constexpr int inner_bits_for(uint32_t W) { return W <= 4 ? 5 : 4; }
+constexpr uint32_t ztab_slots_for(int KB) { return KB >= 6 ? 512u : 256u; }
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+constexpr int inner_bits_for(uint32_t W) { return W <= 2 ? 6 : W <= 4 ? 5 : 4; }
 
 // how the terms of a lane are summed
 enum {
@@ -89,10 +93,10 @@ struct ImgHeader {
                         // bits 16-18 the node part of R (mod 8)
     uint32_t ntab_lds;  // byte offset of the node table in dynamic LDS
     uint32_t ztab_bits; // z > 0: the z vanishing bits all lie in word 0, and at off_ztab come a
-    uint32_t ztab_mult; //   table of kZtabSlots (key, mask) pairs and the 2^KB values of
-    uint32_t off_ztab;  //   P(gray(k)), W words each, P(y) = XOR of the inner columns picked by y.
-    uint32_t ztab_lds;  //   A block whose first term has a = L & zmask reads the pair at slot
-                        //   (a * ztab_mult) >> (32 - log2 kZtabSlots): if its key is a, bit k
+    uint32_t ztab_mult; //   table of ztab_slots_for(KB) (key, mask lo, mask hi, 0) entries and
+    uint32_t off_ztab;  //   the 2^KB values of P(gray(k)), W words each, P(y) = XOR of the inner
+    uint32_t ztab_lds;  //   columns picked by y.  A block whose first term has a = L & zmask reads
+    uint32_t ztab_shift;//   the entry at slot (a * ztab_mult) >> ztab_shift: if its key is a, bit k
                         //   of its mask says whether step k survives, else none does (the
                         //   multiplier maps the at most 2^KB values P(gray(k)) & zmask to
                         //   distinct slots).  Both tables are copied to dynamic LDS at byte

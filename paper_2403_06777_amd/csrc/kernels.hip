@@ -80,7 +80,8 @@ size_t dyn_lds_bytes(const ImgHeader &H) {
     const size_t base = H.acc == ACC_CLASS ? (size_t)H.zero_entry * H.q_limbs * 8 : (size_t)H.table_n * 32;
     const size_t end = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4 : base;
     if (!H.ztab_bits) return end;
-    const size_t zwords = 2 * (size_t)kZtabSlots + ((size_t)1 << inner_bits_for(H.W)) * H.W;
+    const int kb = inner_bits_for(H.W);
+    const size_t zwords = 4 * (size_t)ztab_slots_for(kb) + ((size_t)1 << kb) * H.W;
     return std::max(end, (size_t)H.ztab_lds + zwords * 4);
 }
 

@@ -1099,13 +1099,16 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // Surviving steps of a block by the vanishing bits, when those all lie in word 0 (compacting
     // walks): step k of a block survives iff P(gray(k)) & zmask = a, a = L & zmask at the block's
     // first term, P(y) the XOR of the inner columns picked by y.  The at most 2^KB keys
-    // P(gray(k)) & zmask, each with the mask of its steps, go to a hashed table of kZtabSlots
+    // P(gray(k)) & zmask, each with the mask of its steps, go to a hashed table of
+    // ztab_slots_for(KB)
     // (key, mask) pairs; the multiplier is the first of a fixed sequence that maps the keys to
     // distinct slots.  Then come the KS values P(gray(k)) (W words each).  Both are copied to
     // LDS after the other tables.
     H.ztab_bits = 0;
     H.ztab_mult = 0;
     H.off_ztab = (uint32_t)img.size();
+    const uint32_t zslots = ztab_slots_for(KB);
+    H.ztab_shift = 32u - (uint32_t)__builtin_ctz(zslots);
     {
         const size_t end_lds = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4
                                         : (acc_mode == ACC_CLASS ? (size_t)H.zero_entry * q_limbs * 8
@@ -1121,8 +1124,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                     if (y >> j & 1)
                         for (int w2 = 0; w2 < W; ++w2) pstep[(size_t)k * W + w2] ^= img[H.off_col + j * W + w2];
             }
-            std::map<uint32_t, uint32_t> steps;  // key -> mask of its steps
-            for (int k = 0; k < KS; ++k) steps[pstep[(size_t)k * W] & zmask[0]] |= 1u << k;
+            std::map<uint32_t, uint64_t> steps;  // key -> mask of its steps
+            for (int k = 0; k < KS; ++k) steps[pstep[(size_t)k * W] & zmask[0]] |= (uint64_t)1 << k;
             uint64_t state = 0x243F6A8885A308D3ull;  // a fixed sequence of odd multipliers
             for (int attempt = 0; attempt < 4096 && !H.ztab_mult; ++attempt) {
                 state += 0x9E3779B97F4A7C15ull;
@@ -1130,10 +1133,10 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
                 x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
                 const uint32_t mult = (uint32_t)(x ^ (x >> 31)) | 1u;
-                std::vector<char> used_slot(kZtabSlots, 0);
+                std::vector<char> used_slot(zslots, 0);
                 bool ok = true;
                 for (const auto &kv : steps) {
-                    const uint32_t slot = (kv.first * mult) >> kZtabShift;
+                    const uint32_t slot = (kv.first * mult) >> H.ztab_shift;
                     if (used_slot[slot]) {
                         ok = false;
                         break;
@@ -1144,11 +1147,12 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             }
             if (H.ztab_mult) {
                 H.ztab_bits = (uint32_t)__builtin_popcount(zmask[0]);
-                std::vector<uint32_t> zt(2 * kZtabSlots, 0);  // (key, mask); empty slots have mask 0
+                std::vector<uint32_t> zt(4 * zslots, 0);  // (key, mask lo, hi, 0); empty slots have mask 0
                 for (const auto &kv : steps) {
-                    const uint32_t slot = (kv.first * H.ztab_mult) >> kZtabShift;
-                    zt[2 * slot] = kv.first;
-                    zt[2 * slot + 1] = kv.second;
+                    const uint32_t slot = (kv.first * H.ztab_mult) >> H.ztab_shift;
+                    zt[4 * slot] = kv.first;
+                    zt[4 * slot + 1] = (uint32_t)kv.second;
+                    zt[4 * slot + 2] = (uint32_t)(kv.second >> 32);
                 }
                 img.insert(img.end(), zt.begin(), zt.end());
                 img.insert(img.end(), pstep.begin(), pstep.end());
