@@ -798,14 +798,6 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 // is past the end of the range do nothing (or, in the compacting walk, walk without results).
 // With class counters the runs are cut into chunks of at most chunk_units units, the same
 // number of chunks in every wave of the workgroup, and the counters are flushed after each.
-// Resident waves per SIMD asked of the compiler for k_eval: the two-word compacting walk with
-// monomials and class counters fits six waves (80 registers, no spills in its hot loop, 4%
-// faster on the kernel-sized workload); the other variants keep the compiler's choice (asking
-// them for six waves spills registers to scratch).
-constexpr unsigned eval_waves_hint(int W, bool MONO, int ACC, uint32_t SET) {
-    return W == 2 && MONO && ACC == ACC_CLASS && (SET & kSlotSetAll) != kSlotSetAll ? 6u : 1u;
-}
-
 template <int W, bool MONO, int ACC, uint32_t SET>
 __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img, uint64_t s_first, uint64_t s_count,
                                           uint64_t wave, uint64_t n_waves, uint64_t chunk_units, int64_t *s_tab,
@@ -856,8 +848,7 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
 }
 
 template <int W, bool MONO, int ACC, uint32_t SET>
-__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(eval_waves_hint(W, MONO, ACC, SET))))
-void k_eval(ImgHeader H, const uint8_t *__restrict__ img,
+__global__ __launch_bounds__(kMaxThreads) void k_eval(ImgHeader H, const uint8_t *__restrict__ img,
                                                       uint64_t s_begin, uint64_t s_count, uint64_t chunk_units,
                                                       Partial *__restrict__ partials) {
     extern __shared__ int64_t s_dyn[];

@@ -1188,11 +1188,14 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // and one popcount-accumulate per word it spans (with the node table: one AND and one LDS
     // read for all node factors), the table index and shift (8), the accumulation (int64 12,
     // int128 40, class counter 5) and with monomials the term's phase field (2).
-    //  * walks of at least KB positions: with factors that can vanish, each term's
-    //    vanishing test (a W-word compare) and for a surviving term the rebuild of its form
-    //    vector (W); otherwise each term's column XOR (W).  Per block: the outer column XOR (W),
-    //    with vanishing factors the masked start vector and the end XOR (2W; with the table of
-    //    surviving steps its index and the end XOR, 1 + W), with monomials
+    //  * walks of at least KB positions: with factors that can vanish and W <= 4 the vanishing
+    //    test is per block (below) and a surviving term costs the rebuild of its form vector
+    //    (W); with wider form vectors each term's vanishing test (a W-word compare) as well;
+    //    otherwise each term's column XOR (W).  Per block: the outer column XOR (W), with
+    //    vanishing factors the block's test and the end XOR (the table of surviving steps:
+    //    mask, hash product and shift, key compare and the end XOR, 4 + W; the reduced basis:
+    //    KB bit extracts with W XORs each, the compare and the end XOR, KB (2 + W) + 2W), with
+    //    monomials
     //    the vector-pair selection (NF), the flip's own change (5), 5 per firing slice-dependent
     //    flip entry and 4 + 4 NF per toggling inner-vector entry (slice test, 2 NF field adds);
     //  * shorter walks: per term the column XOR (W), the vanishing test (2W) and the flip
@@ -1211,7 +1214,9 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             if (set >> i & 1) slot_ops += 2.0 * slot_words(set, i, W);
         const double stats = 8 + acc_ops + slot_ops + (mono ? 2 : 0);
         double ops;
-        if (blocks && has_zero) ops = W + nz * (W + stats);
+        const bool compact = blocks && has_zero && W <= 4;
+        if (compact) ops = nz * (W + stats);
+        else if (blocks && has_zero) ops = W + nz * (W + stats);
         else if (blocks) ops = W + stats;
         else ops = W + (has_zero ? 2.0 * W : 0) + nz * stats;
         double setup = (double)(w.pe - g) * 2.0 * W;
@@ -1238,7 +1243,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             const uint64_t nb = steps >> KB;
             const uint32_t *c3idx = img.data() + H.off_c3idx;
             const uint32_t *c3 = img.data() + H.off_c3;
-            const double vanish_test = H.ztab_bits ? 1.0 + W : 2.0 * W;  // table index, or masked start
+            const double vanish_test = !compact ? 2.0 * W : H.ztab_bits ? 4.0 + W : KB * (2.0 + W) + 2.0 * W;
             walk += (double)nb * ((has_zero ? vanish_test : 0) + (mono ? NF : 0));
             for (uint64_t b = 1; b < nb; ++b) {
                 const int i = KB + __builtin_ctzll(b);
