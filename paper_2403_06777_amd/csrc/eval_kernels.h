@@ -931,7 +931,7 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
         if ((ACC_) == ACC_I128) return CALL(w, m, ACC_I128, kSlotSetAll);                    \
         if ((ACC_) == ACC_I64) {                                                             \
             if ((MENU_) == 2) return CALL(w, m, ACC_I64, kSlotSetPhase);                     \
-            if ((MENU_) == 3 && w <= 8) return CALL(w, m, ACC_I64, kSlotSetPhase | kNTAB);   \
+            if ((MENU_) == 3 && w <= 8) return CALL(w, m, ACC_I64, kSlotSetPhaseLow | kNTAB);\
             if (w > 1 && w < 16 && N0_) {                                                    \
                 if ((MENU_) == 1) return CALL(w, m, ACC_I64, kSlotSetNodes | kNW0);          \
                 return CALL(w, m, ACC_I64, kSlotSetAll | kNW0);                              \
@@ -940,7 +940,7 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
             return CALL(w, m, ACC_I64, kSlotSetAll);                                         \
         }                                                                                    \
         if ((MENU_) == 2) return CALL(w, m, ACC_CLASS, kSlotSetPhase);                       \
-        if ((MENU_) == 3 && w <= 8) return CALL(w, m, ACC_CLASS, kSlotSetPhase | kNTAB);     \
+        if ((MENU_) == 3 && w <= 8) return CALL(w, m, ACC_CLASS, kSlotSetPhaseLow | kNTAB);  \
         if (w > 1 && w < 16 && N0_) {                                                        \
             if ((MENU_) == 1) return CALL(w, m, ACC_CLASS, kSlotSetNodes | kNW0);            \
             return CALL(w, m, ACC_CLASS, kSlotSetAll | kNW0);                                \

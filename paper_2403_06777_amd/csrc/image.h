@@ -35,15 +35,18 @@ IMG_HD constexpr int slot_weight(int i) {
 constexpr uint32_t kSlotSetAll = 0x7FFu;    // every slot
 constexpr uint32_t kSlotSetNodes = 0x7C5u;  // A+1, B+1, E-1, E-2, R*: factors 1 + w^{k l}
 constexpr uint32_t kSlotSetPhase = 0x700u;  // R* only: phase terms without factors
-// Added to the phase-only set: the node factors are looked up in a table indexed by their bits
-// (at most kMaxTableNodes node factors, bits 0 .. n-1 of word 0), whose entry holds the term's
-// vanishing flag, A - B (offset), E and the node part of R; only the phase slots are counted.
+constexpr uint32_t kSlotSetPhaseLow = 0x300u;  // R*1, R*2: phase terms beside the node table
+// Added to the low phase set: the node factors are looked up in a table indexed by their bits
+// (at most kMaxTableNodes node factors, bits 0 .. n-1 of word 0, then the bit of the one
+// combined weight-4 phase term), whose entry holds the term's vanishing flag, A - B (offset), E
+// and the part of R from the nodes and from the linear terms on those bits; the R*1 and R*2
+// slots count the other linear terms (all their weight-4 parts are in that combined term).
 constexpr uint32_t kSlotsNodeTable = 0x40000000u;
 constexpr int kMaxTableNodes = 10;
 IMG_HD constexpr uint32_t slot_set_of(uint32_t menu_index) {
     return menu_index == 1 ? kSlotSetNodes
          : menu_index == 2 ? kSlotSetPhase
-         : menu_index == 3 ? (kSlotSetPhase | kSlotsNodeTable)
+         : menu_index == 3 ? (kSlotSetPhaseLow | kSlotsNodeTable)
                            : kSlotSetAll;
 }
 // Added to a slot set: the node-factor slots (A, B, E) have bits in word 0 only (at most 32

@@ -515,6 +515,46 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         if (f.mask == 0) const_phase += c * f.cst;
         else w.lin.push_back({c, l.form});
     }
+    // The weight-4 parts of the linear phase terms are one term: w^(4 (f_1 + ... + f_m)) =
+    // (-1)^(f_1 xor ... xor f_m), and the xor of affine forms over GF(2) is one affine form.
+    // Every other form keeps its coefficient mod 4.  The combined term comes first, so its bit
+    // of L is the first after the node bits, where the node table can carry it.
+    {
+        std::vector<int> seen;
+        std::map<int, long long> tot;
+        for (const auto &l : w.lin) {
+            if (!tot.count(l.second)) seen.push_back(l.second);
+            tot[l.second] += l.first;
+        }
+        IrForm g{0, 0};
+        bool any4 = false;
+        std::vector<std::pair<int, int>> lin;
+        for (int f : seen) {
+            const int t = mod8(tot[f]);
+            if (t & 4) {
+                g.cst ^= w.forms[f].cst;
+                g.mask ^= w.forms[f].mask;
+                any4 = true;
+            }
+            if (t & 3) lin.push_back({t & 3, f});
+        }
+        if (any4 && g.mask == 0) {
+            const_phase += 4 * g.cst;
+        } else if (any4) {
+            int fg = -1;
+            for (size_t f = 0; f < w.forms.size() && fg < 0; ++f)
+                if (w.forms[f].mask == g.mask) {
+                    fg = (int)f;
+                    if (w.forms[f].cst != g.cst) const_phase += 4;  // (-1)^(f xor 1) = -(-1)^f
+                }
+            if (fg < 0) {
+                fg = (int)w.forms.size();
+                w.forms.push_back(g);
+            }
+            lin.insert(lin.begin(), {4, fg});
+        }
+        w.lin.swap(lin);
+    }
     for (const auto &m : ir.mono) {
         std::vector<int> vs;
         for (int v : m.vars) vs.push_back(v + q);
@@ -620,10 +660,12 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         node_owned[b] = 1;
         n.first = b;
     }
+    int lin4_bit = -1;  // the bit of the combined weight-4 phase term
     for (auto &l : w.lin) {
         int f = l.second;
         if (form_slot[f] < 0) form_slot[f] = new_bit(f);
         l.second = form_slot[f];
+        if (l.first & 4) lin4_bit = l.second;
     }
     const int F = (int)used.size();
     int W = 1;
@@ -723,6 +765,10 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     const int n_nodes = (int)w.nodes.size();
     bool use_ntab = n_nodes >= 1 && n_nodes <= kMaxTableNodes && acc_mode != ACC_I128 && W <= 8;
     for (int j = 0; j < n_nodes && use_ntab; ++j) use_ntab = w.nodes[j].first == j;
+    // the table is indexed by the node bits and, when it follows them, the bit of the combined
+    // weight-4 phase term; it carries every linear phase weight on those bits
+    const int ntab_bits = n_nodes + (lin4_bit == n_nodes ? 1 : 0);
+    std::vector<long long> wt_tab(use_ntab ? ntab_bits : 0, 0);
 
     // ---- image words
     std::vector<uint32_t> img;
@@ -848,6 +894,10 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             H.stat_base[s] = 0;
         }
         wt[STAT_R] = wt_lin;
+        for (int b = 0; b < ntab_bits; ++b) {
+            wt_tab[b] = wt_lin[b];
+            wt[STAT_R][b] = 0;
+        }
         H.stat_base[STAT_R] = (int32_t)mod8(base_lin);
     }
     int active_slots = 0;
@@ -877,6 +927,10 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         img.insert(img.end(), mask.begin(), mask.end());
         active_slots += any ? 1 : 0;
         if (any) active_mask |= 1u << i;
+    }
+    if (use_ntab && (active_mask & ~slot_set_of(3u) & kSlotSetAll)) {
+        *err = "internal: a weight-4 phase slot beside the node table";
+        return SIM_EINVAL;
     }
     H.slot_menu = use_ntab ? 3u
                 : (active_mask & ~kSlotSetPhase) == 0 ? 2u
@@ -1075,7 +1129,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // the node table: entry u describes the node factors with bits u of L
     H.off_ntab = (uint32_t)img.size();
     if (use_ntab) {
-        H.ntab_n = 1u << n_nodes;
+        H.ntab_n = 1u << ntab_bits;
         for (uint32_t u = 0; u < H.ntab_n; ++u) {
             long long st[N_STATS] = {0, 0, 0, 0};
             bool vanish = false;
@@ -1085,6 +1139,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 if (v == 4) vanish = true;
                 for (int s2 = 0; s2 < N_STATS; ++s2) st[s2] += fns[s2](v);
             }
+            for (int b = 0; b < ntab_bits; ++b)  // linear weights count the bits of L as stored
+                if (u >> b & 1) st[STAT_R] += wt_tab[b];
             uint32_t e = 1u;
             if (!vanish) {
                 const long long m = std::min(st[STAT_A], st[STAT_B]);

@@ -155,3 +155,24 @@ def test_node_pairs_with_constant_product_are_folded():
     f2 = pr2.add_form(0, 0b011)
     pr2.nodes += [(f2, 0, 4), (f2, 4, 4), (pr2.add_form(0, 0b100), 1, 4)]
     assert zx.sim_ir_info(pr2.to_text())["is_zero"] == 1
+
+
+def test_weight4_phase_parts_share_one_form():
+    # w^(4 f) parts of linear terms on k forms take one combined form: the program keeps the
+    # node forms, the forms with a coefficient mod 4, and at most one more
+    p = 12
+    prog = wl.ProgramSpec(p)
+    for i in range(3):
+        f = prog.add_form(i & 1, 0b111 << i)
+        prog.nodes.append((f, 1, 2))
+    four = [prog.add_form(i & 1, (0b1011 << i) & 0xFFF) for i in range(5)]
+    prog.lin += [(4, f) for f in four]
+    odd = prog.add_form(1, 0b110000000001)
+    prog.lin.append((6, odd))
+    assert zx.sim_ir_info(prog.to_text())["n_forms"] == 3 + 1 + 1
+    # parts that add up to the constant 1 (-1 overall), to another term's form or to a node
+    # factor's form leave no form of their own
+    for case in ("constant", "opposite", "node"):
+        prog = wl.weight4_phase_program(0, 10, 2, case)
+        n_forms = zx.sim_ir_info(prog.to_text())["n_forms"]
+        assert n_forms == len(prog.forms) - {"constant": 3, "opposite": 1, "node": 2}[case]

@@ -334,6 +334,20 @@ def test_node_table_programs(o2, n_nodes, n_lin, p):
         assert gpu_value(text) == oracle_value(o2, text)
 
 
+@pytest.mark.parametrize("case", ["random", "node", "opposite", "constant"])
+def test_weight4_phase_parts_combined(o2, case):
+    # the weight-4 parts of the linear phase terms as one form: beside node tables of 1 to 10
+    # factors (the combined bit makes 11 table bits at 10 factors), on a node factor's form,
+    # on another term's form with the other constant, or adding up to a constant
+    for n_nodes, p in [(1, 9), (4, 13), (10, 15), (0, 11), (6, 22)]:
+        if case == "node" and n_nodes == 0:
+            continue
+        prog = wl.weight4_phase_program(n_nodes, p, n_nodes, case)
+        text = prog.to_text()
+        say("weight-4 parts", case, n_nodes, p, zx.sim_ir_info(text)["n_forms"])
+        assert gpu_value(text) == oracle_value(o2, text), (case, n_nodes, p)
+
+
 def test_enqueued_evaluations_match_synchronous_ones(o2):
     # several programs enqueued back to back (one stream, then two streams, then mixed with
     # synchronous calls that reuse the device's scratch): every device-written value equals the

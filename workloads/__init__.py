@@ -24,6 +24,7 @@ from .programs import (
     random_program,
     block_separable_program,
     appendix_d_terms,
+    weight4_phase_program,
 )
 
 __all__ = [
@@ -41,4 +42,5 @@ __all__ = [
     "random_program",
     "block_separable_program",
     "appendix_d_terms",
+    "weight4_phase_program",
 ]

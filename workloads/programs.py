@@ -267,3 +267,49 @@ def appendix_d_terms() -> List[ProgramSpec]:
             prog.pairs.append((f1, f2, a, b))
         terms.append(prog)
     return terms
+
+
+def weight4_phase_program(seed: int, p: int, n_nodes: int, case: str) -> ProgramSpec:
+    """Programs whose linear phase terms carry weight-4 parts (coefficients 4..7) in the ways
+    they can combine: `random` (many terms with coefficients 1..7, half of them on forms
+    already there, the node factors' included), `node` (the parts' forms add up to a node
+    factor's form), `opposite` (they add up to another linear term's form with the other
+    constant), `constant` (they add up to the constant 1)."""
+    rng = SplitMix64(STREAM_RANDOM_PROGRAM, 7_000_003 + seed * 1009 + p * 31 + n_nodes)
+    prog = ProgramSpec(p)
+
+    def mask():
+        m = _random_mask(rng, p, 0.4)
+        return m if m else 1 << rng.randint(0, p - 1)
+
+    for _ in range(n_nodes):
+        f = prog.add_form(rng.randint(0, 1), mask())
+        prog.nodes.append((f, rng.randint(0, 7), rng.randint(1, 7)))
+    if case == "random":
+        for _ in range(3 * p):
+            if prog.forms and rng.bernoulli(0.5):
+                f = rng.randint(0, len(prog.forms) - 1)
+            else:
+                f = prog.add_form(rng.randint(0, 1), mask())
+            prog.lin.append((rng.randint(1, 7), f))
+    else:
+        a = prog.add_form(rng.randint(0, 1), mask())
+        b = prog.add_form(rng.randint(0, 1), mask())
+        ca, ma = prog.forms[a]
+        cb, mb = prog.forms[b]
+        prog.lin += [(4, a), (5, b)]
+        if case == "node":
+            c0, m0 = prog.forms[0]
+            c = prog.add_form(c0 ^ ca ^ cb ^ rng.randint(0, 1), m0 ^ ma ^ mb)
+            prog.lin.append((4, c))
+        elif case == "opposite":
+            d = prog.add_form(ca ^ cb ^ 1, ma ^ mb)
+            prog.lin.append((rng.randint(1, 3), d))
+        elif case == "constant":
+            prog.lin.append((4, prog.add_form(cb ^ 1, mb)))
+            prog.lin.append((4, prog.add_form(ca, ma)))
+        else:
+            raise ValueError(case)
+        for _ in range(p // 2):  # terms without a weight-4 part
+            prog.lin.append((rng.randint(1, 3), prog.add_form(rng.randint(0, 1), mask())))
+    return prog
