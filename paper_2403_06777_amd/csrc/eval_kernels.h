@@ -150,16 +150,31 @@ template <int ACC>
 struct Acc {
     int64_t a64[4];
     i128 a128[4];
+    uint32_t a32[4];  // one block's int64-mode terms, modulo 2^32 (see flush32)
     __device__ void clear() {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             a64[k] = 0;
             a128[k] = 0;
+            a32[k] = 0;
+        }
+    }
+    // A node-table program has at most kMaxTableNodes node factors, and a term's coordinates
+    // are at most 2^kMaxTableNodes in absolute value (each factor has coefficient sum 2 in the
+    // w-basis, and w^r and the linear phases only permute and negate coordinates), so the at
+    // most 64 terms a lane adds in one block sum to less than 2^31: they are added in 32-bit
+    // registers (one shift-and-add each) and moved to the int64 sums after the block.
+    static_assert(kMaxTableNodes + kMaxInnerBits < 31, "a block's sum must fit in int32");
+    __device__ void flush32() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a64[k] += (int64_t)(int32_t)a32[k];
+            a32[k] = 0;
         }
     }
 };
 
-template <int W, int ACC, uint32_t SET, bool ZERO>
+template <int W, int ACC, uint32_t SET, bool ZERO, bool B32 = false>
 __device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, const int64_t *tab,
                                          unsigned long long *cnt, const uint32_t (&L)[W], int phi, Acc<ACC> &acc) {
     const TermClass t = classify<W, SET, ZERO>(H, S, L, phi);
@@ -173,7 +188,12 @@ __device__ __forceinline__ void add_term(const ImgHeader &H, const Slots<W> &S, 
         const uint32_t idx = t.zero ? H.zero_entry : t.cls;
         const longlong2 *p = reinterpret_cast<const longlong2 *>(tab + (size_t)idx * 4);
         const longlong2 v01 = p[0], v23 = p[1];
-        if (ACC == ACC_I64) {
+        if (ACC == ACC_I64 && B32) {
+            acc.a32[0] += (uint32_t)v01.x << t.h;
+            acc.a32[1] += (uint32_t)v01.y << t.h;
+            acc.a32[2] += (uint32_t)v23.x << t.h;
+            acc.a32[3] += (uint32_t)v23.y << t.h;
+        } else if (ACC == ACC_I64) {
             acc.a64[0] += (int64_t)((uint64_t)v01.x << t.h);
             acc.a64[1] += (int64_t)((uint64_t)v01.y << t.h);
             acc.a64[2] += (int64_t)((uint64_t)v23.x << t.h);
@@ -298,6 +318,8 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     constexpr int KB = inner_bits_for(W);  // inner bits of a block
     constexpr int KS = 1 << KB;             // its terms
     constexpr int NF = KS / 8;              // words of its 4-bit phase fields
+    // node-table programs in int64 mode add a block's terms in 32 bits (Acc::flush32)
+    constexpr bool B32 = ACC == ACC_I64 && (SET & kSlotsNodeTable) != 0 && !CQ;
     CU32 *col = wd + H.off_col;
     uint32_t ck[KB][W];
 #pragma unroll
@@ -573,7 +595,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                     }
                     if (words_equal<W>(a, d)) {
                         const int f = MONO ? (int)((fv[k >> 3] >> (4 * (k & 7))) & 7u) : 0;
-                        add_term<W, ACC, SET, false>(H, S, tab, cnt, Lk, phi + f, acc);
+                        add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, Lk, phi + f, acc);
                     }
                 }
             }
@@ -581,16 +603,17 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
 #pragma unroll
             for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
         } else {
-            add_term<W, ACC, SET, false>(H, S, tab, cnt, L, phi, acc);
+            add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi, acc);
 #pragma unroll
             for (int k = 1; k < KS; ++k) {
                 const int j = __builtin_ctz(k);
 #pragma unroll
                 for (int w = 0; w < W; ++w) L[w] ^= ck[j][w];
                 const int f = MONO ? (int)((fv[k >> 3] >> (4 * (k & 7))) & 7u) : 0;
-                add_term<W, ACC, SET, false>(H, S, tab, cnt, L, phi + f, acc);
+                add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + f, acc);
             }
         }
+        if (B32) acc.flush32();
         if (MONO) phi += (int)(fv[NF - 1] >> 28);  // the block's last state
     }
 }

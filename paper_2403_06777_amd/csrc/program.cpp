@@ -1261,19 +1261,23 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     {
         const double nz = nonzero_fraction(used, w.nodes);
         P.nonzero_fraction = nz;
-        const double acc_ops = H.acc == ACC_I64 ? 12.0 : H.acc == ACC_I128 ? 40.0 : 5.0;
         const bool mono = !w.mono.empty();
         const bool blocks = g >= KB;
+        const bool compact = blocks && has_zero && W <= 4;
+        // node-table programs in int64 mode walking blocks without compaction add a block's
+        // terms in 32 bits (one shift-and-add per coordinate) and move them to int64 per block
+        const bool b32 = H.acc == ACC_I64 && use_ntab && blocks && !compact;
+        const double acc_ops = b32 ? 4.0 : H.acc == ACC_I64 ? 12.0 : H.acc == ACC_I128 ? 40.0 : 5.0;
+        const double flush_ops = b32 ? 12.0 / KS : 0.0;
         double slot_ops = 0;
         const uint32_t set = slot_set_of(H.slot_menu) | (H.node_word0 ? kSlotsNodeWord0 : 0u);
         for (int i = 0; i < kSlots; ++i)
             if (set >> i & 1) slot_ops += 2.0 * slot_words(set, i, W);
         const double stats = 8 + acc_ops + slot_ops + (mono ? 2 : 0);
         double ops;
-        const bool compact = blocks && has_zero && W <= 4;
         if (compact) ops = nz * (W + stats);
-        else if (blocks && has_zero) ops = W + nz * (W + stats);
-        else if (blocks) ops = W + stats;
+        else if (blocks && has_zero) ops = W + flush_ops + nz * (W + stats);
+        else if (blocks) ops = W + flush_ops + stats;
         else ops = W + (has_zero ? 2.0 * W : 0) + nz * stats;
         double setup = (double)(w.pe - g) * 2.0 * W;
         if (mono) setup += 5.0 * H.n_monohi + 5.0 * img[H.off_aidx + g] + 4.0 * g + (blocks ? (4.0 + 4.0 * NF) * H.n_c2 : 0);

@@ -334,6 +334,24 @@ def test_node_table_programs(o2, n_nodes, n_lin, p):
         assert gpu_value(text) == oracle_value(o2, text)
 
 
+def test_node_table_largest_terms(o2):
+    # ten node factors 1 + w^0 = 2 at l = 0 (1 + w^2 at l = 1) on single parameters: terms up
+    # to 2^10 in a coordinate, the most a node-table block sums in 32 bits; the linear terms
+    # give the terms both signs
+    for seed in range(2):
+        rng = wl.SplitMix64(760, seed)
+        p = 16
+        prog = wl.ProgramSpec(p)
+        for i in range(10):
+            prog.nodes.append((prog.add_form(0, 1 << i), 0, 2))
+        for _ in range(12):
+            m = rng.randint(1, (1 << p) - 1)
+            prog.lin.append((rng.randint(1, 7), prog.add_form(rng.randint(0, 1), m)))
+        text = prog.to_text()
+        say("largest node-table terms", seed)
+        assert gpu_value(text) == oracle_value(o2, text)
+
+
 @pytest.mark.parametrize("case", ["random", "node", "opposite", "constant"])
 def test_weight4_phase_parts_combined(o2, case):
     # the weight-4 parts of the linear phase terms as one form: beside node tables of 1 to 10
