@@ -49,11 +49,13 @@ IMG_HD constexpr uint32_t slot_set_of(uint32_t menu_index) {
          : menu_index == 3 ? (kSlotSetPhaseLow | kSlotsNodeTable)
                            : kSlotSetAll;
 }
-// Added to a slot set: the node-factor slots (A, B, E) have bits in word 0 only (at most 32
-// node factors, whose bits come first), so they read one word; the phase slots read all W.
+// Added to a slot set: the node-factor slots (A, B, E) and the R*4 slot have bits in word 0
+// only, so they read one word; the R*1 and R*2 slots read all W.  The node bits come first,
+// and the R*4 weights sit on them and on the one combined weight-4 phase term that follows
+// them, so at most 31 node factors qualify.
 constexpr uint32_t kSlotsNodeWord0 = 0x80000000u;
 IMG_HD constexpr int slot_words(uint32_t set, int slot, int W) {
-    return (set & kSlotsNodeWord0) && slot_stat(slot) != STAT_R ? 1 : W;
+    return (set & kSlotsNodeWord0) && (slot_stat(slot) != STAT_R || slot_weight(slot) == 4) ? 1 : W;
 }
 
 // Walk positions 0 .. KB-1 (the inner bits) are stepped in unrolled blocks of 2^KB terms: the

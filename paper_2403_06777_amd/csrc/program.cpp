@@ -936,11 +936,11 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 : (active_mask & ~kSlotSetPhase) == 0 ? 2u
                 : (active_mask & ~kSlotSetNodes) == 0 ? 1u : 0u;
     {
-        // node-factor bits are allocated first, so with at most 32 node factors the A, B and E
-        // masks live in word 0
+        // node-factor bits are allocated first, then the combined weight-4 phase term, so with
+        // at most 31 node factors the A, B, E and R*4 masks live in word 0
         bool word0 = W > 1;
         for (int i = 0; i < kSlots && word0; ++i) {
-            if (slot_stat(i) == STAT_R) continue;
+            if (slot_stat(i) == STAT_R && slot_weight(i) != 4) continue;
             const uint32_t *m = img.data() + H.off_slots + i * (W + 1) + 1;
             for (int k = 1; k < W; ++k) word0 = word0 && m[k] == 0;
         }

@@ -355,9 +355,10 @@ def test_node_table_largest_terms(o2):
 @pytest.mark.parametrize("case", ["random", "node", "opposite", "constant"])
 def test_weight4_phase_parts_combined(o2, case):
     # the weight-4 parts of the linear phase terms as one form: beside node tables of 1 to 10
-    # factors (the combined bit makes 11 table bits at 10 factors), on a node factor's form,
-    # on another term's form with the other constant, or adding up to a constant
-    for n_nodes, p in [(1, 9), (4, 13), (10, 15), (0, 11), (6, 22)]:
+    # factors (the combined bit makes 11 table bits at 10 factors), with 20 or 31 factors
+    # (R*4 slot read from word 0 beside wider form vectors), on a node factor's form, on
+    # another term's form with the other constant, or adding up to a constant
+    for n_nodes, p in [(1, 9), (4, 13), (10, 15), (0, 11), (6, 22), (20, 16), (31, 14)]:
         if case == "node" and n_nodes == 0:
             continue
         prog = wl.weight4_phase_program(n_nodes, p, n_nodes, case)
