@@ -159,12 +159,13 @@ struct Acc {
             a32[k] = 0;
         }
     }
-    // A node-table program has at most kMaxTableNodes node factors, and a term's coordinates
-    // are at most 2^kMaxTableNodes in absolute value (each factor has coefficient sum 2 in the
-    // w-basis, and w^r and the linear phases only permute and negate coordinates), so the at
-    // most 64 terms a lane adds in one block sum to less than 2^31: they are added in 32-bit
-    // registers (one shift-and-add each) and moved to the int64 sums after the block.
-    static_assert(kMaxTableNodes + kMaxInnerBits < 31, "a block's sum must fit in int32");
+    // With n node factors a term's coordinates are at most 2^n in absolute value (each factor
+    // has coefficient sum 2 in the w-basis, and w^r and the linear phases only permute and
+    // negate coordinates), so when n + KB <= 30 (header flag block_sum32; always so for
+    // node-table programs) the 2^KB terms a lane adds in one block sum to less than 2^31: they
+    // are added in 32-bit registers (one shift-and-add each) and moved to the int64 sums after
+    // the block.
+    static_assert(kMaxTableNodes + kMaxInnerBits < 31, "node-table blocks must fit in int32");
     __device__ void flush32() {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -310,7 +311,7 @@ __device__ __forceinline__ uint32_t field_at(const uint32_t (&fv)[NF], uint32_t 
 // (valid = false) and never report a surviving term, so the queue is always operated on by
 // the whole wave.
 // Blocks [b0, b1) of the slice are walked; L and phi hold the state of block b0's first term.
-template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ, bool ZT>
+template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ, bool ZT, bool B32 = false>
 __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
                                             unsigned long long *cnt, uint64_t s, bool valid, uint32_t b0,
                                             uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, WaveQueue *Q,
@@ -318,8 +319,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     constexpr int KB = inner_bits_for(W);  // inner bits of a block
     constexpr int KS = 1 << KB;             // its terms
     constexpr int NF = KS / 8;              // words of its 4-bit phase fields
-    // node-table programs in int64 mode add a block's terms in 32 bits (Acc::flush32)
-    constexpr bool B32 = ACC == ACC_I64 && (SET & kSlotsNodeTable) != 0 && !CQ;
+    static_assert(!B32 || (ACC == ACC_I64 && !CQ), "32-bit block sums: int64 mode, walks without a queue");
     CU32 *col = wd + H.off_col;
     uint32_t ck[KB][W];
 #pragma unroll
@@ -693,10 +693,25 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         return;
     }
     if (H.g >= (uint32_t)inner_bits_for(W)) {
-        if (!H.has_zero)
-            walk_blocks<W, MONO, ACC, SET, false, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
-        else if (!kCompact<W>)
-            walk_blocks<W, MONO, ACC, SET, true, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q, acc);
+        // int64 node-table and node-word-0 kernels add a block's terms in 32 bits where the
+        // header allows it
+        constexpr bool B32_OK = ACC == ACC_I64 && (SET & (kSlotsNodeTable | kSlotsNodeWord0)) != 0;
+        const bool b32 = B32_OK && H.block_sum32;
+        if (!H.has_zero) {
+            if (b32)
+                walk_blocks<W, MONO, ACC, SET, false, false, false, B32_OK>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi,
+                                                                           dal, Q, acc);
+            else
+                walk_blocks<W, MONO, ACC, SET, false, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal,
+                                                                    Q, acc);
+        } else if (!kCompact<W>) {
+            if (b32)
+                walk_blocks<W, MONO, ACC, SET, true, false, false, B32_OK>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi,
+                                                                          dal, Q, acc);
+            else
+                walk_blocks<W, MONO, ACC, SET, true, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q,
+                                                                   acc);
+        }
         return;
     }
     // short walks: one step at a time

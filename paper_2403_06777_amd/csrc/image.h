@@ -107,6 +107,7 @@ struct ImgHeader {
                         //   distinct slots).  Both tables are copied to dynamic LDS at byte
                         //   offset ztab_lds.
     uint32_t node_word0;  // the node-factor slot masks are zero beyond word 0
+    uint32_t block_sum32; // int64 mode, node factors + KB <= 30: a lane's block of terms sums below 2^31
     uint32_t n_slices_lo, n_slices_hi;  // 2^(pe - g)
     uint32_t off_col;   // pe * W words: forms containing packed position j
     uint32_t off_cvec;  // W words: L at the all-zero assignment

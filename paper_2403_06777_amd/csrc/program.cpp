@@ -946,6 +946,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         }
         H.node_word0 = word0 ? 1u : 0u;
     }
+    // a term's coordinates are at most 2^(node factors), a lane's block holds 2^KB terms
+    H.block_sum32 = acc_mode == ACC_I64 && n_nodes + KB <= 30 ? 1u : 0u;
     active_slots = __builtin_popcount(slot_set_of(H.slot_menu) & kSlotSetAll);
     // monomials in packed positions
     const uint64_t walk_mask = g >= 64 ? ~0ull : (((uint64_t)1 << g) - 1);
@@ -1264,13 +1266,17 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         const bool mono = !w.mono.empty();
         const bool blocks = g >= KB;
         const bool compact = blocks && has_zero && W <= 4;
-        // node-table programs in int64 mode walking blocks without compaction add a block's
-        // terms in 32 bits (one shift-and-add per coordinate) and move them to int64 per block
-        const bool b32 = H.acc == ACC_I64 && use_ntab && blocks && !compact;
+        // the slot set of the kernel variant the program is dispatched to (int128 mode: all)
+        const bool nw0_kernel = H.acc != ACC_I128 && W > 1 && W < 16 && H.node_word0 && H.slot_menu <= 1;
+        const uint32_t set = H.acc == ACC_I128 ? kSlotSetAll
+                                               : slot_set_of(H.slot_menu) | (nw0_kernel ? kSlotsNodeWord0 : 0u);
+        // node-table and node-word-0 programs in int64 mode whose block sums fit in 32 bits,
+        // walking blocks without compaction, add a block's terms in 32 bits (one shift-and-add
+        // per coordinate) and move them to int64 per block
+        const bool b32 = H.acc == ACC_I64 && H.block_sum32 && (H.slot_menu == 3 || nw0_kernel) && blocks && !compact;
         const double acc_ops = b32 ? 4.0 : H.acc == ACC_I64 ? 12.0 : H.acc == ACC_I128 ? 40.0 : 5.0;
         const double flush_ops = b32 ? 12.0 / KS : 0.0;
         double slot_ops = 0;
-        const uint32_t set = slot_set_of(H.slot_menu) | (H.node_word0 ? kSlotsNodeWord0 : 0u);
         for (int i = 0; i < kSlots; ++i)
             if (set >> i & 1) slot_ops += 2.0 * slot_words(set, i, W);
         const double stats = 8 + acc_ops + slot_ops + (mono ? 2 : 0);

@@ -352,6 +352,23 @@ def test_node_table_largest_terms(o2):
         assert gpu_value(text) == oracle_value(o2, text)
 
 
+@pytest.mark.parametrize("n_nodes", [24, 25])
+def test_block_sums_at_the_int32_bound(o2, n_nodes):
+    # 24 node factors 1 + w^0 = 2 at l = 0 on single parameters, two form words (64-term
+    # blocks): terms up to 2^24 in a coordinate, 64 of them just below 2^31, the most a block
+    # sums in 32 bits; with 25 factors the block sums stay in int64
+    rng = wl.SplitMix64(770, n_nodes)
+    p = n_nodes
+    prog = wl.ProgramSpec(p)
+    for i in range(n_nodes):
+        prog.nodes.append((prog.add_form(0, 1 << i), 0, 2))
+    for _ in range(12):
+        prog.lin.append((rng.randint(1, 7), prog.add_form(rng.randint(0, 1), rng.randint(1, (1 << p) - 1))))
+    text = prog.to_text()
+    say("int32 block-sum bound", n_nodes, zx.sim_ir_info(text)["n_forms"])
+    assert gpu_value(text) == oracle_value(o2, text)
+
+
 @pytest.mark.parametrize("case", ["random", "node", "opposite", "constant"])
 def test_weight4_phase_parts_combined(o2, case):
     # the weight-4 parts of the linear phase terms as one form: beside node tables of 1 to 10
