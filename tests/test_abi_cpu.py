@@ -176,3 +176,24 @@ def test_weight4_phase_parts_share_one_form():
         prog = wl.weight4_phase_program(0, 10, 2, case)
         n_forms = zx.sim_ir_info(prog.to_text())["n_forms"]
         assert n_forms == len(prog.forms) - {"constant": 3, "opposite": 1, "node": 2}[case]
+
+
+def _single_parameter_nodes(n_nodes, seed):
+    rng = wl.SplitMix64(770, seed)
+    prog = wl.ProgramSpec(n_nodes)
+    for i in range(n_nodes):
+        prog.nodes.append((prog.add_form(0, 1 << i), 0, 2))
+    for _ in range(12):
+        prog.lin.append((rng.randint(1, 7), prog.add_form(rng.randint(0, 1), rng.randint(1, (1 << n_nodes) - 1))))
+    return prog
+
+
+def test_block_sums_in_32_bits_stop_at_the_bound():
+    # two form words, 64-term blocks: with 24 node factors a block's terms sum below 2^31
+    # (24 + 6 <= 30) and are added in 32 bits (4 lane operations per term instead of 12, plus
+    # 12 per block); with 25 they are not
+    a = zx.sim_ir_info(_single_parameter_nodes(24, 24).to_text())
+    b = zx.sim_ir_info(_single_parameter_nodes(25, 25).to_text())
+    assert a["n_forms"] > 32 and b["n_forms"] > 32 and a["n_forms"] <= 64 and b["n_forms"] <= 64
+    # (the one more high parameter adds 4 / 256 to the per-slice set-up)
+    assert b["ops_per_term"] - a["ops_per_term"] == pytest.approx(8 - 12 / 64 + 4 / 256, abs=1e-9)
