@@ -153,7 +153,7 @@ def outcomes_section(stream, seed: int = 1, n_max: int = 1000) -> dict:
 
 
 def sampling_section(stream, seed: int = 0, n_max: int = 1000) -> dict:
-    """Repeated weak simulation (Appendix E): the prefix programs of the first k qubits
+    """Repeated weak simulation (Appendix F): the prefix programs of the first k qubits
     (doubled diagram, the k outcomes as parameters) compiled once for k = 1 .. n, then N
     samples drawn bit by bit, each step evaluating every distinct prefix once in one batch;
     against compiling and evaluating each of those prefixes as a fixed-string program."""

@@ -85,7 +85,7 @@ typedef struct {
  * program's last n_qubits parameters are y_0 .. y_{n-1} (see sim_eval_outcomes).
  * PREFIX: the marginal of the first k = qubit qubits, P(y_0 .. y_{k-1}) =
  * <0^n| C^dag (|y><y|_{0..k-1} (x) I) C |0^n> (the doubled diagram of Fig. 3 right, the
- * k-th step of the repeated weak simulation of Appendix E), 1 <= k <= n_qubits.  With
+ * k-th step of the repeated weak simulation of Appendix F), 1 <= k <= n_qubits.  With
  * out_bits NULL the k outcomes are query parameters (the program's last k parameters are
  * y_0 .. y_{k-1}, k <= 62; evaluate with sim_eval_outcomes or sim_sample); otherwise y_i =
  * out_bits[i] for i < k and the program is a plain scalar. */
@@ -264,8 +264,8 @@ SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *
 SIM_API int sim_enqueue_amplitude(const sim_program *prog, void *stream, void *ev_before, void *ev_after,
                                   sim_zomega *dev_out);
 
-/* Repeated weak simulation (Appendix E's algorithm, with the conditional probabilities of
- * the product rule of Section 2.3).  progs[k-1] is the PREFIX program of the first k qubits
+/* Repeated weak simulation (Appendix F's algorithm, with the conditional probabilities of
+ * the product rule of Section 2.2).  progs[k-1] is the PREFIX program of the first k qubits
  * of one circuit, compiled with the outcomes as parameters (k = 1 .. K, K <= 62); the caller
  * guarantees they come from the same circuit.  uniforms holds n rows of K integers below
  * 2^53; sample i draws its bits in qubit order, bit k being 0 iff
@@ -288,6 +288,60 @@ SIM_API int sim_sample(const sim_program *const *progs, size_t K, size_t n, cons
  * sum exceeds int128 coefficients. */
 SIM_API int sim_marginal_sum(const sim_program *prog, const uint8_t *pattern, void *stream,
                              const sim_tuning *t, sim_zomega *out);
+
+/* ---- caller-owned scratch (the repeated-evaluation interface of Sections 3.3 and 4: many
+ * evaluations of resident programs, the caller owning every device buffer).
+ *
+ * The calls below take device memory from the caller instead of the library's own scratch:
+ * dev_scratch (256-byte aligned, e.g. a torch tensor's data_ptr()) of scratch_bytes bytes.
+ * They never allocate or free device memory; a region that is too small gives SIM_ERANGE
+ * (message: the bytes needed) and nothing is launched.  The caller must not use the region
+ * for anything else while a call that uses it runs on the device.  Results are exactly those
+ * of the library-scratch calls they mirror. */
+
+/* Bytes of dev_scratch that sim_eval_amplitude_ws and sim_eval_range_ws need for any of the n
+ * programs, and that sim_eval_batch_ws, sim_batch_prepare and sim_enqueue_batch need for the
+ * whole set (the largest of these).  t may be NULL. */
+SIM_API int sim_scratch_bytes(const sim_program *const *progs, size_t n, const sim_tuning *t, size_t *bytes);
+
+/* sim_eval_amplitude with the partial sums in dev_scratch.  Blocks until *out is valid. */
+SIM_API int sim_eval_amplitude_ws(const sim_program *prog, void *stream, void *dev_scratch, size_t scratch_bytes,
+                                  sim_zomega *out);
+
+/* Raw partial sum (flags = RAW) over the assignments of units [first, first + count), a unit
+ * being 2^g consecutive assignments in slice order (sim_program_layout), with the program's
+ * walk bits <= g <= p: g = walk bits is sim_eval_range; larger g splits the 2^p assignments
+ * into 2^(p - g) equal shards (Section 3.3's independent terms, e.g. one per GPU).  Partials of
+ * disjoint ranges add exactly (sim_raw_add); finish with sim_finalize.  SIM_EINVAL if g is out
+ * of bounds or the range leaves the program.  Blocks until *raw is valid. */
+SIM_API int sim_eval_range_ws(const sim_program *prog, uint64_t first, uint64_t count, uint32_t g, void *stream,
+                              void *dev_scratch, size_t scratch_bytes, sim_zomega *raw);
+
+/* sim_eval_batch with the work layout, partials and results in dev_scratch.  Blocks. */
+SIM_API int sim_eval_batch_ws(const sim_program *const *progs, size_t n, void *stream, void *dev_scratch,
+                              size_t scratch_bytes, const sim_tuning *t, sim_zomega *out);
+
+/* Writes the work layout of a batch of n programs (as sim_eval_batch would run them, tuning t,
+ * which may be NULL) into dev_scratch and waits for the copy; it also creates the library's
+ * auxiliary streams if they do not exist yet.  After that, sim_enqueue_batch with the same
+ * programs, tuning and dev_scratch may be called any number of times, including under stream
+ * capture.  The library keeps a small host-side record of the prepared region (until it is
+ * prepared again or sim_batch_forget); the programs must outlive it. */
+SIM_API int sim_batch_prepare(const sim_program *const *progs, size_t n, const sim_tuning *t, void *dev_scratch,
+                              size_t scratch_bytes, void *stream);
+
+/* Enqueues the batch prepared in dev_scratch on stream without waiting: the device writes the
+ * n canonical results to dev_out (caller-owned device memory, n sim_zomega, 8-byte aligned),
+ * each bit-identical to sim_eval_amplitude.  No allocation, no host synchronisation and no
+ * host memory read by the enqueued work, so a hipGraph capture of the call replays it.  The
+ * kernel variants of the batch run on the library's auxiliary streams, forked from and joined
+ * back into `stream` with events; while a capture holds such a call, no other call on the
+ * device may run.  SIM_EINVAL if dev_scratch was not prepared for these programs and tuning. */
+SIM_API int sim_enqueue_batch(const sim_program *const *progs, size_t n, void *stream, void *dev_scratch,
+                              size_t scratch_bytes, const sim_tuning *t, sim_zomega *dev_out);
+
+/* Drops the host-side record of a region prepared on the current device (no-op if none). */
+SIM_API int sim_batch_forget(void *dev_scratch);
 
 /* sim_finalize for n programs in one launch: out[i] = finalised raws[i] of progs[i]. */
 SIM_API int sim_finalize_batch(const sim_program *const *progs, const sim_zomega *raws, size_t n,

@@ -1,7 +1,7 @@
 """Repeated weak simulation by the chain rule: TEST INFRASTRUCTURE ONLY.
 
-What it computes (the product rule of Section 2.3, used by the weak-simulation algorithm of
-Appendix E): the bits of a sample are drawn in qubit order, and bit k is 0 exactly when
+What it computes (the product rule of Section 2.2, used by the weak-simulation algorithm of
+Appendix F): the bits of a sample are drawn in qubit order, and bit k is 0 exactly when
 u_k < P(B || 0) / P(B), where B holds the bits drawn so far, P(prefix) is the probability that
 the first len(prefix) qubits show that prefix, and u_k is uniform in [0, 1).  Here
 u_k = U_k / 2^53 for a 53-bit integer U_k passed in, and the test U_k P(B) < 2^53 P(B || 0)

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     marginal_query,
     outcomes_query,
     prefix_query,
+    sim_batch_forget,
     sim_batch_plan_create,
     sim_batch_plan_free,
     sim_batch_plan_run,
@@ -20,6 +21,13 @@ from .binding import (  # noqa: F401
     sim_device_cus,
     sim_enqueue_amplitude,
     sim_eval_amplitude,
+    sim_eval_amplitude_ws,
+    sim_eval_batch_ws,
+    sim_eval_range_ws,
+    sim_enqueue_batch,
+    sim_batch_prepare,
+    sim_scratch_bytes,
+    zomegas_from_bytes,
     sim_eval_batch,
     sim_eval_range,
     sim_eval_timed,

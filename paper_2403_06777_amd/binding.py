@@ -131,6 +131,18 @@ SIGNATURES = [
                                           ctypes.POINTER(sim_zomega)]),
     ("sim_raw_add", ctypes.c_int, [ctypes.POINTER(sim_zomega), ctypes.POINTER(sim_zomega),
                                    ctypes.POINTER(sim_zomega)]),
+    ("sim_scratch_bytes", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(sim_tuning),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    ("sim_eval_amplitude_ws", ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, ctypes.POINTER(sim_zomega)]),
+    ("sim_eval_range_ws", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _P, _P,
+                                         ctypes.c_size_t, ctypes.POINTER(sim_zomega)]),
+    ("sim_eval_batch_ws", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, _P, _P, ctypes.c_size_t,
+                                         ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_batch_prepare", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(sim_tuning), _P,
+                                         ctypes.c_size_t, _P]),
+    ("sim_enqueue_batch", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, _P, _P, ctypes.c_size_t,
+                                         ctypes.POINTER(sim_tuning), _P]),
+    ("sim_batch_forget", ctypes.c_int, [_P]),
     ("sim_program_free", None, [_P]),
     ("sim_last_error", ctypes.c_char_p, []),
     ("sim_device_cus", ctypes.c_int, []),
@@ -437,6 +449,58 @@ def sim_batch_plan_run(plan: int, n: int, stream=None):
 
 def sim_batch_plan_free(plan: int):
     lib().sim_batch_plan_free(plan)
+
+
+def sim_scratch_bytes(progs: Sequence[int], tuning: Optional[dict] = None) -> int:
+    """bytes of caller-owned device scratch the *_ws calls and sim_enqueue_batch need"""
+    out = ctypes.c_size_t()
+    _check(lib().sim_scratch_bytes(_prog_array(progs), len(progs), _tuning(tuning), ctypes.byref(out)))
+    return out.value
+
+
+def sim_eval_amplitude_ws(prog: int, dev_scratch: int, scratch_bytes: int, stream=None):
+    out = sim_zomega()
+    _check(lib().sim_eval_amplitude_ws(prog, _stream(stream), dev_scratch, scratch_bytes, ctypes.byref(out)))
+    return _scalar(out)
+
+
+def sim_eval_range_ws(prog: int, first: int, count: int, g: int, dev_scratch: int, scratch_bytes: int,
+                      stream=None):
+    out = sim_zomega()
+    _check(lib().sim_eval_range_ws(prog, first, count, g, _stream(stream), dev_scratch, scratch_bytes,
+                                   ctypes.byref(out)))
+    return out.coeffs()
+
+
+def sim_eval_batch_ws(progs: Sequence[int], dev_scratch: int, scratch_bytes: int, stream=None,
+                      tuning: Optional[dict] = None):
+    n = len(progs)
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_eval_batch_ws(_prog_array(progs), n, _stream(stream), dev_scratch, scratch_bytes,
+                                   _tuning(tuning), outs))
+    return [_scalar(outs[i]) for i in range(n)]
+
+
+def sim_batch_prepare(progs: Sequence[int], dev_scratch: int, scratch_bytes: int, stream=None,
+                      tuning: Optional[dict] = None):
+    _check(lib().sim_batch_prepare(_prog_array(progs), len(progs), _tuning(tuning), dev_scratch, scratch_bytes,
+                                   _stream(stream)))
+
+
+def sim_enqueue_batch(progs: Sequence[int], dev_scratch: int, scratch_bytes: int, dev_out: int, stream=None,
+                      tuning: Optional[dict] = None):
+    """Enqueues a prepared batch; the device writes len(progs) 72-byte results to dev_out."""
+    _check(lib().sim_enqueue_batch(_prog_array(progs), len(progs), _stream(stream), dev_scratch, scratch_bytes,
+                                   _tuning(tuning), dev_out))
+
+
+def sim_batch_forget(dev_scratch: int):
+    _check(lib().sim_batch_forget(dev_scratch))
+
+
+def zomegas_from_bytes(b: bytes, n: int):
+    """n results of 72 bytes each, as written by the device (sim_enqueue_batch)"""
+    return [zomega_from_bytes(bytes(b[72 * i:72 * (i + 1)])) for i in range(n)]
 
 
 def sim_program_free(prog: int):

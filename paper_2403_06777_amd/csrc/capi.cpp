@@ -1,14 +1,17 @@
 // C-ABI of the library: programs, single-program evaluation, ranges, batches and plans.
 //
 // Device memory: a program's packed image is uploaded once at creation.  Per-block partial
-// sums, batch work lists and result slots live in per-device scratch buffers owned by the
-// library (grown on demand, kept until the process ends) and guarded by a per-device lock.
+// sums, batch work lists and result slots of one call are laid out in one region of device
+// scratch memory: the library's own per-device buffer (grown on demand, kept until the process
+// ends, guarded by a per-device lock), or memory the caller owns and passes in (the *_ws entry
+// points, sim_batch_prepare / sim_enqueue_batch), which the library never grows or frees.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -59,7 +62,7 @@ struct DeviceState {
     bool ready = false;
     int cus = 0;
     std::mutex mu;
-    DevBuf partials, result, stage;
+    DevBuf ws;                    // the library's scratch region
     void *host_result = nullptr;  // pinned
     size_t host_cap = 0;
     void *host_stage = nullptr;   // pinned staging of batch layouts
@@ -205,38 +208,100 @@ int eval_grid(DeviceState &D, const sim_program *P, uint64_t count, uint32_t thr
     return SIM_OK;
 }
 
-// one evaluation of a slice range: kernel + finaliser + readback (device lock held)
+// ---- scratch regions
+
+constexpr size_t kAlign = 256;
+size_t up256(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// device memory one call lays its buffers out in
+struct Region {
+    char *base = nullptr;
+    size_t cap = 0;
+};
+
+// the library's own scratch, grown to at least `need` bytes (work enqueued without waiting
+// still uses it, so that is waited for before the buffer is replaced); device lock held
+int lib_region(DeviceState &D, size_t need, Region *R) {
+    if (D.ws.cap < need) {
+        int rc = settle(D);
+        if (rc) return rc;
+        if ((rc = ensure(D.ws, need))) return rc;
+    }
+    R->base = (char *)D.ws.ptr;
+    R->cap = D.ws.cap;
+    return SIM_OK;
+}
+
+// memory the caller passed in: never grown; too small is an error
+int caller_region(void *dev_scratch, size_t bytes, size_t need, Region *R) {
+    if (!dev_scratch) return fail(SIM_EINVAL, "null dev_scratch");
+    if (reinterpret_cast<uintptr_t>(dev_scratch) % kAlign) return fail(SIM_EINVAL, "dev_scratch must be 256-byte aligned");
+    if (bytes < need)
+        return fail(SIM_ERANGE, "dev_scratch holds " + std::to_string(bytes) + " bytes; the call needs " +
+                                    std::to_string(need) + " (see sim_scratch_bytes)");
+    R->base = (char *)dev_scratch;
+    R->cap = bytes;
+    return SIM_OK;
+}
+
+// a single-program evaluation: per-workgroup partials at offset 0, its result at o_res
+struct SinglePlan {
+    uint32_t blocks = 1, threads = 256;
+    size_t o_res = 0, total = 0;
+};
+
+int plan_single(DeviceState &D, const sim_program *P, uint64_t count, const sim_tuning *t, SinglePlan *S) {
+    S->threads = pick_threads(t);
+    int rc = eval_grid(D, P, count, S->threads, t, &S->blocks);
+    if (rc) return rc;
+    S->o_res = up256((size_t)S->blocks * sizeof(Partial));
+    S->total = S->o_res + up256(sizeof(DevResult));
+    return SIM_OK;
+}
+
+// events created for one call and destroyed on every return path
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Blocking evaluation of one slice range in region R (laid out by S): kernel, finaliser, copy of
+// the 72-byte result to host memory (`pinned` staging of the library, or a pageable copy) and a
+// wait on the stream.  Device lock held.
+int eval_single(const sim_program *P, uint64_t first, uint64_t count, bool raw, const SinglePlan &S, const Region &R,
+                void *pinned, hipStream_t stream, sim_zomega *out, float *kernel_ms = nullptr) {
+    Partial *parts = (Partial *)R.base;
+    DevResult *dres = (DevResult *)(R.base + S.o_res);
+    EventPair ev;
+    if (kernel_ms) {
+        HIP_TRY(hipEventCreate(&ev.a));
+        HIP_TRY(hipEventCreate(&ev.b));
+        HIP_TRY(hipEventRecord(ev.a, stream));
+    }
+    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, first, count, parts, S.blocks, S.threads, stream));
+    if (kernel_ms) HIP_TRY(hipEventRecord(ev.b, stream));
+    HIP_TRY(launch_finalize(parts, S.blocks, final_args(P->pk, raw), dres, stream));
+    DevResult r;
+    HIP_TRY(hipMemcpyAsync(pinned ? pinned : (void *)&r, dres, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (kernel_ms) HIP_TRY(hipEventElapsedTime(kernel_ms, ev.a, ev.b));
+    if (pinned) memcpy(&r, pinned, sizeof r);
+    return to_zomega(r, out);
+}
+
+// one evaluation of a slice range in the library's scratch (device lock held)
 int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint64_t count, bool raw,
                       hipStream_t stream, const sim_tuning *t, sim_zomega *out, float *kernel_ms = nullptr) {
-    const PackedProgram &pk = P->pk;
-    const uint32_t threads = pick_threads(t);
-    uint32_t blocks = 1;
+    SinglePlan S;
+    Region R;
     int rc;
-    if ((rc = eval_grid(D, P, count, threads, t, &blocks))) return rc;
-    if ((rc = ensure(D.partials, (size_t)blocks * sizeof(Partial)))) return rc;
-    if ((rc = ensure(D.result, sizeof(DevResult)))) return rc;
+    if ((rc = plan_single(D, P, count, t, &S))) return rc;
+    if ((rc = lib_region(D, S.total, &R))) return rc;
     if ((rc = ensure_host(D, sizeof(DevResult)))) return rc;
-    Partial *parts = (Partial *)D.partials.ptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (kernel_ms) {
-        HIP_TRY(hipEventCreate(&ev0));
-        HIP_TRY(hipEventCreate(&ev1));
-        HIP_TRY(hipEventRecord(ev0, stream));
-    }
-    HIP_TRY(launch_eval(pk.hdr, P->dimg, first, count, parts, blocks, threads, stream));
-    if (kernel_ms) HIP_TRY(hipEventRecord(ev1, stream));
-    FinalArgs fa = final_args(pk, raw);
-    HIP_TRY(launch_finalize(parts, blocks, fa, (DevResult *)D.result.ptr, stream));
-    HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    if (kernel_ms) {
-        HIP_TRY(hipEventElapsedTime(kernel_ms, ev0, ev1));
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
-    }
-    DevResult r;
-    memcpy(&r, D.host_result, sizeof r);
-    return to_zomega(r, out);
+    return eval_single(P, first, count, raw, S, R, D.host_result, stream, out, kernel_ms);
 }
 
 int finish_program(std::unique_ptr<sim_program> &P, sim_program **out) {
@@ -461,20 +526,17 @@ int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, v
         HIP_TRY(hipMemcpyAsync(dev_out, &zero, sizeof zero, hipMemcpyHostToDevice, st));
         return SIM_OK;
     }
-    const uint32_t threads = pick_threads(nullptr);
-    uint32_t blocks = 1;
-    if ((rc = eval_grid(*D, P, P->pk.n_slices, threads, nullptr, &blocks))) return rc;
-    if (D->partials.cap < (size_t)blocks * sizeof(Partial)) {
-        // growing the scratch frees the old buffer: enqueued work must be done with it
-        if ((rc = settle(*D))) return rc;
-        if ((rc = ensure(D->partials, (size_t)blocks * sizeof(Partial)))) return rc;
-    }
+    SinglePlan S;
+    Region R;
+    if ((rc = plan_single(*D, P, P->pk.n_slices, nullptr, &S))) return rc;
+    // growing the scratch frees the old buffer: lib_region waits for enqueued work first
+    if ((rc = lib_region(*D, S.o_res, &R))) return rc;
     if (D->pending && D->pending_stream != st) HIP_TRY(hipStreamWaitEvent(st, D->ev_pending, 0));
-    Partial *parts = (Partial *)D->partials.ptr;
+    Partial *parts = (Partial *)R.base;
     if (ev_before) HIP_TRY(hipEventRecord((hipEvent_t)ev_before, st));
-    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, 0, P->pk.n_slices, parts, blocks, threads, st));
+    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, 0, P->pk.n_slices, parts, S.blocks, S.threads, st));
     if (ev_after) HIP_TRY(hipEventRecord((hipEvent_t)ev_after, st));
-    HIP_TRY(launch_finalize(parts, blocks, final_args(P->pk, false), reinterpret_cast<DevResult *>(dev_out), st));
+    HIP_TRY(launch_finalize(parts, S.blocks, final_args(P->pk, false), reinterpret_cast<DevResult *>(dev_out), st));
     HIP_TRY(hipEventRecord(D->ev_pending, st));
     D->pending = true;
     D->pending_stream = st;
@@ -526,18 +588,19 @@ int sim_finalize(const sim_program *P, const sim_zomega *raw, void *stream, sim_
     std::lock_guard<std::mutex> lk(D->mu);
     if ((rc = settle(*D))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = ensure(D->partials, sizeof(Partial)))) return rc;
-    if ((rc = ensure(D->result, sizeof(DevResult)))) return rc;
+    Region R;
+    const size_t o_res = up256(sizeof(Partial));
+    if ((rc = lib_region(*D, o_res + up256(sizeof(DevResult)), &R))) return rc;
     if ((rc = ensure_host(*D, sizeof(DevResult)))) return rc;
     Partial part;
     for (int k = 0; k < 4; ++k) {
         part.w[2 * k] = raw->c[k].lo;
         part.w[2 * k + 1] = (uint64_t)raw->c[k].hi;
     }
-    HIP_TRY(hipMemcpyAsync(D->partials.ptr, &part, sizeof part, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(R.base, &part, sizeof part, hipMemcpyHostToDevice, st));
     FinalArgs fa = final_args(P->pk, false);
-    HIP_TRY(launch_finalize((Partial *)D->partials.ptr, 1, fa, (DevResult *)D->result.ptr, st));
-    HIP_TRY(hipMemcpyAsync(D->host_result, D->result.ptr, sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIP_TRY(launch_finalize((Partial *)R.base, 1, fa, (DevResult *)(R.base + o_res), st));
+    HIP_TRY(hipMemcpyAsync(D->host_result, R.base + o_res, sizeof(DevResult), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     DevResult r;
     memcpy(&r, D->host_result, sizeof r);
@@ -733,56 +796,88 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
     return SIM_OK;
 }
 
-// device addresses of the pieces of a batch layout inside one staging buffer
+// device addresses of the pieces of a batch layout inside one region
 struct LayoutPtrs {
     const ImgHeader *hdrs;
     const uint64_t *imgs;
     const WorkItem *items;
     const uint32_t *firsts, *counts;
     const FinalArgs *args;
+    Partial *parts;
+    DevResult *res;  // null when the results go elsewhere (sim_enqueue_batch)
+};
+
+// Byte offsets of a batch inside its region: the work layout (headers, image addresses, item
+// ranges, finaliser arguments, work items: uploaded with one copy), the partials and, unless the
+// caller provides device memory for them, the results.
+struct BatchPlan {
+    size_t o_hdrs = 0, o_imgs = 0, o_firsts = 0, o_counts = 0, o_args = 0, o_items = 0, stage = 0;
+    size_t o_parts = 0, o_res = 0, total = 0;
 };
 
 size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// packs the layout into pinned host memory and uploads it with one copy
-int upload_layout(DeviceState &D, const BatchLayout &L, size_t n, hipStream_t st, LayoutPtrs *P) {
-    const size_t o_hdrs = 0;
-    const size_t o_imgs = align16(o_hdrs + n * sizeof(ImgHeader));
-    const size_t o_firsts = align16(o_imgs + n * 8);
-    const size_t o_counts = align16(o_firsts + n * 4);
-    const size_t o_args = align16(o_counts + n * 4);
-    const size_t o_items = align16(o_args + n * sizeof(FinalArgs));
-    const size_t total = align16(o_items + L.items.size() * sizeof(WorkItem)) + 16;
-    int rc;
-    if ((rc = ensure(D.stage, total))) return rc;
-    if (D.host_stage_cap < total) {
-        if (D.host_stage) (void)hipHostFree(D.host_stage);
-        D.host_stage = nullptr;
-        D.host_stage_cap = 0;
-        hipError_t e = hipHostMalloc(&D.host_stage, std::max<size_t>(total, 1 << 16), hipHostMallocDefault);
-        if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
-        D.host_stage_cap = std::max<size_t>(total, 1 << 16);
-    }
-    char *h = (char *)D.host_stage;
+BatchPlan plan_batch(const BatchLayout &L, size_t n, bool results) {
+    BatchPlan B;
+    B.o_hdrs = 0;
+    B.o_imgs = align16(B.o_hdrs + n * sizeof(ImgHeader));
+    B.o_firsts = align16(B.o_imgs + n * 8);
+    B.o_counts = align16(B.o_firsts + n * 4);
+    B.o_args = align16(B.o_counts + n * 4);
+    B.o_items = align16(B.o_args + n * sizeof(FinalArgs));
+    B.stage = align16(B.o_items + L.items.size() * sizeof(WorkItem)) + 16;
+    B.o_parts = up256(B.stage);
+    B.o_res = up256(B.o_parts + std::max<size_t>(1, L.n_partials) * sizeof(Partial));
+    B.total = results ? up256(B.o_res + std::max<size_t>(1, n) * sizeof(DevResult)) : B.o_res;
+    return B;
+}
+
+void pack_stage(const BatchLayout &L, size_t n, const BatchPlan &B, char *h) {
     if (n) {
-        memcpy(h + o_hdrs, L.hdrs.data(), n * sizeof(ImgHeader));
-        memcpy(h + o_imgs, L.imgs.data(), n * 8);
-        memcpy(h + o_firsts, L.firsts.data(), n * 4);
-        memcpy(h + o_counts, L.counts.data(), n * 4);
-        memcpy(h + o_args, L.args.data(), n * sizeof(FinalArgs));
+        memcpy(h + B.o_hdrs, L.hdrs.data(), n * sizeof(ImgHeader));
+        memcpy(h + B.o_imgs, L.imgs.data(), n * 8);
+        memcpy(h + B.o_firsts, L.firsts.data(), n * 4);
+        memcpy(h + B.o_counts, L.counts.data(), n * 4);
+        memcpy(h + B.o_args, L.args.data(), n * sizeof(FinalArgs));
     }
-    if (!L.items.empty()) memcpy(h + o_items, L.items.data(), L.items.size() * sizeof(WorkItem));
-    if ((rc = ensure(D.partials, std::max<size_t>(1, L.n_partials) * sizeof(Partial)))) return rc;
-    if ((rc = ensure(D.result, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
-    if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
-    HIP_TRY(hipMemcpyAsync(D.stage.ptr, h, total, hipMemcpyHostToDevice, st));
-    char *d = (char *)D.stage.ptr;
-    P->hdrs = (const ImgHeader *)(d + o_hdrs);
-    P->imgs = (const uint64_t *)(d + o_imgs);
-    P->firsts = (const uint32_t *)(d + o_firsts);
-    P->counts = (const uint32_t *)(d + o_counts);
-    P->args = (const FinalArgs *)(d + o_args);
-    P->items = (const WorkItem *)(d + o_items);
+    if (!L.items.empty()) memcpy(h + B.o_items, L.items.data(), L.items.size() * sizeof(WorkItem));
+}
+
+LayoutPtrs layout_ptrs(const BatchPlan &B, const Region &R, bool results) {
+    LayoutPtrs P;
+    P.hdrs = (const ImgHeader *)(R.base + B.o_hdrs);
+    P.imgs = (const uint64_t *)(R.base + B.o_imgs);
+    P.firsts = (const uint32_t *)(R.base + B.o_firsts);
+    P.counts = (const uint32_t *)(R.base + B.o_counts);
+    P.args = (const FinalArgs *)(R.base + B.o_args);
+    P.items = (const WorkItem *)(R.base + B.o_items);
+    P.parts = (Partial *)(R.base + B.o_parts);
+    P.res = results ? (DevResult *)(R.base + B.o_res) : nullptr;
+    return P;
+}
+
+// Uploads the work layout into R: from the library's pinned staging (library scratch), or from
+// pageable host memory that `keep` holds until the caller has waited on the stream.
+int upload_stage(DeviceState &D, const BatchLayout &L, size_t n, const BatchPlan &B, const Region &R, bool lib,
+                 hipStream_t st, std::vector<char> *keep) {
+    char *h;
+    if (lib) {
+        if (D.host_stage_cap < B.stage) {
+            if (D.host_stage) (void)hipHostFree(D.host_stage);
+            D.host_stage = nullptr;
+            D.host_stage_cap = 0;
+            const size_t cap = std::max<size_t>(B.stage, 1 << 16);
+            hipError_t e = hipHostMalloc(&D.host_stage, cap, hipHostMallocDefault);
+            if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+            D.host_stage_cap = cap;
+        }
+        h = (char *)D.host_stage;
+    } else {
+        keep->assign(B.stage, 0);
+        h = keep->data();
+    }
+    pack_stage(L, n, B, h);
+    HIP_TRY(hipMemcpyAsync(R.base, h, B.stage, hipMemcpyHostToDevice, st));
     return SIM_OK;
 }
 
@@ -800,29 +895,45 @@ int check_batch_args(const sim_program *const *ps, size_t n, int *dev) {
     return init_device(*dev);
 }
 
-int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, const uint64_t *count, bool raw,
-              void *stream, const sim_tuning *t, sim_zomega *out) {
-    int dev, rc;
-    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+int check_ranges(const sim_program *const *ps, size_t n, const uint64_t *first, const uint64_t *count) {
     if (first && count)
         for (size_t i = 0; i < n; ++i)
             if (first[i] > ps[i]->pk.n_slices || count[i] > ps[i]->pk.n_slices - first[i])
                 return fail(SIM_EINVAL, "slice range outside a program");
-    HIP_TRY(hipSetDevice(dev));
-    DeviceState &D = g_dev[dev];
-    std::lock_guard<std::mutex> lk(D.mu);
-    if ((rc = settle(D))) return rc;
+    return SIM_OK;
+}
+
+// A blocking batch in region R (caller memory or the file-scope array; null: the library's
+// scratch): upload, kernels, finaliser, copy of the results to host memory, wait.  Device lock
+// held.
+int run_batch_locked(DeviceState &D, const sim_program *const *ps, size_t n, const uint64_t *first,
+                     const uint64_t *count, bool raw, hipStream_t st, const sim_tuning *t, const Region *given,
+                     sim_zomega *out) {
+    int rc;
     BatchLayout L;
     if ((rc = build_layout(D, ps, n, first, count, raw, t, &L))) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    LayoutPtrs LP;
-    if ((rc = upload_layout(D, L, n, st, &LP))) return rc;
+    const BatchPlan B = plan_batch(L, n, true);
+    Region R;
+    const bool lib = given == nullptr;
+    if (lib) {
+        if ((rc = lib_region(D, B.total, &R))) return rc;
+        if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
+    } else {
+        if (given->cap < B.total)
+            return fail(SIM_ERANGE, "scratch holds " + std::to_string(given->cap) + " bytes; the batch needs " +
+                                        std::to_string(B.total));
+        R = *given;
+    }
+    std::vector<char> keep;
+    std::vector<DevResult> host(lib ? 0 : std::max<size_t>(1, n));
+    DevResult *hres = lib ? (DevResult *)D.host_result : host.data();
     if (!L.live.empty()) {
-        if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items,
-                                (Partial *)D.partials.ptr, LP.firsts, LP.counts, LP.args,
-                                (DevResult *)D.result.ptr)))
+        if ((rc = upload_stage(D, L, n, B, R, lib, st, &keep))) return rc;
+        const LayoutPtrs LP = layout_ptrs(B, R, true);
+        if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items, LP.parts, LP.firsts, LP.counts, LP.args,
+                                LP.res)))
             return rc;
-        HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hres, LP.res, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(hipStreamSynchronize(st));
     std::vector<sim_zomega> res(n);
@@ -834,11 +945,23 @@ int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, con
             continue;
         }
         DevResult r;
-        memcpy(&r, (const char *)D.host_result + i * sizeof(DevResult), sizeof r);
+        memcpy(&r, (const char *)hres + i * sizeof(DevResult), sizeof r);
         if ((rc = to_zomega(r, &res[i]))) return rc;
     }
     for (size_t i = 0; i < n; ++i) out[i] = res[i];
     return SIM_OK;
+}
+
+int run_batch(const sim_program *const *ps, size_t n, const uint64_t *first, const uint64_t *count, bool raw,
+              void *stream, const sim_tuning *t, sim_zomega *out) {
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    if ((rc = check_ranges(ps, n, first, count))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    if ((rc = settle(D))) return rc;
+    return run_batch_locked(D, ps, n, first, count, raw, (hipStream_t)stream, t, nullptr, out);
 }
 
 }  // namespace
@@ -1133,19 +1256,22 @@ int sim_finalize_batch(const sim_program *const *ps, const sim_zomega *raws, siz
         L.args[i] = final_args(ps[i]->pk, false);
         L.firsts[i] = (uint32_t)i;
     }
-    L.items.resize(n);
-    LayoutPtrs LP;
-    if ((rc = upload_layout(D, L, n, st, &LP))) return rc;
+    L.n_partials = n;
+    const BatchPlan B = plan_batch(L, n, true);
+    Region R;
+    if ((rc = lib_region(D, B.total, &R))) return rc;
+    if ((rc = ensure_host(D, n * sizeof(DevResult)))) return rc;
+    if ((rc = upload_stage(D, L, n, B, R, true, st, nullptr))) return rc;
+    const LayoutPtrs LP = layout_ptrs(B, R, true);
     std::vector<Partial> parts(n);
     for (size_t i = 0; i < n; ++i)
         for (int k = 0; k < 4; ++k) {
             parts[i].w[2 * k] = raws[i].c[k].lo;
             parts[i].w[2 * k + 1] = (uint64_t)raws[i].c[k].hi;
         }
-    HIP_TRY(hipMemcpyAsync(D.partials.ptr, parts.data(), n * sizeof(Partial), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_finalize_batch((Partial *)D.partials.ptr, LP.firsts, LP.counts, LP.args, (uint32_t)n,
-                                  (DevResult *)D.result.ptr, st));
-    HIP_TRY(hipMemcpyAsync(D.host_result, D.result.ptr, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(LP.parts, parts.data(), n * sizeof(Partial), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_finalize_batch(LP.parts, LP.firsts, LP.counts, LP.args, (uint32_t)n, LP.res, st));
+    HIP_TRY(hipMemcpyAsync(D.host_result, LP.res, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::vector<sim_zomega> res(n);
     for (size_t i = 0; i < n; ++i) {
@@ -1265,6 +1391,186 @@ int sim_batch_plan_run(sim_batch_plan *plan, void *stream, sim_zomega *out) {
         if (rc) return rc;
     }
     for (size_t i = 0; i < plan->n; ++i) out[i] = res[i];
+    return SIM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ caller-owned scratch
+
+namespace {
+
+// a batch whose work layout sim_batch_prepare wrote into caller memory, by (device, address)
+struct Prepared {
+    uint64_t fp = 0;
+    size_t n = 0;
+    BatchLayout L;  // without its work items (they are on the device)
+    BatchPlan B;
+};
+std::map<std::pair<int, uintptr_t>, Prepared> g_prepared;  // each device's entries under its lock
+
+uint64_t batch_fingerprint(int dev, const sim_program *const *ps, size_t n, const sim_tuning *t) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xFFu;
+            h *= 0x100000001b3ull;
+        }
+    };
+    mix((uint64_t)dev);
+    mix(n);
+    for (size_t i = 0; i < n; ++i) {
+        mix((uint64_t)(uintptr_t)ps[i]);
+        mix((uint64_t)(uintptr_t)ps[i]->dimg);
+    }
+    const sim_tuning z = {0, 0, 0, 0};
+    const sim_tuning &u = t ? *t : z;
+    mix(((uint64_t)u.block_threads << 32) | u.blocks_per_cu);
+    mix(((uint64_t)u.walk_bits << 32) | u.chunk_log2);
+    return h;
+}
+
+// the single-program and batch needs of a set of programs (device lock held)
+int scratch_need(DeviceState &D, const sim_program *const *ps, size_t n, const sim_tuning *t, size_t *need) {
+    size_t m = up256(sizeof(Partial)) + up256(sizeof(DevResult));  // sim_finalize-sized calls
+    for (size_t i = 0; i < n; ++i) {
+        if (ps[i]->pk.zero) continue;
+        SinglePlan S;
+        int rc = plan_single(D, ps[i], ps[i]->pk.n_slices, t, &S);
+        if (rc) return rc;
+        m = std::max(m, S.total);
+    }
+    BatchLayout L;
+    int rc = build_layout(D, ps, n, nullptr, nullptr, false, t, &L);
+    if (rc) return rc;
+    m = std::max(m, plan_batch(L, n, true).total);
+    *need = m;
+    return SIM_OK;
+}
+
+// one program in caller memory: [first, first + count) in slices
+int eval_single_ws(const sim_program *P, uint64_t first, uint64_t count, bool raw, void *stream, void *dev_scratch,
+                   size_t scratch_bytes, sim_zomega *out) {
+    if (P->pk.zero || count == 0) {
+        zero_result(out, raw);
+        return SIM_OK;
+    }
+    DeviceState *D;
+    int rc = enter_device(P, &D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(D->mu);
+    SinglePlan S;
+    Region R;
+    if ((rc = plan_single(*D, P, count, nullptr, &S))) return rc;
+    if ((rc = caller_region(dev_scratch, scratch_bytes, S.total, &R))) return rc;
+    return eval_single(P, first, count, raw, S, R, nullptr, (hipStream_t)stream, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_scratch_bytes(const sim_program *const *ps, size_t n, const sim_tuning *t, size_t *bytes) {
+    if (!bytes) return fail(SIM_EINVAL, "null argument");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    size_t need = 0;
+    if ((rc = scratch_need(D, ps, n, t, &need))) return rc;
+    *bytes = need;
+    return SIM_OK;
+}
+
+int sim_eval_amplitude_ws(const sim_program *P, void *stream, void *dev_scratch, size_t scratch_bytes,
+                          sim_zomega *out) {
+    if (!P || !out) return fail(SIM_EINVAL, "null argument");
+    return eval_single_ws(P, 0, P->pk.n_slices, false, stream, dev_scratch, scratch_bytes, out);
+}
+
+int sim_eval_range_ws(const sim_program *P, uint64_t first, uint64_t count, uint32_t g, void *stream,
+                      void *dev_scratch, size_t scratch_bytes, sim_zomega *raw) {
+    if (!P || !raw) return fail(SIM_EINVAL, "null argument");
+    const uint32_t wb = (uint32_t)P->pk.walk_bits;
+    if (g < wb || g > (uint32_t)P->pk.p)
+        return fail(SIM_EINVAL, "g must lie between the program's walk bits (" + std::to_string(wb) + ") and p (" +
+                                    std::to_string(P->pk.p) + ")");
+    const uint32_t sh = g - wb;  // slices per unit: 2^sh
+    const uint64_t units = P->pk.n_slices >> sh;
+    if (first > units || count > units - first) return fail(SIM_EINVAL, "range outside the program");
+    return eval_single_ws(P, first << sh, count << sh, true, stream, dev_scratch, scratch_bytes, raw);
+}
+
+int sim_eval_batch_ws(const sim_program *const *ps, size_t n, void *stream, void *dev_scratch, size_t scratch_bytes,
+                      const sim_tuning *t, sim_zomega *out) {
+    if (n && !out) return fail(SIM_EINVAL, "null output");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    Region R;
+    if ((rc = caller_region(dev_scratch, scratch_bytes, 0, &R))) return rc;
+    return run_batch_locked(D, ps, n, nullptr, nullptr, false, (hipStream_t)stream, t, &R, out);
+}
+
+int sim_batch_prepare(const sim_program *const *ps, size_t n, const sim_tuning *t, void *dev_scratch,
+                      size_t scratch_bytes, void *stream) {
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    Prepared Pr;
+    Pr.n = n;
+    if ((rc = build_layout(D, ps, n, nullptr, nullptr, false, t, &Pr.L))) return rc;
+    Pr.B = plan_batch(Pr.L, n, false);
+    Region R;
+    if ((rc = caller_region(dev_scratch, scratch_bytes, Pr.B.total, &R))) return rc;
+    // the auxiliary streams of concurrent kernel variants exist before any capture
+    if ((rc = ensure_aux(D))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<char> keep;
+    if ((rc = upload_stage(D, Pr.L, n, Pr.B, R, false, st, &keep))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    Pr.L.items.clear();
+    Pr.L.items.shrink_to_fit();
+    Pr.fp = batch_fingerprint(dev, ps, n, t);
+    g_prepared[{dev, reinterpret_cast<uintptr_t>(dev_scratch)}] = std::move(Pr);
+    return SIM_OK;
+}
+
+int sim_enqueue_batch(const sim_program *const *ps, size_t n, void *stream, void *dev_scratch, size_t scratch_bytes,
+                      const sim_tuning *t, sim_zomega *dev_out) {
+    if (n && !dev_out) return fail(SIM_EINVAL, "null dev_out");
+    if (reinterpret_cast<uintptr_t>(dev_out) % 8) return fail(SIM_EINVAL, "dev_out must be 8-byte aligned");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    auto it = g_prepared.find({dev, reinterpret_cast<uintptr_t>(dev_scratch)});
+    if (it == g_prepared.end() || it->second.fp != batch_fingerprint(dev, ps, n, t))
+        return fail(SIM_EINVAL, "dev_scratch does not hold this batch: call sim_batch_prepare with the same "
+                                "programs and tuning first");
+    const Prepared &Pr = it->second;
+    Region R;
+    if ((rc = caller_region(dev_scratch, scratch_bytes, Pr.B.total, &R))) return rc;
+    if (!n) return SIM_OK;
+    const LayoutPtrs LP = layout_ptrs(Pr.B, R, false);
+    return enqueue_batch(D, Pr.L, n, t, (hipStream_t)stream, LP.hdrs, LP.imgs, LP.items, LP.parts, LP.firsts,
+                         LP.counts, LP.args, reinterpret_cast<DevResult *>(dev_out));
+}
+
+int sim_batch_forget(void *dev_scratch) {
+    int dev;
+    HIP_TRY(hipGetDevice(&dev));
+    int rc = init_device(dev);
+    if (rc) return rc;
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    g_prepared.erase({dev, reinterpret_cast<uintptr_t>(dev_scratch)});
     return SIM_OK;
 }
 

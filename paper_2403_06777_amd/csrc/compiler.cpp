@@ -34,7 +34,7 @@
 //    qubits, the doubled diagram of Fig. 3 right) does the same with the projector
 //    |y_i><y_i| on each measured qubit: the effect <y_i| and a fresh spider z_i held equal to
 //    y_i by a second polar effect, so the first k outcomes are the program's parameters
-//    (the repeated weak simulation of Appendix E).
+//    (the repeated weak simulation of Appendix F).
 // The scalar is tracked exactly in Z[w] with a power of sqrt2 throughout.
 
 #include "compiler.h"

@@ -232,7 +232,7 @@ def _prefix_value(o2, ir, prefix):
 
 
 def test_prefix_programs_equal_exact_marginals(o2):
-    # the doubled diagram with the first k outcomes as parameters (Fig. 3 right, Appendix E):
+    # the doubled diagram with the first k outcomes as parameters (Fig. 3 right, Appendix F):
     # every prefix of every length equals the exact marginal of the state vector, and the
     # program compiled for one fixed prefix gives the same value
     for seed in range(6):
