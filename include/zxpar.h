@@ -209,7 +209,9 @@ SIM_API int sim_eval_timed(const sim_program *prog, void *stream, sim_zomega *ou
 
 /* Raw partial sum over slices [first_slice, first_slice + n_slices) (flags = RAW): for
  * checkpoint/resume and sharding.  Partials over disjoint slices add exactly; finish with
- * sim_finalize. */
+ * sim_finalize.  "Raw" leaves out the packed program's constant: the IR's scalar times the
+ * factors that the packer folds into it (factors on constant forms, factors whose two values
+ * coincide, cancelling node pairs), so only finalised values compare with the IR's terms. */
 SIM_API int sim_eval_range(const sim_program *prog, uint64_t first_slice, uint64_t n_slices,
                    void *stream, sim_zomega *raw);
 
