@@ -345,6 +345,19 @@ SIM_API int sim_enqueue_batch(const sim_program *const *progs, size_t n, void *s
 /* Drops the host-side record of a region prepared on the current device (no-op if none). */
 SIM_API int sim_batch_forget(void *dev_scratch);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): sim_eval_ranges with the work layout, partials and results in a fixed array of
+ * 4 MiB per device (a file-scope device array, its address taken once per device at set-up).
+ * It calls no hipMalloc, hipFree or hipHostMalloc and creates no stream: every launch goes to
+ * `stream`, and the layout and results move through pageable host copies.  The array keeps the
+ * last call's contents; nothing in it has to start at zero.  Calls on one device share the
+ * array: the device lock serialises them and each waits for its stream before returning, so
+ * they take turns rather than overlap.  SIM_ERANGE (message: the bytes needed) when the batch
+ * needs more than the array holds; other errors as sim_eval_ranges. */
+SIM_API int sim_eval_ranges_static(const sim_program *const *progs, const uint64_t *first_slice,
+                                   const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
+                                   sim_zomega *raw);
+
 /* sim_finalize for n programs in one launch: out[i] = finalised raws[i] of progs[i]. */
 SIM_API int sim_finalize_batch(const sim_program *const *progs, const sim_zomega *raws, size_t n,
                                void *stream, sim_zomega *out);

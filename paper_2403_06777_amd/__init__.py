@@ -33,6 +33,7 @@ from .binding import (  # noqa: F401
     sim_eval_timed,
     sim_eval_outcomes,
     sim_eval_ranges,
+    sim_eval_ranges_static,
     sim_finalize,
     sim_finalize_batch,
     sim_init,

@@ -127,6 +127,9 @@ SIGNATURES = [
     ("sim_eval_ranges", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                        ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_eval_ranges_static", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
+                                              ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
+                                              ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
     ("sim_finalize_batch", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(sim_zomega), ctypes.c_size_t, _P,
                                           ctypes.POINTER(sim_zomega)]),
     ("sim_raw_add", ctypes.c_int, [ctypes.POINTER(sim_zomega), ctypes.POINTER(sim_zomega),
@@ -379,6 +382,18 @@ def sim_eval_ranges(progs: Sequence[int], first_slices: Sequence[int], n_slices:
     counts = (ctypes.c_uint64 * max(1, n))(*n_slices)
     outs = (sim_zomega * max(1, n))()
     _check(lib().sim_eval_ranges(_prog_array(progs), firsts, counts, n, _stream(stream), _tuning(tuning), outs))
+    return [outs[i].coeffs() for i in range(n)]
+
+
+def sim_eval_ranges_static(progs: Sequence[int], first_slices: Sequence[int], n_slices: Sequence[int],
+                           stream=None, tuning: Optional[dict] = None):
+    """sim_eval_ranges in the library's fixed 4 MiB device array (no allocation)"""
+    n = len(progs)
+    firsts = (ctypes.c_uint64 * max(1, n))(*first_slices)
+    counts = (ctypes.c_uint64 * max(1, n))(*n_slices)
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_eval_ranges_static(_prog_array(progs), firsts, counts, n, _stream(stream), _tuning(tuning),
+                                        outs))
     return [outs[i].coeffs() for i in range(n)]
 
 

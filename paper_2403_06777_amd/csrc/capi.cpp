@@ -63,6 +63,7 @@ struct DeviceState {
     int cus = 0;
     std::mutex mu;
     DevBuf ws;                    // the library's scratch region
+    void *static_scratch = nullptr;  // this device's address of the fixed array (kStaticScratchBytes)
     void *host_result = nullptr;  // pinned
     size_t host_cap = 0;
     void *host_stage = nullptr;   // pinned staging of batch layouts
@@ -135,6 +136,10 @@ int init_device(int dev) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     D.cus = prop.multiProcessorCount;
+    // this device's copy of the allocation-free entry point's array
+    void *sp = nullptr;
+    HIP_TRY(static_scratch_address(&sp));
+    D.static_scratch = sp;
     D.ready = true;
     return SIM_OK;
 }
@@ -763,12 +768,13 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
 int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuning *t, hipStream_t stream,
                   const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items,
                   Partial *d_parts, const uint32_t *d_firsts, const uint32_t *d_counts, const FinalArgs *d_args,
-                  DevResult *d_out) {
+                  DevResult *d_out, bool allow_fork = true) {
     const uint32_t threads = pick_threads(t);
     const size_t ng = L.groups.size();
     // kernel variants run concurrently: group k on auxiliary stream k % kAux, forked from and
-    // joined back into `stream` with events (also valid under stream capture)
-    const bool fork = ng > 1 || (ng > 0 && !L.big.empty());
+    // joined back into `stream` with events (also valid under stream capture); without
+    // allow_fork every launch goes to `stream`
+    const bool fork = allow_fork && (ng > 1 || (ng > 0 && !L.big.empty()));
     if (fork) {
         int rc = ensure_aux(D);
         if (rc) return rc;
@@ -908,7 +914,7 @@ int check_ranges(const sim_program *const *ps, size_t n, const uint64_t *first, 
 // held.
 int run_batch_locked(DeviceState &D, const sim_program *const *ps, size_t n, const uint64_t *first,
                      const uint64_t *count, bool raw, hipStream_t st, const sim_tuning *t, const Region *given,
-                     sim_zomega *out) {
+                     sim_zomega *out, bool allow_fork = true) {
     int rc;
     BatchLayout L;
     if ((rc = build_layout(D, ps, n, first, count, raw, t, &L))) return rc;
@@ -931,7 +937,7 @@ int run_batch_locked(DeviceState &D, const sim_program *const *ps, size_t n, con
         if ((rc = upload_stage(D, L, n, B, R, lib, st, &keep))) return rc;
         const LayoutPtrs LP = layout_ptrs(B, R, true);
         if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items, LP.parts, LP.firsts, LP.counts, LP.args,
-                                LP.res)))
+                                LP.res, allow_fork)))
             return rc;
         HIP_TRY(hipMemcpyAsync(hres, LP.res, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
     }
@@ -1575,3 +1581,25 @@ int sim_batch_forget(void *dev_scratch) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free entry point
+
+extern "C" int sim_eval_ranges_static(const sim_program *const *ps, const uint64_t *first_slice,
+                                      const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
+                                      sim_zomega *raw) {
+    if (n && (!raw || !first_slice || !n_slices)) return fail(SIM_EINVAL, "null argument");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    if ((rc = check_ranges(ps, n, first_slice, n_slices))) return rc;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    if (!D.static_scratch) return fail(SIM_EDEVICE, "the fixed scratch array has no address on this device");
+    // the device lock serialises calls, and each waits for its stream before returning, so the
+    // array is used by one call at a time
+    std::lock_guard<std::mutex> lk(D.mu);
+    Region R;
+    R.base = (char *)D.static_scratch;
+    R.cap = kStaticScratchBytes;
+    // every launch on the caller's stream: no auxiliary streams are created
+    return run_batch_locked(D, ps, n, first_slice, n_slices, true, (hipStream_t)stream, t, &R, raw, false);
+}

@@ -54,6 +54,11 @@ hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item
                                  const uint32_t *d_item_count, const FinalArgs *d_args, uint32_t n_progs,
                                  DevResult *d_out, hipStream_t stream);
 
+// bytes of the file-scope device array of the allocation-free entry point, and its address on
+// the current device (called once per device with that device current)
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+hipError_t static_scratch_address(void **ptr);
+
 // resident blocks per compute unit of the single-program evaluation kernel of H
 hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
 

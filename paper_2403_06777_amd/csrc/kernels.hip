@@ -150,3 +150,12 @@ hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item
                        d_item_first, d_item_count, d_args, d_out);
     return hipGetLastError();
 }
+
+// Fixed device scratch of the allocation-free entry point (sim_eval_ranges_static): one copy per
+// device, held until the process ends.  Host code never passes this name to a kernel: it is a
+// host-side stand-in; static_scratch_address gives each device's own address.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(void **ptr) {
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
