@@ -136,6 +136,13 @@ typedef struct {
     uint32_t vanish_table_bits; /* z > 0: the vanishing factors own the low z bits of the form
                                vector and a block's surviving terms are read from a 2^z-entry
                                table; 0: found by the reduced-basis test (or nothing vanishes) */
+    uint32_t n_params_given;  /* parameters of the program as given (before the elimination) */
+    uint32_t n_eliminated;    /* parameters solved for by the exact elimination of the vanishing
+                                 conditions: n_params = n_params_given - n_eliminated, and the
+                                 2^n_params terms summed are exactly the nonzero ones' subspace */
+    uint32_t n_form_monomials; /* phase monomials that the elimination turned into products of
+                                 two or three affine forms */
+    uint32_t n_mono_forms;    /* distinct forms of those products (at most 32) */
 } sim_info;
 
 /* launch shape of the evaluation kernels; zero fields take the library's choice */
@@ -168,6 +175,13 @@ SIM_API int sim_init(int device);
  * exceed int128. */
 SIM_API int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out);
 
+/* sim_program_from_ir with flags: SIM_IR_KEEP_VANISHING keeps the factors that can vanish as
+ * factors tested at run time instead of solving their conditions exactly (the default packs
+ * the sum over the surviving affine subspace only; see sim_info.n_eliminated).  Same value
+ * either way.  SIM_EINVAL on unknown flags. */
+#define SIM_IR_KEEP_VANISHING 1u
+SIM_API int sim_program_from_ir_flags(const char *ir_text, size_t len, uint32_t flags, sim_program **out);
+
 /* Host-side compiler (Section 3): circuit text -> ZX diagram closed with |0^n> and the
  * query's effect -> parametric Clifford simplification with one Boolean parameter per
  * remaining T-like spider -> term program, uploaded like sim_program_from_ir.  opts may be
@@ -180,6 +194,14 @@ SIM_API int sim_program_info(const sim_program *prog, sim_info *out);
 /* Host only (no device needed): parses and packs an IR text and reports what
  * sim_program_from_ir would create, without uploading anything.  Same errors. */
 SIM_API int sim_ir_info(const char *ir_text, size_t len, sim_info *out);
+
+/* sim_ir_info with the flags of sim_program_from_ir_flags. */
+SIM_API int sim_ir_info_flags(const char *ir_text, size_t len, uint32_t flags, sim_info *out);
+
+/* Host only: sim_program_affine_layout of the program sim_program_from_ir would create from
+ * the IR text; *p_out receives its n_params (also when cap is too small: SIM_ERANGE). */
+SIM_API int sim_ir_affine_layout(const char *ir_text, size_t len, uint64_t *x0, uint64_t *cols, uint32_t cap,
+                                 uint32_t *p_out);
 
 /* Host only: runs the compiler of sim_compile and writes the resulting IR text into buf
  * (cap bytes, NUL-terminated; *len_out receives the full length, SIM_ERANGE if it does not
@@ -195,8 +217,19 @@ SIM_API int sim_program_ir(const sim_program *prog, char *buf, size_t cap, size_
 
 /* Assignment order of slices: slice s covers the 2^walk_bits assignments whose index, read
  * in the order perm[0..p-1] (bit j of the index is parameter perm[j]), lies in
- * [s << walk_bits, (s + 1) << walk_bits).  perm must hold p entries. */
+ * [s << walk_bits, (s + 1) << walk_bits).  perm must hold p entries.  SIM_EINVAL for a program
+ * whose vanishing conditions were eliminated (its slices are not a relabelling of the given
+ * parameters' assignments): use sim_program_affine_layout. */
 SIM_API int sim_program_layout(const sim_program *prog, int32_t *perm, uint32_t cap);
+
+/* Assignments of the slice-ordered index t (0 <= t < 2^p, p = n_params; slice s covers
+ * [s << walk_bits, (s + 1) << walk_bits)) as assignments of the n_params_given parameters of
+ * the program as given: x(t) = *x0 XOR (XOR of cols[j] over the set bits j of t), bit i of an
+ * assignment being parameter x_i.  Without elimination x0 = 0 and cols[j] = 1 << perm[j]; with
+ * it (Section 5's vanishing factors solved for exactly) x(t) runs over the affine subspace on
+ * which no factor vanishes, and every assignment outside it has a zero term.  cols must hold
+ * n_params entries (SIM_ERANGE otherwise). */
+SIM_API int sim_program_affine_layout(const sim_program *prog, uint64_t *x0, uint64_t *cols, uint32_t cap);
 
 /* The whole hot path for one program: sum over all 2^p assignments on the GPU, times the
  * constant, in canonical form. */

@@ -7,7 +7,7 @@ leg use this module.
 
 import os
 import subprocess
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 from . import zomega as zw
 
@@ -31,15 +31,20 @@ class OracleOverflow(RuntimeError):
 
 def evaluate(ir_text: str, threads: Optional[int] = None, first: Optional[int] = None,
              count: Optional[int] = None, perm: Optional[Sequence[int]] = None,
-             terms: bool = False, timeout: Optional[float] = None) -> dict:
+             terms: bool = False, timeout: Optional[float] = None,
+             points: Optional[Tuple[int, Sequence[int]]] = None) -> dict:
     """Returns {'raw': sum without scalar, 'value': (c * sum, e), 'canonical': (z, e),
-    'terms': {index: z}}."""
+    'terms': {index: z}}.  points = (x0, cols): index t is the assignment x0 ^ (xor of cols[j]
+    over the set bits j of t) instead of a relabelling of 0 .. 2^p - 1."""
     exe = build()
     args = [exe, "--threads", str(threads or os.cpu_count() or 1)]
     if first is not None or count is not None:
         args += ["--first", str(first or 0), "--count", str(count)]
     if perm is not None:
         args += ["--perm", ",".join(str(v) for v in perm)]
+    if points is not None:
+        x0, cols = points
+        args += ["--points", ",".join("%x" % v for v in [x0] + list(cols))]
     if terms:
         args.append("--terms")
     proc = subprocess.run(args, input=ir_text, capture_output=True, text=True, timeout=timeout)

@@ -31,7 +31,10 @@
  *     value <v0> <v1> <v2> <v3> <e>      c times the sum, times sqrt2^e
  *     term <x> <t0> <t1> <t2> <t3>       one line per assignment with --terms
  * Options: --threads T, --first F --count N (assignment range), --perm i0,i1,...
- * (bit j of the assignment index sets variable perm[j]; default identity), --terms.
+ * (bit j of the assignment index sets variable perm[j]; default identity), --terms,
+ * --points x0,c0,c1,..,c_{k-1} (hex; instead of --perm: index t names the assignment
+ * x0 XOR the c_j of the set bits j of t, 0 <= t < 2^k, so a range of indices is a set of
+ * points of an affine subspace; the terms are evaluated exactly as for any other index).
  */
 #include <ctype.h>
 #include <pthread.h>
@@ -361,6 +364,8 @@ static zw eval_term(const program_t *P, uint64_t x) {
 typedef struct {
     const program_t *P;
     const int *perm;
+    const uint64_t *points;  /* x0, then k columns (--points) */
+    int n_points;
     uint64_t first, count;
     int print_terms;
     zw sum;
@@ -391,7 +396,15 @@ static void *run_job(void *arg) {
     zw sum = zw_zero();
     for (uint64_t i = 0; i < J->count; i++) {
         uint64_t idx = J->first + i;
-        zw t = eval_term(J->P, index_to_assignment(J->P, J->perm, idx));
+        uint64_t x;
+        if (J->points) {
+            x = J->points[0];
+            for (int j = 0; j < J->n_points; j++)
+                if ((idx >> j) & 1) x ^= J->points[1 + j];
+        } else {
+            x = index_to_assignment(J->P, J->perm, idx);
+        }
+        zw t = eval_term(J->P, x);
         if (J->print_terms) {
             printf("term %llu", (unsigned long long)idx);
             for (int k = 0; k < 4; k++) {
@@ -409,12 +422,13 @@ static void *run_job(void *arg) {
 int main(int argc, char **argv) {
     int threads = 1, print_terms = 0, have_range = 0;
     unsigned long long first = 0, count = 0;
-    const char *perm_arg = NULL;
+    const char *perm_arg = NULL, *points_arg = NULL;
     for (int i = 1; i < argc; i++) {
         if (!strcmp(argv[i], "--threads") && i + 1 < argc) threads = atoi(argv[++i]);
         else if (!strcmp(argv[i], "--first") && i + 1 < argc) { first = strtoull(argv[++i], NULL, 10); have_range = 1; }
         else if (!strcmp(argv[i], "--count") && i + 1 < argc) { count = strtoull(argv[++i], NULL, 10); have_range = 1; }
         else if (!strcmp(argv[i], "--perm") && i + 1 < argc) perm_arg = argv[++i];
+        else if (!strcmp(argv[i], "--points") && i + 1 < argc) points_arg = argv[++i];
         else if (!strcmp(argv[i], "--terms")) print_terms = 1;
         else die("unknown option");
     }
@@ -422,7 +436,26 @@ int main(int argc, char **argv) {
     memset(&P, 0, sizeof P);
     read_program(&P);
 
-    uint64_t total = (uint64_t)1 << P.p;
+    uint64_t *points = NULL;
+    int n_points = 0;
+    if (points_arg) {
+        if (perm_arg) die("--points and --perm exclude each other");
+        points = calloc(64, sizeof(uint64_t));
+        const char *s = points_arg;
+        for (int j = 0; j < 64 && *s; j++) {
+            char *end;
+            unsigned long long v = strtoull(s, &end, 16);
+            if (end == s) die("bad --points");
+            if (P.p < 64 && (v >> P.p)) die("--points: an assignment outside the p parameters");
+            points[j] = v;
+            n_points = j;  /* columns after x0 */
+            s = end;
+            if (*s == ',') s++;
+            else if (*s) die("bad --points");
+        }
+        if (n_points > 62) die("--points: at most 62 columns");
+    }
+    uint64_t total = (uint64_t)1 << (points ? n_points : P.p);
     if (!have_range) {
         first = 0;
         count = total;
@@ -454,6 +487,8 @@ int main(int argc, char **argv) {
     for (int t = 0; t < threads; t++) {
         jobs[t].P = &P;
         jobs[t].perm = perm;
+        jobs[t].points = points;
+        jobs[t].n_points = n_points;
         jobs[t].first = at;
         jobs[t].count = per + ((uint64_t)t < extra ? 1 : 0);
         jobs[t].print_terms = print_terms;

@@ -38,13 +38,17 @@ from .binding import (  # noqa: F401
     sim_finalize_batch,
     sim_init,
     sim_ir_info,
+    sim_ir_affine_layout,
     sim_last_error,
     sim_marginal_sum,
     sim_program_free,
     sim_program_from_ir,
+    sim_program_from_ir_flags,
+    sim_ir_info_flags,
     sim_program_info,
     sim_program_ir,
     sim_program_layout,
+    sim_program_affine_layout,
     sim_raw_add,
     sim_sample,
     zomega_from_bytes,

@@ -78,7 +78,9 @@ class sim_info(ctypes.Structure):
                 ("is_zero", ctypes.c_uint32), ("compile_seconds", ctypes.c_double),
                 ("t_count", ctypes.c_uint32), ("n_constraints", ctypes.c_uint32),
                 ("ops_per_term", ctypes.c_double), ("nonzero_fraction", ctypes.c_double),
-                ("n_outer", ctypes.c_uint32), ("vanish_table_bits", ctypes.c_uint32)]
+                ("n_outer", ctypes.c_uint32), ("vanish_table_bits", ctypes.c_uint32),
+                ("n_params_given", ctypes.c_uint32), ("n_eliminated", ctypes.c_uint32),
+                ("n_form_monomials", ctypes.c_uint32), ("n_mono_forms", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -96,6 +98,10 @@ _lib = None
 SIGNATURES = [
     ("sim_init", ctypes.c_int, [ctypes.c_int]),
     ("sim_program_from_ir", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    ("sim_program_from_ir_flags", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_uint32,
+                                                 ctypes.POINTER(_P)]),
+    ("sim_ir_info_flags", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_uint32,
+                                         ctypes.POINTER(sim_info)]),
     ("sim_compile", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(sim_query),
                                    ctypes.POINTER(sim_compile_opts), ctypes.POINTER(_P)]),
     ("sim_program_info", ctypes.c_int, [_P, ctypes.POINTER(sim_info)]),
@@ -105,6 +111,11 @@ SIGNATURES = [
                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(sim_info)]),
     ("sim_program_ir", ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     ("sim_program_layout", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32]),
+    ("sim_ir_affine_layout", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64),
+                                            ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32,
+                                            ctypes.POINTER(ctypes.c_uint32)]),
+    ("sim_program_affine_layout", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64),
+                                                 ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32]),
     ("sim_eval_amplitude", ctypes.c_int, [_P, _P, ctypes.POINTER(sim_zomega)]),
     ("sim_eval_timed", ctypes.c_int, [_P, _P, ctypes.POINTER(sim_zomega), ctypes.POINTER(ctypes.c_float)]),
     ("sim_eval_range", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, _P, ctypes.POINTER(sim_zomega)]),
@@ -262,6 +273,23 @@ def sim_program_from_ir(ir_text: str) -> int:
     return h.value
 
 
+SIM_IR_KEEP_VANISHING = 1
+
+
+def sim_program_from_ir_flags(ir_text: str, flags: int) -> int:
+    data = ir_text.encode()
+    h = _P()
+    _check(lib().sim_program_from_ir_flags(data, len(data), flags, ctypes.byref(h)))
+    return h.value
+
+
+def sim_ir_info_flags(ir_text: str, flags: int) -> dict:
+    data = ir_text.encode()
+    out = sim_info()
+    _check(lib().sim_ir_info_flags(data, len(data), flags, ctypes.byref(out)))
+    return out.as_dict()
+
+
 def sim_compile(circuit_text: str, query, p_cap: int = 0, eliminate_constraints: bool = True,
                 t_spiders_only: bool = False) -> int:
     q, _keep = query
@@ -313,6 +341,25 @@ def sim_program_layout(prog: int) -> List[int]:
     arr = (ctypes.c_int32 * max(1, p))()
     _check(lib().sim_program_layout(prog, arr, p))
     return list(arr[:p])
+
+
+def sim_ir_affine_layout(ir_text: str):
+    """host only: (x0, cols) of the program the IR text packs to"""
+    data = ir_text.encode()
+    x0 = ctypes.c_uint64()
+    p = ctypes.c_uint32()
+    cols = (ctypes.c_uint64 * 64)()
+    _check(lib().sim_ir_affine_layout(data, len(data), ctypes.byref(x0), cols, 64, ctypes.byref(p)))
+    return x0.value, list(cols[:p.value])
+
+
+def sim_program_affine_layout(prog: int):
+    """(x0, cols): slice-ordered index t is the assignment x0 ^ xor of cols[j] over the bits j of t"""
+    p = sim_program_info(prog)["n_params"]
+    x0 = ctypes.c_uint64()
+    cols = (ctypes.c_uint64 * max(1, p))()
+    _check(lib().sim_program_affine_layout(prog, ctypes.byref(x0), cols, p))
+    return x0.value, list(cols[:p])
 
 
 def sim_eval_amplitude(prog: int, stream=None):

@@ -309,9 +309,9 @@ int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint
     return eval_single(P, first, count, raw, S, R, D.host_result, stream, out, kernel_ms);
 }
 
-int finish_program(std::unique_ptr<sim_program> &P, sim_program **out) {
+int finish_program(std::unique_ptr<sim_program> &P, sim_program **out, bool eliminate = true) {
     std::string err;
-    int rc = pack_program(P->ir, 12, &P->pk, &err);
+    int rc = pack_program(P->ir, 12, &P->pk, &err, eliminate);
     if (rc) return fail(rc, err);
     int dev;
     if ((rc = current_device(&dev))) return rc;
@@ -355,13 +355,18 @@ int sim_device_cus(void) {
     return g_dev[dev].cus;
 }
 
-int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out) {
+int sim_program_from_ir_flags(const char *ir_text, size_t len, uint32_t flags, sim_program **out) {
     if (!ir_text || !out) return fail(SIM_EINVAL, "null argument");
+    if (flags & ~SIM_IR_KEEP_VANISHING) return fail(SIM_EINVAL, "unknown flags");
     std::unique_ptr<sim_program> P(new (std::nothrow) sim_program());
     if (!P) return fail(SIM_ENOMEM, "out of host memory");
     std::string err;
     if (!ir_parse(ir_text, len, &P->ir, &err)) return fail(SIM_EINVAL, err);
-    return finish_program(P, out);
+    return finish_program(P, out, !(flags & SIM_IR_KEEP_VANISHING));
+}
+
+int sim_program_from_ir(const char *ir_text, size_t len, sim_program **out) {
+    return sim_program_from_ir_flags(ir_text, len, 0u, out);
 }
 
 int sim_compile(const char *circuit_text, size_t len, const sim_query *q, const sim_compile_opts *opts,
@@ -412,18 +417,43 @@ void fill_info(const PackedProgram &pk, double compile_seconds, uint32_t t_count
     out->nonzero_fraction = pk.nonzero_fraction;
     out->n_outer = (uint32_t)pk.outer;
     out->vanish_table_bits = pk.hdr.ztab_bits;
+    out->n_params_given = (uint32_t)pk.p_given;
+    out->n_eliminated = (uint32_t)pk.eliminated;
+    out->n_form_monomials = (uint32_t)pk.n_fmono;
+    out->n_mono_forms = (uint32_t)pk.n_mforms;
 }
 }  // namespace
 
-extern "C" int sim_ir_info(const char *ir_text, size_t len, sim_info *out) {
+extern "C" int sim_ir_info_flags(const char *ir_text, size_t len, uint32_t flags, sim_info *out) {
     if (!ir_text || !out) return fail(SIM_EINVAL, "null argument");
+    if (flags & ~SIM_IR_KEEP_VANISHING) return fail(SIM_EINVAL, "unknown flags");
+    IrProgram ir;
+    std::string err;
+    if (!ir_parse(ir_text, len, &ir, &err)) return fail(SIM_EINVAL, err);
+    PackedProgram pk;
+    int rc = pack_program(ir, 12, &pk, &err, !(flags & SIM_IR_KEEP_VANISHING));
+    if (rc) return fail(rc, err);
+    fill_info(pk, 0.0, 0, 0, out);
+    return SIM_OK;
+}
+
+extern "C" int sim_ir_info(const char *ir_text, size_t len, sim_info *out) {
+    return sim_ir_info_flags(ir_text, len, 0u, out);
+}
+
+extern "C" int sim_ir_affine_layout(const char *ir_text, size_t len, uint64_t *x0, uint64_t *cols, uint32_t cap,
+                                    uint32_t *p_out) {
+    if (!ir_text || !x0 || !p_out) return fail(SIM_EINVAL, "null argument");
     IrProgram ir;
     std::string err;
     if (!ir_parse(ir_text, len, &ir, &err)) return fail(SIM_EINVAL, err);
     PackedProgram pk;
     int rc = pack_program(ir, 12, &pk, &err);
     if (rc) return fail(rc, err);
-    fill_info(pk, 0.0, 0, 0, out);
+    *p_out = (uint32_t)pk.p;
+    if (cap < (uint32_t)pk.p || (!cols && pk.p)) return fail(SIM_ERANGE, "cols buffer shorter than p");
+    *x0 = pk.lay_x0;
+    for (int j = 0; j < pk.p; ++j) cols[j] = pk.lay_cols[j];
     return SIM_OK;
 }
 
@@ -480,8 +510,18 @@ int sim_program_ir(const sim_program *P, char *buf, size_t cap, size_t *len_out)
 
 int sim_program_layout(const sim_program *P, int32_t *perm, uint32_t cap) {
     if (!P || (!perm && P->pk.p)) return fail(SIM_EINVAL, "null argument");
+    if (P->pk.eliminated)
+        return fail(SIM_EINVAL, "the program's vanishing conditions were eliminated: use sim_program_affine_layout");
     if (cap < (uint32_t)P->pk.p) return fail(SIM_ERANGE, "perm buffer shorter than p");
     for (int j = 0; j < P->pk.p; ++j) perm[j] = P->pk.perm[j];
+    return SIM_OK;
+}
+
+int sim_program_affine_layout(const sim_program *P, uint64_t *x0, uint64_t *cols, uint32_t cap) {
+    if (!P || !x0 || (!cols && P->pk.p)) return fail(SIM_EINVAL, "null argument");
+    if (cap < (uint32_t)P->pk.p) return fail(SIM_ERANGE, "cols buffer shorter than p");
+    *x0 = P->pk.lay_x0;
+    for (int j = 0; j < P->pk.p; ++j) cols[j] = P->pk.lay_cols[j];
     return SIM_OK;
 }
 

@@ -173,6 +173,15 @@ struct Acc {
             a32[k] = 0;
         }
     }
+    // int64 mode with more terms than int64 holds (header flag block_flush128): a block's sums
+    // (2^KB terms of at most 2^n per coordinate, n + KB <= 62) move to int128 after the block
+    __device__ void flush128() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a128[k] += (i128)a64[k];
+            a64[k] = 0;
+        }
+    }
 };
 
 template <int W, int ACC, uint32_t SET, bool ZERO, bool B32 = false>
@@ -303,6 +312,85 @@ __device__ __forceinline__ uint32_t field_at(const uint32_t (&fv)[NF], uint32_t 
     return (uint32_t)(x >> (4 * (k & 15u))) & 7u;
 }
 
+// bit i of b (8 bits) to bit 4i
+__device__ __forceinline__ uint32_t spread8(uint32_t b) {
+    b = (b | (b << 12)) & 0x000F000Fu;
+    b = (b | (b << 6)) & 0x03030303u;
+    return (b | (b << 3)) & 0x11111111u;
+}
+
+// Adds to ft the phase of the form monomials at each of a block's 2^KB terms, as 4-bit fields
+// (field k of word k / 8).  O holds the monomials' forms at the block's first term; at step k a
+// form is its bit of O xor bit k of its lambda (the parity of its inner part at gray(k)), so a
+// monomial's values over the block are the AND of 2^KB-bit patterns, and c times that pattern is
+// added to three bit planes (a sum mod 8 in bit-sliced form) before the planes become fields.
+template <int KB, int NF>
+__device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32_t O, uint32_t (&ft)[NF]) {
+    constexpr int KW = (1 << KB) >= 32 ? (1 << KB) / 32 : 1;  // 32-bit words of a pattern
+    uint32_t c0[KW], c1[KW], c2[KW];
+#pragma unroll
+    for (int w = 0; w < KW; ++w) c0[w] = c1[w] = c2[w] = 0;
+    CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
+    for (uint32_t e = 0; e < H.n_fmono; ++e) {
+        const u32x8 E = fe[e];
+        const uint32_t h = E[0];
+        const uint32_t c = h & 7u;
+        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, (h >> 16) & 0xFFu, 1u);
+        const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, h >> 24, 1u);
+        uint32_t P[KW];
+#pragma unroll
+        for (int w = 0; w < KW; ++w) P[w] = (E[2 + w] ^ m1) & (E[4 + w] ^ m2);
+        if (((h >> 8) & 3u) == 3u) {
+            const uint32_t m3 = (uint32_t)__builtin_amdgcn_sbfe((int)O, E[1], 1u);
+#pragma unroll
+            for (int w = 0; w < KW; ++w) P[w] &= E[6 + w] ^ m3;
+        }
+        if (c & 1u) {
+#pragma unroll
+            for (int w = 0; w < KW; ++w) {
+                const uint32_t t = c0[w] & P[w];
+                c0[w] ^= P[w];
+                const uint32_t u = c1[w] & t;
+                c1[w] ^= t;
+                c2[w] ^= u;
+            }
+        }
+        if (c & 2u) {
+#pragma unroll
+            for (int w = 0; w < KW; ++w) {
+                const uint32_t t = c1[w] & P[w];
+                c1[w] ^= P[w];
+                c2[w] ^= t;
+            }
+        }
+        if (c & 4u) {
+#pragma unroll
+            for (int w = 0; w < KW; ++w) c2[w] ^= P[w];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        const int wi = (8 * j) / 32, sh = (8 * j) % 32;
+        const uint32_t f = spread8((c0[wi] >> sh) & 0xFFu) | (spread8((c1[wi] >> sh) & 0xFFu) << 1) |
+                           (spread8((c2[wi] >> sh) & 0xFFu) << 2);
+        ft[j] = field_add(ft[j], f);
+    }
+}
+
+// phase of the form monomials at one term whose forms' values are the bits of O (short walks)
+__device__ __forceinline__ int form_phase(const ImgHeader &H, CU32 *wd, uint32_t O) {
+    CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
+    int ph = 0;
+    for (uint32_t e = 0; e < H.n_fmono; ++e) {
+        const u32x8 E = fe[e];
+        const uint32_t h = E[0];
+        uint32_t v = (O >> ((h >> 16) & 0xFFu)) & (O >> (h >> 24));
+        if (((h >> 8) & 3u) == 3u) v &= O >> E[1];
+        ph += (v & 1u) ? (int)(h & 7u) : 0;
+    }
+    return ph;
+}
+
 // The blocks of a slice: 2^(g - KB) blocks of 2^KB terms.  Between blocks one
 // outer walk position flips (column XOR, phase change from the position's lists); inside a
 // block the flip positions are compile-time constants, the inner columns sit in registers and
@@ -314,8 +402,8 @@ __device__ __forceinline__ uint32_t field_at(const uint32_t (&fv)[NF], uint32_t 
 template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ, bool ZT, bool B32 = false>
 __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
                                             unsigned long long *cnt, uint64_t s, bool valid, uint32_t b0,
-                                            uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, WaveQueue *Q,
-                                            Acc<ACC> &acc) {
+                                            uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, uint32_t Sf,
+                                            WaveQueue *Q, Acc<ACC> &acc) {
     constexpr int KB = inner_bits_for(W);  // inner bits of a block
     constexpr int KS = 1 << KB;             // its terms
     constexpr int NF = KS / 8;              // words of its 4-bit phase fields
@@ -363,6 +451,12 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
         }
     }
     uint32_t gray = (b0 ^ (b0 >> 1)) << KB;  // walk bits at or above KB
+    // the outer walk parts of the form monomials' forms at the current walk state (uniform)
+    uint32_t G = 0;
+    if (MONO && H.n_fmono) {
+        CU32 *gc = wd + H.off_gcol;
+        for (uint32_t bits = gray; bits; bits &= bits - 1u) G ^= gc[__builtin_ctz(bits)];
+    }
     if (MONO && b0) {
         // inner-and-outer monomials already switched on at the start state
         CU32 *e3 = wd + H.off_c3all;
@@ -418,6 +512,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
                     dd += ((s & hm) == hm) ? (int)c : 0;
                 }
                 phi += ((gray >> i) & 1u) ? dd : -dd;
+                G ^= r[3];
                 // inner vectors of the monomials that also need outer bits: those of position i
                 // whose other outer bits are set switch on (bit i now 1) or off
                 const bool on = (gray >> i) & 1u;
@@ -603,17 +698,24 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
 #pragma unroll
             for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
         } else {
-            add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi, acc);
+            // with form monomials, their absolute phase at each term joins the block's fields
+            // (fv itself, relative to the first term, keeps carrying phi across blocks)
+            uint32_t ft[NF];
+#pragma unroll
+            for (int j = 0; j < NF; ++j) ft[j] = fv[j];
+            if (MONO && H.n_fmono) form_fields<KB, NF>(H, wd, Sf ^ G ^ ((b & 1u) ? H.gcol_top : 0u), ft);
+            add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + (MONO ? (int)(ft[0] & 7u) : 0), acc);
 #pragma unroll
             for (int k = 1; k < KS; ++k) {
                 const int j = __builtin_ctz(k);
 #pragma unroll
                 for (int w = 0; w < W; ++w) L[w] ^= ck[j][w];
-                const int f = MONO ? (int)((fv[k >> 3] >> (4 * (k & 7))) & 7u) : 0;
+                const int f = MONO ? (int)((ft[k >> 3] >> (4 * (k & 7))) & 7u) : 0;
                 add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + f, acc);
             }
         }
         if (B32) acc.flush32();
+        if (ACC == ACC_I64 && H.block_flush128) acc.flush128();
         if (MONO) phi += (int)(fv[NF - 1] >> 28);  // the block's last state
     }
 }
@@ -663,6 +765,15 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
             dal |= (uint64_t)(f & 7) << (4 * i);
         }
     }
+    // the form monomials' forms at the slice's first assignment, without their walk parts
+    uint32_t Sf = 0;
+    if (MONO && H.n_fmono) {
+        CU32 *mf = wd + H.off_mforms;
+        for (uint32_t j = 0; j < H.n_mforms; ++j) {
+            const uint64_t hm = (uint64_t)mf[4 * j] | ((uint64_t)mf[4 * j + 1] << 32);
+            Sf |= (mf[4 * j + 2] ^ (uint32_t)(__popcll(s & hm) & 1)) << j;
+        }
+    }
     if (b0) {
         // the walk starts at block b0: its first state has the walk bits of gray(b0 * 2^K)
         const uint32_t t0 = b0 << inner_bits_for(W);
@@ -686,9 +797,9 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         // the table of surviving steps or the reduced-basis test, chosen once per slice (two
         // copies of the loop, so that neither holds the other's registers)
         if (H.ztab_bits)
-            walk_blocks<W, MONO, ACC, SET, true, true, true>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q, acc);
+            walk_blocks<W, MONO, ACC, SET, true, true, true>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Sf, Q, acc);
         else
-            walk_blocks<W, MONO, ACC, SET, true, true, false>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Q,
+            walk_blocks<W, MONO, ACC, SET, true, true, false>(H, S, wd, tab, cnt, s, valid, b0, b1, L, phi, dal, Sf, Q,
                                                                acc);
         return;
     }
@@ -700,22 +811,24 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         if (!H.has_zero) {
             if (b32)
                 walk_blocks<W, MONO, ACC, SET, false, false, false, B32_OK>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi,
-                                                                           dal, Q, acc);
+                                                                           dal, Sf, Q, acc);
             else
-                walk_blocks<W, MONO, ACC, SET, false, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal,
+                walk_blocks<W, MONO, ACC, SET, false, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Sf,
                                                                     Q, acc);
         } else if (!kCompact<W>) {
             if (b32)
                 walk_blocks<W, MONO, ACC, SET, true, false, false, B32_OK>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi,
-                                                                          dal, Q, acc);
+                                                                          dal, Sf, Q, acc);
             else
-                walk_blocks<W, MONO, ACC, SET, true, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Q,
+                walk_blocks<W, MONO, ACC, SET, true, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Sf, Q,
                                                                    acc);
         }
         return;
     }
-    // short walks: one step at a time
-    add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi, acc);
+    // short walks: one step at a time (form monomials evaluated per term)
+    const bool fm = MONO && H.n_fmono;
+    uint32_t Of = Sf;
+    add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi + (fm ? form_phase(H, wd, Of) : 0), acc);
     uint32_t gray = 0;
     for (uint32_t t = 1; t < (1u << H.g); ++t) {
         const uint32_t i = (uint32_t)__builtin_ctz(t);
@@ -723,7 +836,8 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
 #pragma unroll
         for (int w = 0; w < W; ++w) L[w] ^= col[i * W + w];
         if (MONO) phi += flip_phase(H, wd, i, gray, dal, s);
-        add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi, acc);
+        if (fm) Of ^= wd[H.off_gcol + i];
+        add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi + (fm ? form_phase(H, wd, Of) : 0), acc);
     }
 }
 
@@ -793,7 +907,7 @@ template <int ACC>
 __device__ __forceinline__ void acc_to_i128(Acc<ACC> &acc, i128 (&out)[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (ACC == ACC_I64) out[k] += (i128)acc.a64[k];
+        if (ACC == ACC_I64) out[k] += (i128)acc.a64[k] + acc.a128[k];
         if (ACC == ACC_I128) out[k] += acc.a128[k];
     }
     acc.clear();

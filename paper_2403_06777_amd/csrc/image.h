@@ -155,6 +155,19 @@ struct ImgHeader {
     uint32_t n_c3all;     //   each (even[NF], odd[NF], outer walk mask, slice mask lo, hi)
     uint32_t off_monowalk;  // n_monowalk entries, 4 words: every monomial with a walk part
     uint32_t n_monowalk;    //   (c, walk mask, slice mask lo, hi)
+    // Form monomials (products of two or three affine forms, left by the exact elimination of
+    // the vanishing conditions).  Their n_mforms <= 32 distinct forms are the bits of a per-lane
+    // vector O: at the first term of a block O = S ^ G ^ (odd block ? gcol_top : 0), S the forms'
+    // constants and slice parts (per lane and slice), G their outer walk parts (uniform, xor of
+    // gcol[i] over the set walk bits i; gcol[i] is word 3 of position i's record), and at step k
+    // of the block a form is its bit of O xor bit k of its lambda.
+    uint32_t n_fmono;
+    uint32_t off_fmono;   // 8 words each: c | deg << 8 | j1 << 16 | j2 << 24, j3, lambda lo/hi x 3
+    uint32_t n_mforms;
+    uint32_t off_mforms;  // 4 words each: slice mask lo, hi, constant, 0
+    uint32_t off_gcol;    // g words: the forms containing walk position i
+    uint32_t gcol_top;    // gcol[KB - 1]: the top inner bit, set at the first term of odd blocks
+    uint32_t block_flush128;  // int64 mode: each block's sums move to int128 after the block
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
     uint32_t table_n;         // entries (value classes + one zero entry)
     int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e

@@ -27,6 +27,8 @@
 
 #include "program.h"
 
+#include <array>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -335,6 +337,201 @@ static double nonzero_fraction(const std::vector<IrForm> &forms, const std::vect
     return std::ldexp(1.0, -rank);
 }
 
+// ---- exact elimination of the vanishing conditions
+//
+// A node factor 1 + w^{a + b l(x)} with a = 4 or a + b = 4 (mod 8) is zero at one value of its
+// form (1 + w^4 = 0: the factor kills the term, Section 5), so every term that survives has
+// l(x) = keep, one affine equation over GF(2) per such factor.  Gaussian elimination solves them
+// for `rank` pivot parameters (never a query parameter; among a condition's parameters the one
+// met by the fewest monomials of degree >= 2), and substituting x_v = r_v XOR <m_v, x> (m_v over
+// the free parameters) restricts the sum to the surviving affine subspace: the 2^(p - rank)
+// assignments of the free parameters.  Forms stay affine forms (the vanishing factors' forms
+// become the constant `keep`, so they fold into the program constant); a variable monomial with
+// a pivot becomes a product of affine forms (a form monomial), or a linear term or a variable
+// monomial again when its forms reduce to one form or to plain parameters.  The sum is the same
+// number: the eliminated terms are exactly the zero ones.
+//
+// Returns false (nothing changed) when the program has no vanishing factor, has pair factors, a
+// condition involves query parameters only, or the form monomials would use more than
+// kMaxMonoForms distinct forms.
+struct Elimination {
+    int rank = 0;
+    std::vector<int> free_orig;  // new parameter j is original parameter free_orig[j]
+    uint64_t x0 = 0;             // the assignment of the given parameters at t = 0
+    std::vector<uint64_t> cols;  // ... and what new parameter j = 1 adds to it
+};
+constexpr int kMaxMonoForms = 32;
+
+static bool eliminate_vanishing(const IrProgram &ir, IrProgram *red, std::vector<IrFormMono> *fmono,
+                                Elimination *el) {
+    if (!ir.pairs.empty() || ir.p == 0) return false;
+    const int p = ir.p;
+    std::vector<std::pair<uint64_t, int>> rows;  // parity(mask & x) = rhs
+    for (const auto &n : ir.nodes) {
+        const IrForm &f = ir.forms[n.form];
+        const int v0 = mod8(n.a), v1 = mod8((long long)n.a + n.b);
+        if (f.mask == 0 || v0 == v1 || (v0 != 4 && v1 != 4)) continue;
+        const int keep = v0 == 4 ? 1 : 0;
+        rows.push_back({f.mask, keep ^ f.cst});
+    }
+    if (rows.empty()) return false;
+    std::vector<int> inc(p, 0);
+    for (const auto &m : ir.mono)
+        if (m.vars.size() >= 2)
+            for (int v : m.vars) inc[v]++;
+    const int inner_p = p - ir.outer;
+    const uint64_t eligible = inner_p >= 64 ? ~0ull : (((uint64_t)1 << inner_p) - 1);
+    std::vector<std::pair<uint64_t, int>> R;  // reduced rows: each pivot bit in its own row only
+    std::vector<int> pv;
+    bool contradiction = false;
+    for (auto r : rows) {
+        uint64_t m = r.first;
+        int rhs = r.second;
+        for (size_t i = 0; i < R.size(); ++i)
+            if (m >> pv[i] & 1) {
+                m ^= R[i].first;
+                rhs ^= R[i].second;
+            }
+        if (!m) {
+            if (rhs) contradiction = true;
+            continue;
+        }
+        const uint64_t cand = m & eligible;
+        if (!cand) return false;
+        int best = -1;
+        for (uint64_t c = cand; c; c &= c - 1) {
+            const int v = __builtin_ctzll(c);
+            if (best < 0 || inc[v] < inc[best]) best = v;
+        }
+        for (size_t i = 0; i < R.size(); ++i)
+            if (R[i].first >> best & 1) {
+                R[i].first ^= m;
+                R[i].second ^= rhs;
+            }
+        R.push_back({m, rhs});
+        pv.push_back(best);
+    }
+    *red = IrProgram();
+    *fmono = {};
+    *el = Elimination();
+    if (contradiction) {  // no assignment survives: the sum is zero
+        *red = ir;
+        red->scalar = zw_zero();
+        red->e = 0;
+        el->free_orig.resize(p);
+        for (int i = 0; i < p; ++i) {
+            el->free_orig[i] = i;
+            el->cols.push_back((uint64_t)1 << i);
+        }
+        return true;
+    }
+    uint64_t pivots = 0;
+    std::vector<IrForm> sub(p);  // each parameter as an affine form of the free parameters
+    for (int i = 0; i < p; ++i) sub[i] = IrForm{0, (uint64_t)1 << i};
+    for (size_t i = 0; i < R.size(); ++i) {
+        pivots |= (uint64_t)1 << pv[i];
+        sub[pv[i]] = IrForm{R[i].second, R[i].first & ~((uint64_t)1 << pv[i])};
+    }
+    std::vector<int> new_of(p, -1);
+    for (int i = 0; i < p; ++i)
+        if (!(pivots >> i & 1)) {
+            new_of[i] = (int)el->free_orig.size();
+            el->free_orig.push_back(i);
+        }
+    el->rank = (int)R.size();
+    for (int u : el->free_orig) {
+        uint64_t col = (uint64_t)1 << u;
+        for (size_t i = 0; i < R.size(); ++i)
+            if (sub[pv[i]].mask >> u & 1) col |= (uint64_t)1 << pv[i];
+        el->cols.push_back(col);
+    }
+    for (size_t i = 0; i < R.size(); ++i)
+        if (sub[pv[i]].cst) el->x0 |= (uint64_t)1 << pv[i];
+    auto substitute = [&](const IrForm &f) {  // over original free parameters
+        IrForm g{f.cst, f.mask & ~pivots};
+        for (uint64_t b = f.mask & pivots; b; b &= b - 1) {
+            const IrForm &s = sub[__builtin_ctzll(b)];
+            g.cst ^= s.cst;
+            g.mask ^= s.mask;
+        }
+        return g;
+    };
+    auto remap = [&](uint64_t m) {
+        uint64_t r = 0;
+        for (; m; m &= m - 1) r |= (uint64_t)1 << new_of[__builtin_ctzll(m)];
+        return r;
+    };
+    red->p = p - el->rank;
+    red->outer = ir.outer;
+    for (const auto &f : ir.forms) {
+        const IrForm g = substitute(f);
+        red->forms.push_back(IrForm{g.cst, remap(g.mask)});
+    }
+    red->nodes = ir.nodes;
+    red->lin = ir.lin;
+    red->scalar = ir.scalar;
+    red->e = ir.e;
+    std::vector<IrForm> mforms;  // distinct forms of the form monomials
+    for (const auto &m : ir.mono) {
+        bool has_pivot = false;
+        for (int v : m.vars) has_pivot = has_pivot || (pivots >> v & 1);
+        if (!has_pivot) {
+            IrMono nm{m.c, {}};
+            for (int v : m.vars) nm.vars.push_back(new_of[v]);
+            red->mono.push_back(nm);
+            continue;
+        }
+        // the product of the substituted forms, as 0/1 values: drop factors 1, stop at a factor 0,
+        // l * l = l, l * (1 xor l) = 0
+        std::vector<IrForm> fs;
+        bool zero = false;
+        for (int v : m.vars) {
+            const IrForm g = sub[v];
+            if (g.mask == 0) {
+                if (!g.cst) zero = true;
+                continue;
+            }
+            bool dup = false;
+            for (const auto &h : fs)
+                if (h.mask == g.mask) {
+                    dup = true;
+                    if (h.cst != g.cst) zero = true;
+                }
+            if (!dup) fs.push_back(g);
+        }
+        if (zero) continue;
+        if (fs.empty()) {  // the constant c: a linear term on a constant form
+            red->forms.push_back(IrForm{1, 0});
+            red->lin.push_back(IrLin{m.c, (int)red->forms.size() - 1});
+            continue;
+        }
+        if (fs.size() == 1) {
+            red->forms.push_back(IrForm{fs[0].cst, remap(fs[0].mask)});
+            red->lin.push_back(IrLin{m.c, (int)red->forms.size() - 1});
+            continue;
+        }
+        bool plain = true;
+        for (const auto &h : fs) plain = plain && h.cst == 0 && __builtin_popcountll(h.mask) == 1;
+        if (plain) {
+            IrMono nm{m.c, {}};
+            for (const auto &h : fs) nm.vars.push_back(new_of[__builtin_ctzll(h.mask)]);
+            red->mono.push_back(nm);
+            continue;
+        }
+        IrFormMono fm{m.c, {}};
+        for (const auto &h : fs) {
+            const IrForm r{h.cst, remap(h.mask)};
+            fm.forms.push_back(r);
+            bool seen = false;
+            for (const auto &q : mforms) seen = seen || (q.cst == r.cst && q.mask == r.mask);
+            if (!seen) mforms.push_back(r);
+        }
+        fmono->push_back(fm);
+    }
+    if ((int)mforms.size() > kMaxMonoForms) return false;
+    return true;
+}
+
 // Which parameters are walked, and in what order (walk position q + j for walked[j]), decides
 // the walk's per-block work on variable monomials: a monomial costs work at each flip of one
 // of its outer walk positions i >= KB, an entry of the flip list when it also needs walk bits
@@ -427,9 +624,17 @@ std::vector<int> refine_walk_order(const Work &w, int p, int q, int inner_p, std
     return walked;
 }
 
-int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err) {
+int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *out, std::string *err,
+                 bool eliminate) {
     PackedProgram &P = *out;
     P = PackedProgram();
+    IrProgram reduced;
+    std::vector<IrFormMono> fmono;
+    Elimination elim;
+    const bool eliminated = eliminate && eliminate_vanishing(ir_given, &reduced, &fmono, &elim);
+    const IrProgram &ir = eliminated ? reduced : ir_given;
+    P.p_given = ir_given.p;
+    P.eliminated = eliminated ? elim.rank : 0;
     P.p = ir.p;
     P.q = (int)ir.pairs.size();
     Work w;
@@ -583,14 +788,15 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // monomials the set-up is a few XORs per high parameter.  The kernels balance work in
     // blocks of a walk, so long walks cost no balance, but a wave holds 64 slices, so the walk
     // leaves at least 64 slices where the program is large enough.
-    const int want = w.mono.empty() ? 8 : 12;
+    const bool any_mono = !w.mono.empty() || !fmono.empty();
+    const int want = any_mono ? 12 : 8;
     const int inner_p = p - ir.outer;  // query parameters are never walked
     int g_orig = std::min(inner_p, std::min(max_walk_bits, want));
     if (p - g_orig < 6) g_orig = std::max(std::min(inner_p, kMaxInnerBits), p - 6);
     g_orig = std::min(g_orig, inner_p);
-    if (!w.mono.empty()) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
+    if (any_mono) g_orig = std::min(g_orig, std::max(0, 16 - q));  // packed 4-bit fields
     if (p - g_orig > 62) g_orig = p - 62;
-    if (!w.mono.empty() && q + g_orig > 16) {
+    if (any_mono && q + g_orig > 16) {
         *err = "too many pair factors together with variable monomials (at most 16 walk bits)";
         return SIM_ERANGE;
     }
@@ -633,6 +839,42 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
             if (m >> v & 1) r |= (uint64_t)1 << pos_of[v];
         return r;
     };
+    // slice-ordered index -> assignment of the given parameters
+    P.lay_cols.clear();
+    P.lay_x0 = eliminated ? elim.x0 : 0;
+    for (int j = 0; j < p; ++j) {
+        const int v = P.perm[j];
+        P.lay_cols.push_back(eliminated ? elim.cols[v] : (uint64_t)1 << v);
+        if (eliminated) P.perm[j] = elim.free_orig[v];
+    }
+    // Form monomials: their distinct forms are bits 0 .. n_mf - 1 of a per-lane vector O.  At the
+    // first term of a block, O = S ^ G ^ (odd block ? gcol[KB - 1] : 0): S per lane and slice (the
+    // constants and slice parts), G the outer walk parts of the current walk state (updated with
+    // gcol[i] at each flip of walk position i, wave-uniform).  At step k of the block a form is
+    // its bit of O xor lambda bit k, lambda = its inner part's parity at gray(k).
+    std::vector<IrForm> mforms;
+    std::vector<std::array<int, 3>> fm_idx;
+    for (const auto &m : fmono) {
+        std::array<int, 3> ix = {-1, -1, -1};
+        for (size_t t = 0; t < m.forms.size(); ++t) {
+            const IrForm f{m.forms[t].cst, permute(m.forms[t].mask)};
+            int j = -1;
+            for (size_t u = 0; u < mforms.size(); ++u)
+                if (mforms[u].cst == f.cst && mforms[u].mask == f.mask) j = (int)u;
+            if (j < 0) {
+                j = (int)mforms.size();
+                mforms.push_back(f);
+            }
+            ix[t] = j;
+        }
+        fm_idx.push_back(ix);
+    }
+    std::vector<uint32_t> gcol(g, 0);
+    for (size_t j = 0; j < mforms.size(); ++j)
+        for (int i = 0; i < g; ++i)
+            if (mforms[j].mask >> i & 1) gcol[i] |= 1u << j;
+    P.n_fmono = (int)fmono.size();
+    P.n_mforms = (int)mforms.size();
 
     // ---- forms actually used, in packed positions
     // every node factor owns its bit of L (so its statistic weights are single steps);
@@ -748,6 +990,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     // accumulation mode: int64 registers when the static bound allows, else per-block class
     // counters when they fit the LDS budget, else int128 registers
     uint32_t acc_mode, q_limbs;
+    bool flush128 = false;
     {
         long long emax = base[STAT_E];
         for (int f = 0; f < F; ++f)
@@ -758,7 +1001,12 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         const long long bound_bits = (long long)w.nodes.size() + w.pe;
         const size_t class_bytes = (size_t)nd * 16 * q_limbs * 8;
         if (bound_bits <= 62) acc_mode = ACC_I64;
-        else if (class_bytes <= 48 * 1024) acc_mode = ACC_CLASS;
+        // a block's 2^KB terms sum below 2^(nodes + KB) per coordinate: int64 within a block,
+        // moved to int128 after it (walks of whole blocks without vanishing factors)
+        else if (!has_zero && g >= KB && (long long)w.nodes.size() + KB <= 62) {
+            acc_mode = ACC_I64;
+            flush128 = true;
+        } else if (class_bytes <= 48 * 1024) acc_mode = ACC_CLASS;
         else acc_mode = ACC_I128;
     }
     // node table: few node factors (their bits are 0 .. n-1, allocated first), W up to 8
@@ -778,7 +1026,7 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.g = (uint32_t)g;
     H.W = (uint32_t)W;
     H.has_zero = has_zero ? 1u : 0u;
-    H.has_mono = w.mono.empty() ? 0u : 1u;
+    H.has_mono = any_mono ? 1u : 0u;
     H.n_slices_lo = (uint32_t)P.n_slices;
     H.n_slices_hi = (uint32_t)(P.n_slices >> 32);
     H.off_col = (uint32_t)img.size();
@@ -1098,7 +1346,8 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     H.off_pos = (uint32_t)img.size();
     for (int i = 0; i < g; ++i) {
         const uint32_t *didx = img.data() + H.off_didx;
-        const uint32_t rec[4] = {(uint32_t)ui[i], didx[i] | (didx[i + 1] << 16), c3start[i] | (c3start[i + 1] << 16), 0};
+        const uint32_t rec[4] = {(uint32_t)ui[i], didx[i] | (didx[i + 1] << 16), c3start[i] | (c3start[i + 1] << 16),
+                                 gcol[i]};
         img.insert(img.end(), rec, rec + 4);
     }
     // for a walk that starts inside a slice: each inner-and-outer monomial once, with its whole
@@ -1117,6 +1366,50 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
         img.push_back((uint32_t)(hm >> 32));
         H.n_monowalk++;
     }
+
+    // form monomials: 8 words each (c | deg << 8 | j1 << 16 | j2 << 24, j3, and the three
+    // forms' lambda as lo, hi words; lambda holds the block's 2^KB steps, KB <= 6); the forms:
+    // 4 words each (slice mask lo, hi, constant, 0)
+    H.block_flush128 = flush128 ? 1u : 0u;
+    H.n_fmono = (uint32_t)fmono.size();
+    H.n_mforms = (uint32_t)mforms.size();
+    H.gcol_top = g >= KB && KB > 0 ? gcol[KB - 1] : 0u;
+    while (img.size() % 8) img.push_back(0);
+    H.off_fmono = (uint32_t)img.size();
+    {
+        auto lambda = [&](const IrForm &f) {
+            uint64_t lam = 0;
+            if (g >= KB)
+                for (int k = 0; k < KS; ++k) {
+                    const uint64_t y = (uint64_t)(k ^ (k >> 1));
+                    if (__builtin_popcountll(f.mask & y & (((uint64_t)1 << KB) - 1)) & 1) lam |= (uint64_t)1 << k;
+                }
+            return lam;
+        };
+        for (size_t e = 0; e < fmono.size(); ++e) {
+            const auto &ix = fm_idx[e];
+            const int deg = ix[2] >= 0 ? 3 : 2;
+            uint32_t ent[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            ent[0] = (uint32_t)mod8(fmono[e].c) | ((uint32_t)deg << 8) | ((uint32_t)ix[0] << 16) | ((uint32_t)ix[1] << 24);
+            ent[1] = deg == 3 ? (uint32_t)ix[2] : 0u;
+            for (int t = 0; t < deg; ++t) {
+                const uint64_t lam = lambda(mforms[ix[t]]);
+                ent[2 + 2 * t] = (uint32_t)lam;
+                ent[3 + 2 * t] = (uint32_t)(lam >> 32);
+            }
+            img.insert(img.end(), ent, ent + 8);
+        }
+    }
+    H.off_mforms = (uint32_t)img.size();
+    for (const auto &f : mforms) {
+        const uint64_t hm = g >= 64 ? 0 : f.mask >> g;
+        img.push_back((uint32_t)hm);
+        img.push_back((uint32_t)(hm >> 32));
+        img.push_back((uint32_t)f.cst);
+        img.push_back(0u);
+    }
+    H.off_gcol = (uint32_t)img.size();
+    img.insert(img.end(), gcol.begin(), gcol.end());
 
     // ---- value table
     H.d_off = (int32_t)(-dmin);
@@ -1259,11 +1552,17 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
     //  * shorter walks: per term the column XOR (W), the vanishing test (2W) and the flip
     //    (5 plus 5 per firing slice-dependent entry);
     //  * per slice: the high parameters into L (2W each), 5 per slice-dependent monomial entry,
-    //    4 per walk position for the packed always-firing fields, 4 + 4 NF per inner-vector entry.
+    //    4 per walk position for the packed always-firing fields, 4 + 4 NF per inner-vector entry,
+    //    5 per form of the form monomials (its bit of S);
+    //  * form monomials, per block: O (1); per monomial a bit extract and KW XORs per form (KW =
+    //    words of a block's 2^KB-bit pattern), KW ANDs per further form, and the add of c times the
+    //    pattern to three bit planes (5, 3, 1 KW for the bits of c); the planes to 4-bit fields (23
+    //    per field word) and their add (2 per field word).  Shorter walks: per term O (1) and 5 per
+    //    monomial.  Blocks moved from int64 to int128 sums: 16 per block.
     {
         const double nz = nonzero_fraction(used, w.nodes);
         P.nonzero_fraction = nz;
-        const bool mono = !w.mono.empty();
+        const bool mono = any_mono;
         const bool blocks = g >= KB;
         const bool compact = blocks && has_zero && W <= 4;
         // the slot set of the kernel variant the program is dispatched to (int128 mode: all)
@@ -1322,6 +1621,20 @@ int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std
                 }
             }
         }
+        const double KW = KS >= 32 ? KS / 32.0 : 1.0;
+        double fm_block = 0;
+        if (!fmono.empty()) {
+            fm_block = 1 + NF * (23.0 + 2.0);
+            for (size_t e = 0; e < fmono.size(); ++e) {
+                const int deg = fm_idx[e][2] >= 0 ? 3 : 2;
+                const int c = mod8(fmono[e].c);
+                fm_block += deg * (1 + KW) + (deg - 1) * KW + ((c & 1) ? 5 : 0) * KW + ((c & 2) ? 3 : 0) * KW +
+                            ((c & 4) ? 1 : 0) * KW;
+            }
+            setup += 5.0 * mforms.size();
+        }
+        if (blocks) walk += (double)(steps >> KB) * (fm_block + (flush128 ? 16.0 : 0.0));
+        else if (!fmono.empty()) ops += 1 + 5.0 * fmono.size();
         P.ops_per_term = ops + (setup + walk) / (double)steps;
     }
 

@@ -40,6 +40,14 @@ struct IrProgram {
     int32_t e = 0;
 };
 
+// A product of affine forms with a Z/8 coefficient: phi += c * l_1(x) ... l_d(x) (d = 2 or 3).
+// Variable monomials become such products when the exact elimination of the vanishing
+// conditions substitutes an affine form for a parameter; they never appear in IR text.
+struct IrFormMono {
+    int c;
+    std::vector<IrForm> forms;
+};
+
 bool ir_parse(const char *text, size_t len, IrProgram *out, std::string *err);
 std::string ir_print(const IrProgram &prog);
 
@@ -59,10 +67,22 @@ struct PackedProgram {
     int W = 1;
     double ops_per_term = 0.0;  // algorithmic int32 lane-ops per term (see pack_program)
     double nonzero_fraction = 1.0;  // exact fraction of assignments where no factor vanishes
+    // exact elimination of the vanishing conditions (pack_program): the program as given has
+    // p_given parameters; `eliminated` of them were solved for, so the kernel sums over the
+    // 2^p (p = p_given - eliminated) surviving assignments x = x0 XOR sum_j t_j cols[j], t the
+    // slice-ordered index (cols and x0 are assignments of the given parameters)
+    int p_given = 0;
+    int eliminated = 0;
+    uint64_t lay_x0 = 0;
+    std::vector<uint64_t> lay_cols;
+    int n_fmono = 0, n_mforms = 0;
 };
 
 // Returns 0 or a negative SIM_E* code with *err set.  max_walk_bits caps the Gray walk.
-int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err);
+// eliminate: solve the vanishing conditions exactly (see eliminate_vanishing in the packer);
+// false keeps them as factors tested at run time
+int pack_program(const IrProgram &ir, int max_walk_bits, PackedProgram *out, std::string *err,
+                 bool eliminate = true);
 
 // exact value of one table entry: w^r * sqrt2^e * (1 + w)^d (d >= 0) or (1 + w^3)^(-d)
 Zw table_value(int d, int r, int e);

@@ -50,22 +50,26 @@ def wide_vanishing_program(seed, p=24, n_vanish=36, basis=6):
 
 
 def test_vanishing_step_table_is_reported():
-    # vanishing factors whose bits all lie in word 0 use the table of surviving steps (the
-    # kernel-sized programs: 11 and 12 of them); more than 32 use the reduced-basis test;
-    # programs without vanishing factors report 0
-    assert zx.sim_ir_info(wl.kernel_sized_program(0).to_text())["vanish_table_bits"] == 11
-    assert zx.sim_ir_info(wl.kernel_sized_program(1).to_text())["vanish_table_bits"] == 12
-    assert zx.sim_ir_info(wide_vanishing_program(0).to_text())["vanish_table_bits"] == 0
+    # kept at run time, vanishing factors whose bits all lie in word 0 use the table of
+    # surviving steps (the kernel-sized programs: 11 and 12 of them); more than 32 use the
+    # reduced-basis test; programs without vanishing factors report 0
+    keep = zx.binding.SIM_IR_KEEP_VANISHING
+    assert zx.sim_ir_info_flags(wl.kernel_sized_program(0).to_text(), keep)["vanish_table_bits"] == 11
+    assert zx.sim_ir_info_flags(wl.kernel_sized_program(1).to_text(), keep)["vanish_table_bits"] == 12
+    assert zx.sim_ir_info_flags(wide_vanishing_program(0).to_text(), keep)["vanish_table_bits"] == 0
     assert zx.sim_ir_info(wl.random_program(0, 10, n_nodes=0, n_lin=8).to_text())["vanish_table_bits"] == 0
 
 
 def test_ir_info_kernel_sized():
     prog = wl.kernel_sized_program(0)
-    info = zx.sim_ir_info(prog.to_text())
+    info = zx.sim_ir_info_flags(prog.to_text(), zx.binding.SIM_IR_KEEP_VANISHING)
     assert info["n_params"] == 32
     assert info["n_factors"] == 64
     assert info["n_monomials"] == len(prog.mono)
     assert info["n_slices"] << info["walk_bits"] == 1 << 32
+    info = zx.sim_ir_info(prog.to_text())  # the 11 vanishing factors solved for
+    assert info["n_params"] == 21 and info["n_factors"] == 53
+    assert info["n_slices"] << info["walk_bits"] == 1 << 21
 
 
 @pytest.mark.parametrize("text,frag", [
@@ -92,7 +96,21 @@ def test_error_names_line():
 
 
 def test_static_bound_refuses_overflow():
+    # 80 node factors over 60 parameters: the bound 2^(factors + p) exceeds int128 with the 12
+    # vanishing factors kept; solved for, 68 factors and parameters go and the program fits
     prog = wl.random_program(0, 60, n_nodes=80, general_ab=False)
+    with pytest.raises(zx.SimError) as ei:
+        zx.sim_ir_info_flags(prog.to_text(), binding.SIM_IR_KEEP_VANISHING)
+    assert ei.value.code == binding.SIM_ERANGE
+    info = zx.sim_ir_info(prog.to_text())
+    assert info["n_eliminated"] == 12 and info["n_params"] + info["n_factors"] <= 125
+    # no factor can vanish: 80 factors + 60 parameters > 125 is refused either way
+    from workloads.programs import ProgramSpec
+    rng = wl.SplitMix64(84, 0)
+    prog = ProgramSpec(60)
+    for _ in range(80):
+        prog.nodes.append((prog.add_form(rng.randint(0, 1), rng.randint(1, (1 << 60) - 1)), 0,
+                           rng.choice([1, 2, 3, 5, 6, 7])))
     with pytest.raises(zx.SimError) as ei:
         zx.sim_ir_info(prog.to_text())
     assert ei.value.code == binding.SIM_ERANGE
@@ -174,7 +192,8 @@ def test_weight4_phase_parts_share_one_form():
     # factor's form leave no form of their own
     for case in ("constant", "opposite", "node"):
         prog = wl.weight4_phase_program(0, 10, 2, case)
-        n_forms = zx.sim_ir_info(prog.to_text())["n_forms"]
+        # (factors that can vanish kept: solved for, their forms would fold away too)
+        n_forms = zx.sim_ir_info_flags(prog.to_text(), binding.SIM_IR_KEEP_VANISHING)["n_forms"]
         assert n_forms == len(prog.forms) - {"constant": 3, "opposite": 1, "node": 2}[case]
 
 

@@ -1,0 +1,139 @@
+"""Programs whose vanishing conditions the packer solves for exactly (needs an MI355X): the
+kernel sums over the surviving affine subspace only, with the phase monomials that met a
+solved parameter evaluated as products of affine forms.  Every value against the oracle over
+all 2^p assignments of the program as given (and the same program with the factors kept at
+run time); sampled ranges against the oracle on the same points of the subspace; the full
+p = 32 kernel-sized sums against the committed oracle goldens."""
+
+import os
+import sys
+
+import pytest
+
+import paper_2403_06777_amd as zx
+import workloads as wl
+from workloads.programs import ProgramSpec
+
+pytestmark = pytest.mark.gpu
+KEEP = zx.binding.SIM_IR_KEEP_VANISHING
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_value(text, flags=0):
+    h = zx.sim_program_from_ir_flags(text, flags)
+    try:
+        return zx.sim_eval_amplitude(h)
+    finally:
+        zx.sim_program_free(h)
+
+
+@pytest.mark.parametrize("p,factors,monos", [(8, 24, 30), (12, 40, 60), (16, 64, 120), (20, 64, 200), (22, 48, 150)])
+def test_eliminated_kernel_sized_family(o2, p, factors, monos):
+    for seed in range(3):
+        text = wl.kernel_sized_program(seed, p=p, n_factors=factors, n_monomials=monos).to_text()
+        info = zx.sim_ir_info(text)
+        say("eliminated family", p, factors, monos, seed, info["n_eliminated"], info["n_form_monomials"],
+            info["n_mono_forms"], info["walk_bits"])
+        want = o2.evaluate(text)["canonical"]
+        assert gpu_value(text) == want
+        if p <= 16:
+            assert gpu_value(text, KEEP) == want
+
+
+@pytest.mark.parametrize("factors,n_lin", [(40, 60), (40, 150), (30, 400)])
+def test_form_monomials_on_wider_form_vectors(o2, factors, n_lin):
+    # more forms (linear phase terms): 4, 8 and 16 words per form vector (blocks of 32 and 16
+    # terms)
+    prog = wl.kernel_sized_program(7, p=20, n_factors=factors, n_monomials=120)
+    rng = wl.SplitMix64(81, factors + n_lin)
+    for _ in range(n_lin):
+        f = prog.add_form(rng.randint(0, 1), rng.randint(1, (1 << 20) - 1))
+        prog.lin.append((rng.randint(1, 7), f))
+    text = prog.to_text()
+    info = zx.sim_ir_info(text)
+    say("wide forms", info["n_forms"], info["n_eliminated"], info["n_form_monomials"])
+    assert info["n_eliminated"] > 0 and info["n_form_monomials"] > 0
+    assert gpu_value(text) == o2.evaluate(text)["canonical"]
+
+
+def _many_conditions(seed, p, n_vanish, n_other, n_mono, deg=3):
+    rng = wl.SplitMix64(82, seed * 131 + p)
+    pr = ProgramSpec(p)
+    for _ in range(n_vanish):
+        pr.nodes.append((pr.add_form(rng.randint(0, 1), rng.randint(1, (1 << p) - 1)), rng.choice([0, 4]),
+                         4))
+    for _ in range(n_other):
+        pr.nodes.append((pr.add_form(rng.randint(0, 1), rng.randint(1, (1 << p) - 1)), rng.randint(0, 7),
+                         rng.choice([1, 2, 3, 5, 6, 7])))
+    pr.mono = wl.programs._random_monomials(rng, p, n_mono, deg)
+    return pr
+
+
+@pytest.mark.parametrize("p,n_vanish", [(9, 6), (11, 8), (14, 9), (16, 5)])
+def test_short_walks_and_all_form_monomials(o2, p, n_vanish):
+    # few parameters left (walks shorter than a block: form monomials per term), and programs
+    # whose every monomial meets a solved parameter
+    for seed in range(4):
+        text = _many_conditions(seed, p, n_vanish, 10, 3 * p).to_text()
+        info = zx.sim_ir_info(text)
+        say("short walks", p, n_vanish, seed, info["n_params"], info["walk_bits"], info["n_monomials"],
+            info["n_form_monomials"])
+        assert gpu_value(text) == o2.evaluate(text)["canonical"]
+
+
+def test_contradicting_conditions_on_the_gpu(o2):
+    from tests.test_elimination_cpu import _vanishing_programs
+    text = _vanishing_programs()[-1]
+    assert gpu_value(text) == ((0, 0, 0, 0), 0) == o2.evaluate(text)["canonical"]
+    for k, text in enumerate(_vanishing_programs()[:-1]):
+        say("vanishing program", k)
+        assert gpu_value(text) == o2.evaluate(text)["canonical"]
+
+
+def test_sampled_ranges_match_the_oracle_on_the_same_points(o2):
+    text = wl.kernel_sized_program(4, p=26, n_factors=64, n_monomials=200).to_text()
+    h = zx.sim_program_from_ir(text)
+    try:
+        info = zx.sim_program_info(h)
+        x0, cols = zx.sim_program_affine_layout(h)
+        wb, ns = info["walk_bits"], info["n_slices"]
+        say("ranges", info["n_params"], info["n_eliminated"], ns)
+        assert info["n_eliminated"] > 0
+        with pytest.raises(zx.SimError):
+            zx.sim_program_layout(h)
+        rng = wl.SplitMix64(83, 0)
+        for _ in range(4):
+            s0 = rng.randint(0, ns - 8)
+            raw = zx.sim_eval_range(h, s0, 8)
+            ref = o2.evaluate(text, first=s0 << wb, count=8 << wb, points=(x0, cols))["canonical"]
+            assert zx.sim_finalize(h, raw) == ref
+    finally:
+        zx.sim_program_free(h)
+
+
+def _golden(seed):
+    path = os.path.join(GOLDEN, f"kernel_sized_p32_seed{seed}.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        tok = line.split()
+        if tok and tok[0] == "canonical":
+            v = [int(t) for t in tok[1:]]
+            return tuple(v[:4]), v[4]
+    return None
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_kernel_sized_p32_equals_the_oracle_golden(seed):
+    want = _golden(seed)
+    if want is None:
+        pytest.skip("golden not written yet (tests/golden/make_kernel_sized.py)")
+    text = wl.kernel_sized_program(seed).to_text()
+    say("golden p32", seed)
+    assert gpu_value(text) == want
+    assert gpu_value(text, KEEP) == want

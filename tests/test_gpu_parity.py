@@ -20,8 +20,8 @@ def say(*args):
     sys.stdout.flush()
 
 
-def gpu_value(text):
-    h = zx.sim_program_from_ir(text)
+def gpu_value(text, flags=0):
+    h = zx.sim_program_from_ir_flags(text, flags)
     try:
         return zx.sim_eval_amplitude(h)
     finally:
@@ -122,26 +122,30 @@ def test_folded_node_pairs_keep_the_sum(o2):
         assert gpu_value(text) == oracle_value(o2, text)
 
 
+KEEP = zx.binding.SIM_IR_KEEP_VANISHING
+
+
 def test_vanishing_step_table_and_basis_paths(o2):
-    # a block's surviving steps come from the hashed table when the vanishing bits lie in word
-    # 0 (kernel-sized programs), else from the reduced-basis test (more than 32 vanishing
-    # factors); both against the oracle, exhaustively at p = 20 and 24, and on sampled slices
-    # of two p = 32 programs
+    # factors that can vanish kept at run time (SIM_IR_KEEP_VANISHING; by default they are
+    # solved for exactly): a block's surviving steps come from the hashed table when the
+    # vanishing bits lie in word 0 (kernel-sized programs), else from the reduced-basis test
+    # (more than 32 vanishing factors); both against the oracle, exhaustively at p = 20 and 24,
+    # and on sampled slices of two p = 32 programs
     from tests.test_abi_cpu import wide_vanishing_program
     for seed in range(4):
         text = wl.kernel_sized_program(seed, p=20, n_factors=64, n_monomials=200).to_text()
-        assert zx.sim_ir_info(text)["vanish_table_bits"] > 0
+        assert zx.sim_ir_info_flags(text, KEEP)["vanish_table_bits"] > 0
         say("vanishing steps, table", seed)
-        assert gpu_value(text) == oracle_value(o2, text)
+        assert gpu_value(text, KEEP) == oracle_value(o2, text)
     for seed in range(3):
         text = wide_vanishing_program(seed).to_text()
-        info = zx.sim_ir_info(text)
+        info = zx.sim_ir_info_flags(text, KEEP)
         assert info["vanish_table_bits"] == 0 and info["nonzero_fraction"] > 0
         say("vanishing steps, basis", seed, info["nonzero_fraction"])
-        assert gpu_value(text) == oracle_value(o2, text)
+        assert gpu_value(text, KEEP) == oracle_value(o2, text)
     for seed in (1, 3):
         text = wl.kernel_sized_program(seed).to_text()
-        h = zx.sim_program_from_ir(text)
+        h = zx.sim_program_from_ir_flags(text, KEEP)
         try:
             info = zx.sim_program_info(h)
             assert info["vanish_table_bits"] > 0
@@ -158,16 +162,19 @@ def test_vanishing_step_table_and_basis_paths(o2):
 
 
 def test_kernel_sized_full_size_sampled_slices(o2):
-    # p = 32: the whole sum equals the sum of range partials, and sampled ranges equal the
-    # oracle on exactly the same assignments
+    # p = 32 (2^21 surviving terms after the exact elimination): the whole sum equals the sum of
+    # range partials, and sampled ranges equal the oracle on exactly the same assignments (the
+    # points of the surviving subspace that the slices cover; compared finalised, since the
+    # vanishing factors, constant on the subspace, are in the packed constant)
     prog = wl.kernel_sized_program(0)
     text = prog.to_text()
     h = zx.sim_program_from_ir(text)
     try:
         info = zx.sim_program_info(h)
-        perm = zx.sim_program_layout(h)
+        x0, cols = zx.sim_program_affine_layout(h)
         wb, ns = info["walk_bits"], info["n_slices"]
         say("full size", info)
+        assert info["n_eliminated"] == 11 and info["n_params"] == 21
         whole = zx.sim_eval_amplitude(h)
         parts = (0, 0, 0, 0)
         G = 8
@@ -179,9 +186,9 @@ def test_kernel_sized_full_size_sampled_slices(o2):
         for _ in range(4):
             s0 = rng.randint(0, ns - 16)
             raw = zx.sim_eval_range(h, s0, 16)
-            ref = o2.evaluate(text, first=s0 << wb, count=16 << wb, perm=perm)["raw"]
+            ref = o2.evaluate(text, first=s0 << wb, count=16 << wb, points=(x0, cols))["canonical"]
             say("slices", s0, raw, ref)
-            assert raw == ref
+            assert zx.sim_finalize(h, raw) == ref
     finally:
         zx.sim_program_free(h)
 

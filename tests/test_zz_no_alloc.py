@@ -44,10 +44,10 @@ def test_static_ranges_equal_ranges(o2):
         # packing, so the comparison is of finalised values)
         for h, i, f, c, w in zip(hs, infos, firsts, counts, want):
             if i["n_params"] <= 16 and i["n_slices"] > 1:
-                perm = zx.sim_program_layout(h)
+                points = zx.sim_program_affine_layout(h)
                 t = zx.sim_program_ir(h)
                 wb = i["walk_bits"]
-                ref = o2.evaluate(t, first=f << wb, count=c << wb, perm=perm)["canonical"]
+                ref = o2.evaluate(t, first=f << wb, count=c << wb, points=points)["canonical"]
                 assert zx.sim_finalize(h, w) == ref
         # second call: fewer programs, shorter ranges
         sub = [0, 3, 6]
@@ -66,10 +66,11 @@ def test_static_ranges_equal_ranges(o2):
 
 
 def test_static_ranges_refuse_what_does_not_fit():
-    # 40 programs of 2^25 terms in work items of 2^13 terms: 4096 items each, whose partials
-    # and layout (about 14 MB) exceed the fixed array
+    # 40 programs of 2^25 terms (their vanishing factors kept, so nothing is solved for) in work
+    # items of 2^13 terms: 4096 items each, whose partials and layout (about 14 MB) exceed the
+    # fixed array
     prog = wl.kernel_sized_program(6, p=25, n_factors=20, n_monomials=0)
-    h = zx.sim_program_from_ir(prog.to_text())
+    h = zx.sim_program_from_ir_flags(prog.to_text(), zx.binding.SIM_IR_KEEP_VANISHING)
     try:
         info = zx.sim_program_info(h)
         with pytest.raises(zx.SimError) as e:
