@@ -1,13 +1,17 @@
 """Benchmark of the evaluation hot path on one MI355X.
 
 One step = one whole pass of the hot path over the kernel-sized workload: the packed program
-is resident on the device, the persistent Gray-walk kernel evaluates all 2^32 terms, the
-finaliser adds the block partials, applies the constant and canonicalises, and the 72-byte
-result comes back.  Prints one JSON line.
+is resident on the device, the Gray-walk kernel evaluates its terms, the finaliser adds the
+block partials, applies the constant and canonicalises, and the device writes the exact value.
+Prints one JSON line.
 
 Workload (the kernel-sized configuration): random parametric scalar with p = 32 Boolean
 parameters, 64 factors 1 + w^{k l(x)} (k uniform in 1..7, l a random affine form of density
 0.3), and a phase polynomial of 200 random monomials of degree <= 3 with Z/8 coefficients.
+
+Counted terms: the packer solves the affine conditions of the factors that can vanish (k = 4)
+exactly and sums over the surviving subspace, so the count is 2^p' with p' = p minus the rank
+of those conditions (2^21 for seed 0), never 2^p; the CPU baseline evaluates the same points.
 """
 
 import argparse
@@ -58,23 +62,33 @@ def counter_figures() -> dict:
     return fields
 
 
-def cpu_baseline(ir_text: str, p: int, target_s: float) -> dict:
-    """The oracle (term-by-term CPU evaluator) on a bounded sample of the same program."""
+def cpu_baseline(ir_text: str, p: int, target_s: float, points=None) -> dict:
+    """The oracle (term-by-term CPU evaluator) on a bounded sample of the same counted terms:
+    the first points of the surviving subspace in slice order (points = (x0, cols)), on all
+    host threads and on one."""
     from oracle import o2
     o2.build()
     cores = os.cpu_count() or 1
-    # calibrate on a small range, then run about target_s seconds of work
-    n0 = 1 << 14
-    t0 = time.perf_counter()
-    o2.evaluate(ir_text, threads=cores, first=0, count=n0)
-    dt = max(time.perf_counter() - t0, 1e-3)
-    n = int(min(1 << p, max(n0, n0 * target_s / dt)))
-    n = max(n0, (n // n0) * n0)
-    t0 = time.perf_counter()
-    o2.evaluate(ir_text, threads=cores, first=0, count=n)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "terms/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of the 2^{p} assignments (binary order), {dt:.1f} s on {cores} threads"}
+
+    def rate(threads, seconds):
+        # calibrate on a small range, then run about `seconds` of work
+        n0 = 1 << 12
+        t0 = time.perf_counter()
+        o2.evaluate(ir_text, threads=threads, first=0, count=n0, points=points)
+        dt = max(time.perf_counter() - t0, 1e-3)
+        n = int(min(1 << p, max(n0, n0 * seconds / dt)))
+        n = max(n0, (n // n0) * n0)
+        t0 = time.perf_counter()
+        o2.evaluate(ir_text, threads=threads, first=0, count=n, points=points)
+        dt = time.perf_counter() - t0
+        return n / dt, n, dt
+
+    v, n, dt = rate(cores, target_s)
+    v1, n1, dt1 = rate(1, max(1.0, target_s / 4))
+    return {"value": v, "unit": "terms/s", "cores": cores, "kind": "oracle",
+            "single_core": v1,
+            "sample": f"first {n} of the 2^{p} counted terms (points of the surviving subspace in slice order), "
+                      f"{dt:.1f} s on {cores} threads; single core: {n1} terms in {dt1:.1f} s"}
 
 
 def progress(*args):
@@ -318,6 +332,22 @@ def batch_section(stream, p_cap: int) -> dict:
         eager_s = time.perf_counter() - t0
         if res != single or eager != single:
             raise SystemExit("batched results differ from single-launch results")
+        # the largest program of the batch alone: the roofline of a launch that fills the GPU
+        big = max(range(len(handles)), key=lambda i: ps[i])
+        binfo = zx.sim_program_info(handles[big])
+        kms = []
+        for _ in range(4):
+            val, ms = zx.sim_eval_timed(handles[big], stream)
+            if val != single[big]:
+                raise SystemExit("the largest program's timed value differs")
+            kms.append(ms)
+        kms = sorted(kms)[1:]  # the first is a warm-up
+        big_s = sum(kms) / len(kms) / 1000.0
+        big_ops = binfo["ops_per_term"] * float(1 << binfo["n_params"])
+        largest = {"p": binfo["n_params"], "terms": 1 << binfo["n_params"], "kernel_ms": big_s * 1000.0,
+                   "terms_per_s": (1 << binfo["n_params"]) / big_s, "ops_per_term": binfo["ops_per_term"],
+                   "achieved": big_ops / big_s / 1e12, "peak": ALU_PEAK_TOPS, "unit": "TOP/s (int32 lane ops)",
+                   "frac": big_ops / big_s / 1e12 / ALU_PEAK_TOPS, "bound": "alu"}
     finally:
         for h in handles:
             zx.sim_program_free(h)
@@ -334,6 +364,7 @@ def batch_section(stream, p_cap: int) -> dict:
         "latency_single_p50_s": percentile(done_at, 0.5), "latency_single_p99_s": percentile(done_at, 0.99),
         "single_call_p50_s": percentile(per_call, 0.5), "single_call_p99_s": percentile(per_call, 0.99),
         "tuning": tuning, "results_identical": True,
+        "roofline_largest_program": largest,
     }
 
 
@@ -351,21 +382,24 @@ def serve_section(stream, n_requests: int, p_cap: int) -> dict:
     mu = st.done / st.wall if st.wall > 0 else 1.0
     progress(f"serve: single-query service rate {mu:.1f}/s")
     rows = []
-    for mult in (0.25, 0.5, 1.0, 2.0, 4.0):
+    # the swept rates with a budget that holds every program, then 2x with a budget of 256 KiB
+    # (a few dozen resident programs): compiled programs wait for memory (held_for_memory)
+    for mult, budget in ((0.25, 256 << 20), (0.5, 256 << 20), (1.0, 256 << 20), (2.0, 256 << 20),
+                         (4.0, 256 << 20), (2.0, 256 << 10)):
         rate = mult * mu
         reqs = S.make_stream(pool, n_requests, rate=rate, seed=int(mult * 100))
-        srv = S.Server(backend, mem_budget=256 << 20, max_active=256, tick_terms=1 << 27, compile_workers=8)
+        srv = S.Server(backend, mem_budget=budget, max_active=256, tick_terms=1 << 27, compile_workers=8)
         try:
             a = srv.run(reqs, realtime=True).summary()
         finally:
             srv.close()
         fifo_reqs = S.make_stream(pool, n_requests, rate=rate, seed=int(mult * 100))
-        b = S.run_fifo(backend, fifo_reqs, realtime=True).summary()
+        b = S.run_fifo(backend, fifo_reqs, realtime=True, cache_budget=budget).summary()
         same = all(x.result == y.result for x, y in zip(reqs, fifo_reqs) if x.status == y.status == "done")
-        rows.append({"rate_per_s": rate, "rate_x_service": mult, "continuous": a, "fifo": b,
-                     "results_identical": same})
-        progress(f"serve: rate {rate:.1f}/s continuous p50 {a['p50_s']} p99 {a['p99_s']} | "
-                 f"fifo p50 {b['p50_s']} p99 {b['p99_s']}")
+        rows.append({"rate_per_s": rate, "rate_x_service": mult, "mem_budget_bytes": budget, "continuous": a,
+                     "fifo": b, "results_identical": same})
+        progress(f"serve: rate {rate:.1f}/s budget {budget} continuous p50 {a['p50_s']} p99 {a['p99_s']} "
+                 f"held {a['held_for_memory']} | fifo p50 {b['p50_s']} p99 {b['p99_s']}")
     return {"workload": "Poisson stream, 70% amplitudes / 30% marginals P(q=v) by doubled diagram, pool of "
                         "64 circuits (U{20..50} qubits, U{20..80} T, U{200..1000} Clifford gates)",
             "requests_per_rate": n_requests, "p_cap": p_cap, "service_rate_per_s": mu, "rates": rows}
@@ -384,7 +418,7 @@ def main():
     ap.add_argument("--no-outcomes", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-marginals", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--p-cap", type=int, default=36)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed steps, copy a device buffer of this size once (a plain copy of "
@@ -409,6 +443,7 @@ def main():
     h = zx.sim_program_from_ir(text)
     info = zx.sim_program_info(h)
     p = info["n_params"]
+    points = zx.sim_program_affine_layout(h)
     stream = torch.cuda.current_stream()
 
     ref = None
@@ -471,10 +506,15 @@ def main():
             "workload": "kernel-sized random parametric scalar: p=32 Boolean parameters, 64 factors "
                         "1+w^{k l(x)} (k uniform 1..7, affine forms of density 0.3), phase polynomial of "
                         f"200 random monomials of degree <= 3 over Z/8, seed {args.seed}",
-            "p": p,
+            "p": info["n_params_given"],
+            "p_eff": p,
+            "eliminated": info["n_eliminated"],
             "terms": int(terms),
+            "terms_counted": "2^p_eff: the assignments on which no factor vanishes (the vanishing "
+                             "conditions solved for exactly); 2^p - 2^p_eff zero terms are never formed",
             "factors": info["n_factors"],
             "monomials": info["n_monomials"],
+            "form_monomials": info["n_form_monomials"],
             "walk_bits": info["walk_bits"],
             "parallelism": "single GPU",
         },
@@ -507,7 +547,7 @@ def main():
     if not args.no_serve:
         out["serving"] = serve_section(stream, args.serve_requests, min(args.p_cap, 32))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(text, p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(text, p, args.cpu_seconds, points)
     print(json.dumps(out), flush=True)
 
 

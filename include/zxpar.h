@@ -278,6 +278,19 @@ SIM_API int sim_eval_ranges(const sim_program *const *progs, const uint64_t *fir
                     const uint64_t *n_slices, size_t n, void *stream, const sim_tuning *t,
                     sim_zomega *raw);
 
+/* One step of continuous batching (the serving loop's tick): for each request i, the raw sum
+ * of slices [first_slice[i], first_slice[i] + n_slices[i]) of progs[i] plus carry[i] (the raw
+ * sum of its earlier slices, flags RAW; carry NULL = all zero).  out[i] is that raw sum (flags
+ * RAW) when last[i] is 0, else its finalised value (the constant, the sqrt2 power, canonical
+ * form: what sim_finalize of the raw sum gives).  Work items of every request in one batch of
+ * launches, the carried sums and the finalisation in the same finaliser launch, and one wait:
+ * a request that ends in this step is answered by it.  Partial sums over disjoint slices add
+ * exactly, so a request's final value does not depend on how its slices were split into steps
+ * or which requests shared them. */
+SIM_API int sim_serve_step(const sim_program *const *progs, const uint64_t *first_slice, const uint64_t *n_slices,
+                           const sim_zomega *carry, const uint8_t *last, size_t n, void *stream,
+                           const sim_tuning *t, sim_zomega *out);
+
 /* Amplitudes of an OUTCOMES program (query kind SIM_QUERY_OUTCOMES) for n output strings:
  * bits holds n rows of n_outer bytes (0/1), row k = y_0 .. y_{n_outer-1}; out[k] =
  * <y|C|0^n> in canonical form, bit-identical to compiling and evaluating the AMPLITUDE query

@@ -51,6 +51,7 @@ from .binding import (  # noqa: F401
     sim_program_affine_layout,
     sim_raw_add,
     sim_sample,
+    sim_serve_step,
     zomega_from_bytes,
 )
 

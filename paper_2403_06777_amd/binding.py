@@ -138,6 +138,10 @@ SIGNATURES = [
     ("sim_eval_ranges", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                        ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_serve_step", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(sim_zomega),
+                                      ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t, _P,
+                                      ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
     ("sim_eval_ranges_static", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                               ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                               ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
@@ -430,6 +434,21 @@ def sim_eval_ranges(progs: Sequence[int], first_slices: Sequence[int], n_slices:
     outs = (sim_zomega * max(1, n))()
     _check(lib().sim_eval_ranges(_prog_array(progs), firsts, counts, n, _stream(stream), _tuning(tuning), outs))
     return [outs[i].coeffs() for i in range(n)]
+
+
+def sim_serve_step(progs: Sequence[int], first_slices: Sequence[int], n_slices: Sequence[int], carries,
+                   last: Sequence[bool], stream=None, tuning: Optional[dict] = None):
+    """One continuous-batching step: entry i is the raw sum (coefficients) of its slices plus
+    carries[i] when last[i] is false, else the finalised ((coefficients), e)."""
+    n = len(progs)
+    firsts = (ctypes.c_uint64 * max(1, n))(*first_slices)
+    counts = (ctypes.c_uint64 * max(1, n))(*n_slices)
+    cz = (sim_zomega * max(1, n))(*[_raw(c) for c in carries])
+    lz = (ctypes.c_uint8 * max(1, n))(*[1 if x else 0 for x in last])
+    outs = (sim_zomega * max(1, n))()
+    _check(lib().sim_serve_step(_prog_array(progs), firsts, counts, cz, lz, n, _stream(stream), _tuning(tuning),
+                                outs))
+    return [_scalar(outs[i]) if last[i] else outs[i].coeffs() for i in range(n)]
 
 
 def sim_eval_ranges_static(progs: Sequence[int], first_slices: Sequence[int], n_slices: Sequence[int],

@@ -257,6 +257,15 @@ struct SinglePlan {
 
 int plan_single(DeviceState &D, const sim_program *P, uint64_t count, const sim_tuning *t, SinglePlan *S) {
     S->threads = pick_threads(t);
+    if (!(t && t->block_threads)) {
+        // fewer work units (waves) than four per compute unit: one-wave workgroups, so that the
+        // waves spread over every compute unit instead of filling half of them
+        const ImgHeader &H = P->pk.hdr;
+        const uint32_t kb = (uint32_t)inner_bits_for(H.W);
+        const uint32_t lg_units = H.g >= kb ? H.g - kb : 0u;
+        const uint64_t units = ((count + 63) / 64) << std::min<uint32_t>(lg_units, 40);
+        if (units < 4 * (uint64_t)std::max(1, D.cus)) S->threads = 64;
+    }
     int rc = eval_grid(D, P, count, S->threads, t, &S->blocks);
     if (rc) return rc;
     S->o_res = up256((size_t)S->blocks * sizeof(Partial));
@@ -808,7 +817,7 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
 int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuning *t, hipStream_t stream,
                   const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items,
                   Partial *d_parts, const uint32_t *d_firsts, const uint32_t *d_counts, const FinalArgs *d_args,
-                  DevResult *d_out, bool allow_fork = true) {
+                  DevResult *d_out, bool allow_fork = true, const Partial *d_carry = nullptr) {
     const uint32_t threads = pick_threads(t);
     const size_t ng = L.groups.size();
     // kernel variants run concurrently: group k on auxiliary stream k % kAux, forked from and
@@ -838,7 +847,7 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
             HIP_TRY(hipStreamWaitEvent(stream, D.ev_join[a], 0));
         }
     }
-    HIP_TRY(launch_finalize_batch(d_parts, d_firsts, d_counts, d_args, (uint32_t)n, d_out, stream));
+    HIP_TRY(launch_finalize_batch(d_parts, d_firsts, d_counts, d_args, (uint32_t)n, d_out, stream, d_carry));
     return SIM_OK;
 }
 
@@ -1642,4 +1651,59 @@ extern "C" int sim_eval_ranges_static(const sim_program *const *ps, const uint64
     R.cap = kStaticScratchBytes;
     // every launch on the caller's stream: no auxiliary streams are created
     return run_batch_locked(D, ps, n, first_slice, n_slices, true, (hipStream_t)stream, t, &R, raw, false);
+}
+
+// ------------------------------------------------------------------ serving step
+
+extern "C" int sim_serve_step(const sim_program *const *ps, const uint64_t *first_slice, const uint64_t *n_slices,
+                              const sim_zomega *carry, const uint8_t *last, size_t n, void *stream,
+                              const sim_tuning *t, sim_zomega *out) {
+    if (n && (!out || !first_slice || !n_slices || !last)) return fail(SIM_EINVAL, "null argument");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    if ((rc = check_ranges(ps, n, first_slice, n_slices))) return rc;
+    if (carry)
+        for (size_t i = 0; i < n; ++i)
+            if (!(carry[i].flags & SIM_ZOMEGA_RAW)) return fail(SIM_EINVAL, "carry values must be raw partial sums");
+    if (!n) return SIM_OK;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    if ((rc = settle(D))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    BatchLayout L;
+    if ((rc = build_layout(D, ps, n, first_slice, n_slices, true, t, &L))) return rc;
+    for (size_t i = 0; i < n; ++i) L.args[i].raw = last[i] ? 0u : 1u;  // finalise the requests that end here
+    const BatchPlan B = plan_batch(L, n, true);
+    // the carried sums follow the results in the same region
+    const size_t o_carry = B.total;
+    Region R;
+    if ((rc = lib_region(D, o_carry + up256(n * sizeof(Partial)), &R))) return rc;
+    if ((rc = ensure_host(D, n * sizeof(DevResult)))) return rc;
+    if ((rc = upload_stage(D, L, n, B, R, true, st, nullptr))) return rc;
+    std::vector<Partial> cp(n);
+    for (size_t i = 0; i < n; ++i)
+        for (int k = 0; k < 4; ++k) {
+            cp[i].w[2 * k] = carry ? carry[i].c[k].lo : 0u;
+            cp[i].w[2 * k + 1] = carry ? (uint64_t)carry[i].c[k].hi : 0u;
+        }
+    HIP_TRY(hipMemcpyAsync(R.base + o_carry, cp.data(), n * sizeof(Partial), hipMemcpyHostToDevice, st));
+    const LayoutPtrs LP = layout_ptrs(B, R, true);
+    if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items, LP.parts, LP.firsts, LP.counts, LP.args,
+                            LP.res, true, (const Partial *)(R.base + o_carry))))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(D.host_result, LP.res, n * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<sim_zomega> res(n);
+    for (size_t i = 0; i < n; ++i) {
+        if (ps[i]->pk.zero) {
+            zero_result(&res[i], !last[i]);
+            continue;
+        }
+        DevResult r;
+        memcpy(&r, (const char *)D.host_result + i * sizeof(DevResult), sizeof r);
+        if ((rc = to_zomega(r, &res[i]))) return rc;
+    }
+    for (size_t i = 0; i < n; ++i) out[i] = res[i];
+    return SIM_OK;
 }

@@ -331,8 +331,7 @@ __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32
 #pragma unroll
     for (int w = 0; w < KW; ++w) c0[w] = c1[w] = c2[w] = 0;
     CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
-    for (uint32_t e = 0; e < H.n_fmono; ++e) {
-        const u32x8 E = fe[e];
+    auto one = [&](const u32x8 &E) {
         const uint32_t h = E[0];
         const uint32_t c = h & 7u;
         const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, (h >> 16) & 0xFFu, 1u);
@@ -367,6 +366,21 @@ __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32
 #pragma unroll
             for (int w = 0; w < KW; ++w) c2[w] ^= P[w];
         }
+    };
+    // entries in groups of four, loaded before any of them is used, so that one wait covers the
+    // four scalar loads (with one wave per SIMD nothing else hides their latency)
+    const uint32_t n = H.n_fmono;
+    uint32_t e = 0;
+    for (; e + 4 <= n; e += 4) {
+        u32x8 E[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) E[u] = fe[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) one(E[u]);
+    }
+    for (; e < n; ++e) {
+        const u32x8 E1 = fe[e];
+        one(E1);
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
@@ -439,6 +453,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             v1[j] = ci[NF + j];
         }
         CU32 *e2 = wd + H.off_c2;
+        #pragma unroll 4
         for (uint32_t e = 0; e < H.n_c2; ++e, e2 += 2 * NF + 2) {
             const uint64_t hm = (uint64_t)e2[2 * NF] | ((uint64_t)e2[2 * NF + 1] << 32);
             if ((s & hm) == hm) {
@@ -460,6 +475,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     if (MONO && b0) {
         // inner-and-outer monomials already switched on at the start state
         CU32 *e3 = wd + H.off_c3all;
+        #pragma unroll 4
         for (uint32_t e = 0; e < H.n_c3all; ++e, e3 += 2 * NF + 3) {
             const uint32_t om = e3[2 * NF];
             if ((gray & om) != om) continue;
@@ -741,6 +757,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
     uint32_t L[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) L[w] = wd[H.off_cvec + w];
+    #pragma unroll 4
     for (uint32_t j = H.g; j < H.pe; ++j) {
         const uint32_t m = 0u - (uint32_t)((s >> (j - H.g)) & 1u);
 #pragma unroll
@@ -750,6 +767,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
     uint64_t dal = 0;  // 4-bit field i: always-firing slice-dependent change at a flip of i (mod 8)
     if (MONO) {
         CU32 *mh = wd + H.off_monohi;
+        #pragma unroll 4
         for (uint32_t e = 0; e < H.n_monohi; ++e, mh += 3) {
             const uint64_t hm = (uint64_t)mh[1] | ((uint64_t)mh[2] << 32);
             phi += ((s & hm) == hm) ? (int)mh[0] : 0;
@@ -758,6 +776,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         for (uint32_t i = 0; i < H.g; ++i) {
             int f = 0;
             CU32 *ae = wd + H.off_al + 3 * aidx[i];
+            #pragma unroll 4
             for (uint32_t e = aidx[i]; e < aidx[i + 1]; ++e, ae += 3) {
                 const uint64_t hm = (uint64_t)ae[1] | ((uint64_t)ae[2] << 32);
                 f += ((s & hm) == hm) ? (int)ae[0] : 0;
@@ -769,6 +788,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
     uint32_t Sf = 0;
     if (MONO && H.n_fmono) {
         CU32 *mf = wd + H.off_mforms;
+        #pragma unroll 4
         for (uint32_t j = 0; j < H.n_mforms; ++j) {
             const uint64_t hm = (uint64_t)mf[4 * j] | ((uint64_t)mf[4 * j + 1] << 32);
             Sf |= (mf[4 * j + 2] ^ (uint32_t)(__popcll(s & hm) & 1)) << j;
@@ -785,6 +805,7 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         }
         if (MONO) {
             CU32 *mw = wd + H.off_monowalk;
+            #pragma unroll 4
             for (uint32_t e = 0; e < H.n_monowalk; ++e, mw += 4) {
                 const uint32_t wm = mw[1];
                 if ((g0 & wm) != wm) continue;

@@ -50,9 +50,10 @@ hipError_t launch_eval_batch(const ImgHeader &H0, const ImgHeader *d_hdrs, const
                              uint32_t lds_bytes, hipStream_t stream);
 
 // per-program finaliser: program k sums partials [item_first[k], item_first[k] + item_count[k])
+// and, when d_carry is not null, d_carry[k] (a raw sum carried over from earlier launches)
 hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item_first,
                                  const uint32_t *d_item_count, const FinalArgs *d_args, uint32_t n_progs,
-                                 DevResult *d_out, hipStream_t stream);
+                                 DevResult *d_out, hipStream_t stream, const Partial *d_carry = nullptr);
 
 // bytes of the file-scope device array of the allocation-free entry point, and its address on
 // the current device (called once per device with that device current)

@@ -17,13 +17,16 @@ __device__ __forceinline__ i128 load_i128(const uint64_t *w) {
     return (i128)((unsigned __int128)w[0] | ((unsigned __int128)w[1] << 64));
 }
 
-// sums partials [first, first + n), then applies the constant and canonicalises (thread 0)
+// sums partials [first, first + n) and *carry (if not null), then applies the constant and
+// canonicalises (thread 0)
 __device__ void finalize_range(const Partial *partials, uint32_t first, uint32_t n, const FinalArgs &A,
-                               DevResult *out) {
+                               DevResult *out, const Partial *carry = nullptr) {
     __shared__ i128 s_sum[kMaxThreads][4];
     i128 acc[4] = {0, 0, 0, 0};
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
         for (int k = 0; k < 4; ++k) acc[k] += load_i128(partials[first + i].w + 2 * k);
+    if (carry && threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) acc[k] += load_i128(carry->w + 2 * k);
     for (int k = 0; k < 4; ++k) s_sum[threadIdx.x][k] = acc[k];
     __syncthreads();
     // tree reduction over the workgroup (blockDim.x is a power of two)
@@ -69,9 +72,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_finalize_batch(const Partial *_
                                                                 const uint32_t *__restrict__ item_first,
                                                                 const uint32_t *__restrict__ item_count,
                                                                 const FinalArgs *__restrict__ args,
-                                                                DevResult *__restrict__ out) {
+                                                                DevResult *__restrict__ out,
+                                                                const Partial *__restrict__ carry) {
     const uint32_t k = blockIdx.x;
-    finalize_range(partials, item_first[k], item_count[k], args[k], out + k);
+    finalize_range(partials, item_first[k], item_count[k], args[k], out + k, carry ? carry + k : nullptr);
 }
 
 }  // namespace
@@ -144,10 +148,10 @@ hipError_t launch_finalize(const Partial *partials, uint32_t n, const FinalArgs 
 
 hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item_first,
                                  const uint32_t *d_item_count, const FinalArgs *d_args, uint32_t n_progs,
-                                 DevResult *d_out, hipStream_t stream) {
+                                 DevResult *d_out, hipStream_t stream, const Partial *d_carry) {
     if (n_progs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize_batch, dim3(n_progs), dim3(kMaxThreads), 0, stream, partials,
-                       d_item_first, d_item_count, d_args, d_out);
+                       d_item_first, d_item_count, d_args, d_out, d_carry);
     return hipGetLastError();
 }
 

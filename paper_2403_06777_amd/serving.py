@@ -3,11 +3,15 @@
 Requests arrive over time (open loop).  Each is compiled on a host worker thread (the
 reduction of Section 3 runs once per query), then admitted when a slot is free and its
 program fits the device-memory budget; compiled programs stay resident in an LRU cache so
-repeated queries skip compilation.  Every tick runs ONE batched launch
-(sim_eval_ranges) that evaluates the next chunk of slices of every active request; the
-raw partial sums are added exactly, and a request whose slices are all done is finalised
-on the device and answered.  Requests that arrive while others are on the GPU therefore
+repeated queries skip compilation.  Every tick is ONE batched step on the device
+(sim_serve_step): the next chunk of slices of every active request, each added to the raw
+sum carried from its earlier ticks, and the requests whose last slices are in the tick
+finalised in the same step and answered.  Requests that arrive while others are on the GPU
 join the next tick: their work overlaps on the device with the requests already running.
+
+Shares are size-aware: every active request gets a floor share of the tick, and the rest of
+it goes to the requests with the least work left, whole (shortest remaining first), so small
+requests finish in the tick after their arrival while large ones keep moving.
 
 Because partial sums over disjoint slices add exactly in Z[w], a result does not depend
 on how its slices were chunked or which other requests shared its launches: it is
@@ -73,6 +77,9 @@ class ZxBackend:
 
     def eval_ranges(self, handles, firsts, counts):
         return B.sim_eval_ranges(handles, firsts, counts, self.stream, self.tuning)
+
+    def step(self, handles, firsts, counts, carries, last):
+        return B.sim_serve_step(handles, firsts, counts, carries, last, self.stream, self.tuning)
 
     def raw_add(self, a, b):
         return B.sim_raw_add(a, b)
@@ -306,20 +313,27 @@ class Server:
                 self._finish(a.req, a.entry, stats, now())
                 active = []
                 continue
-            # one tick: the next chunk of every active request in a single launch (a request alone
-            # takes larger chunks: fewer launches, while a new arrival still waits at most one)
-            share = self.alone_terms if len(active) == 1 else max(1, self.tick_terms // len(active))
-            handles, firsts, counts = [], [], []
-            for a in active:
-                info = a.entry.info
-                per = max(1, share >> info["walk_bits"])
-                cnt = min(per, info["n_slices"] - a.next_slice)
-                handles.append(a.entry.handle)
-                firsts.append(a.next_slice)
-                counts.append(cnt)
-            raws = self.backend.eval_ranges(handles, firsts, counts)
+            # one tick: the next chunk of every active request in one step on the device
+            counts = self._shares(active)
+            handles = [a.entry.handle for a in active]
+            firsts = [a.next_slice for a in active]
             stats.ticks += 1
             still, finished = [], []
+            if hasattr(self.backend, "step"):
+                last = [a.next_slice + c >= a.entry.info["n_slices"] for a, c in zip(active, counts)]
+                outs = self.backend.step(handles, firsts, counts, [a.raw for a in active], last)
+                t_done = now()
+                for a, cnt, out, fin in zip(active, counts, outs, last):
+                    a.next_slice += cnt
+                    if fin:
+                        a.req.result = out
+                        self._finish(a.req, a.entry, stats, t_done)
+                    else:
+                        a.raw = out
+                        still.append(a)
+                active = still
+                continue
+            raws = self.backend.eval_ranges(handles, firsts, counts)
             for a, cnt, raw in zip(active, counts, raws):
                 a.raw = self.backend.raw_add(a.raw, raw)
                 a.next_slice += cnt
@@ -339,6 +353,33 @@ class Server:
             active = still
         stats.wall = now()
         return stats
+
+    def _shares(self, active: List[_Active]) -> List[int]:
+        """Slices of each active request in the next tick: a floor of a quarter of an equal
+        share each, then the rest of the tick's terms to the requests with the least work left,
+        each taking all of its remainder while the budget lasts (a request alone takes the larger
+        alone_terms budget)."""
+        n = len(active)
+        budget = self.alone_terms if n == 1 else self.tick_terms
+
+        def per_slice(a):
+            return max(1, (1 << a.entry.info["n_params"]) // a.entry.info["n_slices"])
+
+        def left(a):
+            return a.entry.info["n_slices"] - a.next_slice
+
+        floor = max(1, budget // (4 * n))
+        counts = [min(left(a), max(1, floor // per_slice(a))) for a in active]
+        spent = sum(c * per_slice(a) for a, c in zip(active, counts))
+        for k in sorted(range(n), key=lambda k: left(active[k]) * per_slice(active[k])):
+            room = budget - spent
+            if room <= 0:
+                break
+            a = active[k]
+            extra = min(left(a) - counts[k], room // per_slice(a))
+            counts[k] += extra
+            spent += extra * per_slice(a)
+        return counts
 
     def _finish(self, req: Request, ent: _Entry, stats: ServeStats, t: float):
         ent.users -= 1

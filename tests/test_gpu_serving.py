@@ -10,6 +10,54 @@ import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
+def test_serve_step_carries_and_finalises(o2):
+    # three ticks over two programs of uneven size: the carried raw sums and the finalisation
+    # in the last step give the single evaluation, which equals the oracle
+    texts = [wl.kernel_sized_program(5, p=18, n_factors=30, n_monomials=60).to_text(),
+             wl.random_program(6, 14, n_nodes=12, n_pairs=1, n_lin=4, n_mono=20, scalar_range=2).to_text()]
+    hs = [zx.sim_program_from_ir(t) for t in texts]
+    try:
+        want = [zx.sim_eval_amplitude(h) for h in hs]
+        assert want == [o2.evaluate(t)["canonical"] for t in texts]
+        ns = [zx.sim_program_info(h)["n_slices"] for h in hs]
+        cuts = [[0, n // 3, n // 2, n] for n in ns]
+        carry = [(0, 0, 0, 0), (0, 0, 0, 0)]
+        for k in range(3):
+            firsts = [c[k] for c in cuts]
+            counts = [c[k + 1] - c[k] for c in cuts]
+            last = [k == 2, k == 2]
+            out = zx.sim_serve_step(hs, firsts, counts, carry, last)
+            if k < 2:
+                carry = out
+        assert out == want
+    finally:
+        for h in hs:
+            zx.sim_program_free(h)
+
+
+def test_served_results_equal_the_oracle(o2):
+    # every served request whose compiled program has at most 22 parameters, against the
+    # oracle's evaluation of the same compiled program (its IR text)
+    pool = wl.serving_pool(10)
+    reqs = S.make_stream(pool, 50, rate=300.0, seed=8)
+    backend = S.ZxBackend(p_cap=26)
+    srv = S.Server(backend, mem_budget=64 << 20, max_active=32, tick_terms=1 << 20, compile_workers=4)
+    try:
+        st = srv.run(reqs, realtime=True)
+    finally:
+        srv.close()
+    checked = 0
+    for r in reqs:
+        if r.status != "done" or r.p > 22:
+            continue
+        q = zx.amplitude_query(r.bits) if r.kind == "amplitude" else zx.marginal_query(r.n_qubits, r.qubit, r.value)
+        ir, info = zx.sim_compile_to_ir(r.circuit, q, p_cap=26)
+        assert info["n_params"] == r.p
+        assert r.result == o2.evaluate(ir)["canonical"], r.rid
+        checked += 1
+    assert checked >= 20 and st.done + st.rejected == len(reqs)
+
+
 def test_results_in_the_mix_equal_solo_results():
     pool = wl.serving_pool(12)
     reqs = S.make_stream(pool, 60, rate=400.0, seed=3)

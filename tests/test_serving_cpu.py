@@ -132,3 +132,54 @@ def test_poisson_stream_mix():
     assert 0.15 < kinds.count("marginal") / len(kinds) < 0.45
     arr = [r.arrival for r in reqs]
     assert arr == sorted(arr) and 0.8 < arr[-1] / 2.0 < 1.25
+
+
+class StepBackend(FakeBackend):
+    """the one-step-per-tick interface: carried raw sums added and the last step finalised"""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.steps = []
+
+    def step(self, handles, firsts, counts, carries, last):
+        self.steps.append(list(zip(handles, counts, last)))
+        out = []
+        for h, f, c, carry, fin in zip(handles, firsts, counts, carries, last):
+            assert h in self.live
+            n = self.live[h]["n_slices"]
+            assert 0 <= f and f + c <= n and fin == (f + c == n)
+            raw = tuple(x + y for x, y in zip(carry, (sum(range(f, f + c)), c, 0, 0)))
+            out.append((raw, 0) if fin else raw)
+        return out
+
+
+def test_step_interface_gives_solo_results():
+    be = StepBackend()
+    srv = S.Server(be, mem_budget=1 << 30, max_active=8, tick_terms=1 << 12, compile_workers=2)
+    reqs = _reqs(40)
+    st = srv.run(reqs, realtime=False)
+    assert st.done == 40 and st.rejected == 0
+    for r in reqs:
+        n = 1 << (r.p - min(r.p, 4))
+        assert r.result == ((n * (n - 1) // 2, n, 0, 0), 0)
+    assert be.steps
+
+
+def test_small_requests_overtake_a_large_one():
+    # a large request (2^20 terms) is running when small ones (2^10) arrive: each small one
+    # finishes in the tick after its admission, while the large one still progresses every tick
+    sizes = {0: 20}
+    be = StepBackend(p_of=lambda req: sizes.get(req.rid, 10))
+    srv = S.Server(be, mem_budget=1 << 30, max_active=8, tick_terms=1 << 14, compile_workers=1,
+                   alone_terms=1 << 14)
+    reqs = _reqs(6)
+    st = srv.run(reqs, realtime=False)
+    assert st.done == 6
+    big_ticks = [k for k, s in enumerate(be.steps) if any(h == 1 for h, _, _ in s)]
+    for k, s in enumerate(be.steps):
+        for h, c, fin in s:
+            if h != 1:
+                assert fin, (k, s)  # a small request's whole remainder fits the tick
+            else:
+                assert c > 0  # the large one moves in every tick it is active
+    assert len(big_ticks) >= (1 << 20) // (1 << 14)
