@@ -319,11 +319,62 @@ __device__ __forceinline__ uint32_t spread8(uint32_t b) {
     return (b | (b << 3)) & 0x11111111u;
 }
 
+// Form monomials [e0, e1) of one group: DEG3 forms (else two), coefficient C.  Their 2^KB-bit
+// patterns over a block are ANDs of the forms' patterns (a form is its bit of O xor its lambda),
+// and C times each pattern is added to three bit planes (a sum mod 8 in bit-sliced form).  The
+// entries are read four at a time before any is used, so that one wait covers four scalar loads.
+template <int KW, int C, bool DEG3>
+__device__ __forceinline__ void fm_group(CV8 *fe, uint32_t e0,
+                                         uint32_t e1, uint32_t O, uint32_t (&c0)[KW], uint32_t (&c1)[KW],
+                                         uint32_t (&c2)[KW]) {
+    auto one = [&](const u32x8 &E) {
+        const uint32_t h = E[0];
+        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, (h >> 16) & 0xFFu, 1u);
+        const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, h >> 24, 1u);
+        uint32_t P[KW];
+#pragma unroll
+        for (int w = 0; w < KW; ++w) P[w] = (E[2 + w] ^ m1) & (E[4 + w] ^ m2);
+        if (DEG3) {
+            const uint32_t m3 = (uint32_t)__builtin_amdgcn_sbfe((int)O, E[1], 1u);
+#pragma unroll
+            for (int w = 0; w < KW; ++w) P[w] &= E[6 + w] ^ m3;
+        }
+#pragma unroll
+        for (int w = 0; w < KW; ++w) {
+            if (C & 1) {
+                const uint32_t t = c0[w] & P[w];
+                c0[w] ^= P[w];
+                const uint32_t u = c1[w] & t;
+                c1[w] ^= t;
+                c2[w] ^= u;
+            }
+            if (C & 2) {
+                const uint32_t t = c1[w] & P[w];
+                c1[w] ^= P[w];
+                c2[w] ^= t;
+            }
+            if (C & 4) c2[w] ^= P[w];
+        }
+    };
+    uint32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        u32x8 E[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) E[u] = fe[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) one(E[u]);
+    }
+    for (; e < e1; ++e) {
+        const u32x8 E1 = fe[e];
+        one(E1);
+    }
+}
+
 // Adds to ft the phase of the form monomials at each of a block's 2^KB terms, as 4-bit fields
 // (field k of word k / 8).  O holds the monomials' forms at the block's first term; at step k a
-// form is its bit of O xor bit k of its lambda (the parity of its inner part at gray(k)), so a
-// monomial's values over the block are the AND of 2^KB-bit patterns, and c times that pattern is
-// added to three bit planes (a sum mod 8 in bit-sliced form) before the planes become fields.
+// form is its bit of O xor bit k of its lambda (the parity of its inner part at gray(k)).  The
+// entries come in 14 groups by degree and coefficient (fm_group), and the bit planes become
+// fields at the end.
 template <int KB, int NF>
 __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32_t O, uint32_t (&ft)[NF]) {
     constexpr int KW = (1 << KB) >= 32 ? (1 << KB) / 32 : 1;  // 32-bit words of a pattern
@@ -331,57 +382,21 @@ __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32
 #pragma unroll
     for (int w = 0; w < KW; ++w) c0[w] = c1[w] = c2[w] = 0;
     CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
-    auto one = [&](const u32x8 &E) {
-        const uint32_t h = E[0];
-        const uint32_t c = h & 7u;
-        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, (h >> 16) & 0xFFu, 1u);
-        const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, h >> 24, 1u);
-        uint32_t P[KW];
-#pragma unroll
-        for (int w = 0; w < KW; ++w) P[w] = (E[2 + w] ^ m1) & (E[4 + w] ^ m2);
-        if (((h >> 8) & 3u) == 3u) {
-            const uint32_t m3 = (uint32_t)__builtin_amdgcn_sbfe((int)O, E[1], 1u);
-#pragma unroll
-            for (int w = 0; w < KW; ++w) P[w] &= E[6 + w] ^ m3;
-        }
-        if (c & 1u) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) {
-                const uint32_t t = c0[w] & P[w];
-                c0[w] ^= P[w];
-                const uint32_t u = c1[w] & t;
-                c1[w] ^= t;
-                c2[w] ^= u;
-            }
-        }
-        if (c & 2u) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) {
-                const uint32_t t = c1[w] & P[w];
-                c1[w] ^= P[w];
-                c2[w] ^= t;
-            }
-        }
-        if (c & 4u) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) c2[w] ^= P[w];
-        }
-    };
-    // entries in groups of four, loaded before any of them is used, so that one wait covers the
-    // four scalar loads (with one wave per SIMD nothing else hides their latency)
-    const uint32_t n = H.n_fmono;
-    uint32_t e = 0;
-    for (; e + 4 <= n; e += 4) {
-        u32x8 E[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) E[u] = fe[e + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) one(E[u]);
-    }
-    for (; e < n; ++e) {
-        const u32x8 E1 = fe[e];
-        one(E1);
-    }
+    CU32 *gb = wd + H.off_fmgrp;
+    fm_group<KW, 1, false>(fe, gb[0], gb[1], O, c0, c1, c2);
+    fm_group<KW, 2, false>(fe, gb[1], gb[2], O, c0, c1, c2);
+    fm_group<KW, 3, false>(fe, gb[2], gb[3], O, c0, c1, c2);
+    fm_group<KW, 4, false>(fe, gb[3], gb[4], O, c0, c1, c2);
+    fm_group<KW, 5, false>(fe, gb[4], gb[5], O, c0, c1, c2);
+    fm_group<KW, 6, false>(fe, gb[5], gb[6], O, c0, c1, c2);
+    fm_group<KW, 7, false>(fe, gb[6], gb[7], O, c0, c1, c2);
+    fm_group<KW, 1, true>(fe, gb[7], gb[8], O, c0, c1, c2);
+    fm_group<KW, 2, true>(fe, gb[8], gb[9], O, c0, c1, c2);
+    fm_group<KW, 3, true>(fe, gb[9], gb[10], O, c0, c1, c2);
+    fm_group<KW, 4, true>(fe, gb[10], gb[11], O, c0, c1, c2);
+    fm_group<KW, 5, true>(fe, gb[11], gb[12], O, c0, c1, c2);
+    fm_group<KW, 6, true>(fe, gb[12], gb[13], O, c0, c1, c2);
+    fm_group<KW, 7, true>(fe, gb[13], gb[14], O, c0, c1, c2);
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         const int wi = (8 * j) / 32, sh = (8 * j) % 32;
@@ -757,11 +772,17 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
     uint32_t L[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) L[w] = wd[H.off_cvec + w];
+    // the high parameters of the slice into L, and into the form monomials' forms (S: their
+    // constants and slice parts, one column of forms per slice bit)
+    const bool fm = MONO && H.n_fmono;
+    uint32_t Sf = fm ? H.fm_s0 : 0u;
+    CU32 *scol = wd + H.off_scol - H.g;
     #pragma unroll 4
     for (uint32_t j = H.g; j < H.pe; ++j) {
         const uint32_t m = 0u - (uint32_t)((s >> (j - H.g)) & 1u);
 #pragma unroll
         for (int w = 0; w < W; ++w) L[w] ^= col[j * W + w] & m;
+        if (fm) Sf ^= scol[j] & m;
     }
     int phi = 0;
     uint64_t dal = 0;  // 4-bit field i: always-firing slice-dependent change at a flip of i (mod 8)
@@ -785,15 +806,6 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         }
     }
     // the form monomials' forms at the slice's first assignment, without their walk parts
-    uint32_t Sf = 0;
-    if (MONO && H.n_fmono) {
-        CU32 *mf = wd + H.off_mforms;
-        #pragma unroll 4
-        for (uint32_t j = 0; j < H.n_mforms; ++j) {
-            const uint64_t hm = (uint64_t)mf[4 * j] | ((uint64_t)mf[4 * j + 1] << 32);
-            Sf |= (mf[4 * j + 2] ^ (uint32_t)(__popcll(s & hm) & 1)) << j;
-        }
-    }
     if (b0) {
         // the walk starts at block b0: its first state has the walk bits of gray(b0 * 2^K)
         const uint32_t t0 = b0 << inner_bits_for(W);
@@ -847,7 +859,6 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         return;
     }
     // short walks: one step at a time (form monomials evaluated per term)
-    const bool fm = MONO && H.n_fmono;
     uint32_t Of = Sf;
     add_term<W, ACC, SET, true>(H, S, tab, cnt, L, phi + (fm ? form_phase(H, wd, Of) : 0), acc);
     uint32_t gray = 0;
@@ -942,7 +953,36 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
         const uint32_t n = H.zero_entry * H.q_limbs;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_cnt[i] = 0;
     } else {
-        for (uint32_t i = threadIdx.x; i < H.table_n * 4; i += blockDim.x) s_tab[i] = gtab[i];
+        // the value table from its base entries Q(d) (r = 0, e = 0): each thread builds the 16
+        // entries w^r sqrt2^e Q(d) of one d (negacyclic rotations, one product with sqrt2), so a
+        // workgroup loads one entry per d instead of all of them
+        const uint32_t nd = H.zero_entry / 16;
+        longlong2 *t2 = reinterpret_cast<longlong2 *>(s_tab);
+        for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x) {
+            const longlong2 *src = reinterpret_cast<const longlong2 *>(gtab + (size_t)d * 64);
+            const longlong2 a = src[0], b = src[1];
+            int64_t z[4] = {a.x, a.y, b.x, b.y};
+            int64_t y[4] = {z[1] - z[3], z[0] + z[2], z[1] + z[3], z[2] - z[0]};  // sqrt2 z
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const size_t at = ((size_t)d * 16 + (size_t)r * 2) * 2;
+                t2[at] = make_longlong2(z[0], z[1]);
+                t2[at + 1] = make_longlong2(z[2], z[3]);
+                t2[at + 2] = make_longlong2(y[0], y[1]);
+                t2[at + 3] = make_longlong2(y[2], y[3]);
+                // times w: (c0, c1, c2, c3) -> (-c3, c0, c1, c2)
+                const int64_t z3 = z[3], y3 = y[3];
+                z[3] = z[2];
+                z[2] = z[1];
+                z[1] = z[0];
+                z[0] = (int64_t)(0ull - (uint64_t)z3);
+                y[3] = y[2];
+                y[2] = y[1];
+                y[1] = y[0];
+                y[0] = (int64_t)(0ull - (uint64_t)y3);
+            }
+        }
+        if (threadIdx.x < 4) s_tab[(size_t)H.zero_entry * 4 + threadIdx.x] = 0;
     }
     const uint32_t *words = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(gtab) - H.table_byte_off);
     if (H.ntab_n) {

@@ -164,7 +164,11 @@ struct ImgHeader {
     uint32_t n_fmono;
     uint32_t off_fmono;   // 8 words each: c | deg << 8 | j1 << 16 | j2 << 24, j3, lambda lo/hi x 3
     uint32_t n_mforms;
+    uint32_t off_fmgrp;   // 15 words: entries [grp[k], grp[k + 1]) have 2 (k < 7) or 3 forms and
+                          // coefficient k % 7 + 1 (the entries are sorted so)
     uint32_t off_mforms;  // 4 words each: slice mask lo, hi, constant, 0
+    uint32_t off_scol;    // pe - g words: the forms containing slice bit j (S = fm_s0 ^ the
+    uint32_t fm_s0;       //   columns of the set slice bits)
     uint32_t off_gcol;    // g words: the forms containing walk position i
     uint32_t gcol_top;    // gcol[KB - 1]: the top inner bit, set at the first term of odd blocks
     uint32_t block_flush128;  // int64 mode: each block's sums move to int128 after the block

@@ -361,6 +361,9 @@ struct Elimination {
     std::vector<uint64_t> cols;  // ... and what new parameter j = 1 adds to it
 };
 constexpr int kMaxMonoForms = 32;
+// programs of at most 2^kFormMonoMaxParams terms evaluate their variable monomials as form
+// monomials (about 1024 blocks of 64 lanes x 64 terms: one wave per SIMD)
+constexpr int kFormMonoMaxParams = 22;
 
 static bool eliminate_vanishing(const IrProgram &ir, IrProgram *red, std::vector<IrFormMono> *fmono,
                                 Elimination *el) {
@@ -713,7 +716,57 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
         else w.lin.push_back({2, pr.f2});
         w.lin.push_back({6, fz2});                          // -2 (z xor l2)
     }
-    for (const auto &l : ir.lin) {
+    for (const auto &m : ir.mono) {
+        std::vector<int> vs;
+        for (int v : m.vars) vs.push_back(v + q);
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        int &c = w.mono[vs];
+        c = mod8((long long)c + m.c);
+    }
+    for (auto it = w.mono.begin(); it != w.mono.end();) {
+        if (it->second == 0) it = w.mono.erase(it);
+        else ++it;
+    }
+    // Small programs (a few thousand blocks of terms: about one wave per SIMD): the per-slice
+    // set-up of the variable monomials' walk lists would cost more than the blocks themselves, so
+    // every variable monomial becomes a form monomial over coordinate forms (evaluated per block,
+    // nothing per slice), and those of degree one linear terms on their coordinate forms.
+    std::vector<IrLin> extra_lin;
+    {
+        // (only without factors that can vanish: the walks that test them per block do not
+        // evaluate form monomials)
+        bool conv = q == 0 && !w.mono.empty() && w.pe <= kFormMonoMaxParams;
+        for (const auto &n : w.nodes) conv = conv && n.second.first != 4 && n.second.second != 4;
+        std::vector<IrForm> seen;
+        auto note = [&](const IrForm &f) {
+            for (const auto &h : seen)
+                if (h.cst == f.cst && h.mask == f.mask) return;
+            seen.push_back(f);
+        };
+        for (const auto &m : fmono)
+            for (const auto &f : m.forms) note(f);
+        for (const auto &m : w.mono) {
+            if (m.first.size() > 3) conv = false;
+            if (m.first.size() >= 2)
+                for (int v : m.first) note(IrForm{0, (uint64_t)1 << v});
+        }
+        for (const auto &m : w.mono)
+            if (m.first.size() == 1) note(IrForm{0, (uint64_t)1 << m.first[0]});
+        if (conv && (int)seen.size() <= kMaxMonoForms) {
+            // (a degree-one monomial is a form monomial whose one form is taken twice)
+            for (const auto &m : w.mono) {
+                IrFormMono fm{m.second, {}};
+                for (int v : m.first) fm.forms.push_back(IrForm{0, (uint64_t)1 << v});
+                if (fm.forms.size() == 1) fm.forms.push_back(fm.forms[0]);
+                fmono.push_back(fm);
+            }
+            w.mono.clear();
+        }
+    }
+    std::vector<IrLin> all_lin = ir.lin;
+    all_lin.insert(all_lin.end(), extra_lin.begin(), extra_lin.end());
+    for (const auto &l : all_lin) {
         int c = mod8(l.c);
         if (!c) continue;
         const IrForm &f = w.forms[l.form];
@@ -759,18 +812,6 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
             lin.insert(lin.begin(), {4, fg});
         }
         w.lin.swap(lin);
-    }
-    for (const auto &m : ir.mono) {
-        std::vector<int> vs;
-        for (int v : m.vars) vs.push_back(v + q);
-        std::sort(vs.begin(), vs.end());
-        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
-        int &c = w.mono[vs];
-        c = mod8((long long)c + m.c);
-    }
-    for (auto it = w.mono.begin(); it != w.mono.end();) {
-        if (it->second == 0) it = w.mono.erase(it);
-        else ++it;
     }
     if (mod8(const_phase)) w.c0 = zw_rot(w.c0, mod8(const_phase));
     if (w.zero) {
@@ -852,6 +893,16 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
     // constants and slice parts), G the outer walk parts of the current walk state (updated with
     // gcol[i] at each flip of walk position i, wave-uniform).  At step k of the block a form is
     // its bit of O xor lambda bit k, lambda = its inner part's parity at gray(k).
+    // entries grouped by degree (two forms, then three) and coefficient 1..7, so that the kernel
+    // runs one branch-free loop per group; a zero coefficient contributes nothing
+    {
+        std::vector<IrFormMono> sorted;
+        for (int d3 = 0; d3 < 2; ++d3)
+            for (int c = 1; c < 8; ++c)
+                for (const auto &m : fmono)
+                    if ((m.forms.size() == 3) == (d3 == 1) && mod8(m.c) == c) sorted.push_back(m);
+        fmono.swap(sorted);
+    }
     std::vector<IrForm> mforms;
     std::vector<std::array<int, 3>> fm_idx;
     for (const auto &m : fmono) {
@@ -1400,6 +1451,19 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
             img.insert(img.end(), ent, ent + 8);
         }
     }
+    // group boundaries: 15 words, group k = (three forms: k >= 7, coefficient k % 7 + 1) holds
+    // entries [grp[k], grp[k + 1])
+    H.off_fmgrp = (uint32_t)img.size();
+    {
+        uint32_t at = 0;
+        for (int d3 = 0; d3 < 2; ++d3)
+            for (int c = 1; c < 8; ++c) {
+                img.push_back(at);
+                for (size_t e = 0; e < fmono.size(); ++e)
+                    if ((fm_idx[e][2] >= 0) == (d3 == 1) && mod8(fmono[e].c) == c) ++at;
+            }
+        img.push_back(at);
+    }
     H.off_mforms = (uint32_t)img.size();
     for (const auto &f : mforms) {
         const uint64_t hm = g >= 64 ? 0 : f.mask >> g;
@@ -1410,6 +1474,16 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
     }
     H.off_gcol = (uint32_t)img.size();
     img.insert(img.end(), gcol.begin(), gcol.end());
+    H.off_scol = (uint32_t)img.size();
+    H.fm_s0 = 0;
+    for (size_t j = 0; j < mforms.size(); ++j)
+        if (mforms[j].cst) H.fm_s0 |= 1u << j;
+    for (int i = g; i < w.pe; ++i) {
+        uint32_t c = 0;
+        for (size_t j = 0; j < mforms.size(); ++j)
+            if (mforms[j].mask >> i & 1) c |= 1u << j;
+        img.push_back(c);
+    }
 
     // ---- value table
     H.d_off = (int32_t)(-dmin);
@@ -1553,7 +1627,7 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
     //    (5 plus 5 per firing slice-dependent entry);
     //  * per slice: the high parameters into L (2W each), 5 per slice-dependent monomial entry,
     //    4 per walk position for the packed always-firing fields, 4 + 4 NF per inner-vector entry,
-    //    5 per form of the form monomials (its bit of S);
+    //    2 per slice bit for the form monomials' forms (S);
     //  * form monomials, per block: O (1); per monomial a bit extract and KW XORs per form (KW =
     //    words of a block's 2^KB-bit pattern), KW ANDs per further form, and the add of c times the
     //    pattern to three bit planes (5, 3, 1 KW for the bits of c); the planes to 4-bit fields (23
@@ -1631,7 +1705,7 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
                 fm_block += deg * (1 + KW) + (deg - 1) * KW + ((c & 1) ? 5 : 0) * KW + ((c & 2) ? 3 : 0) * KW +
                             ((c & 4) ? 1 : 0) * KW;
             }
-            setup += 5.0 * mforms.size();
+            setup += 2.0 * (w.pe - g);  // S: one masked column XOR per slice bit
         }
         if (blocks) walk += (double)(steps >> KB) * (fm_block + (flush128 ? 16.0 : 0.0));
         else if (!fmono.empty()) ops += 1 + 5.0 * fmono.size();
