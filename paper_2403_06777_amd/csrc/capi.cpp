@@ -205,7 +205,8 @@ int eval_grid(DeviceState &D, const sim_program *P, uint64_t count, uint32_t thr
     }
     const uint32_t kb = (uint32_t)inner_bits_for(H.W);
     const uint32_t lg_units = H.g >= kb ? H.g - kb : 0u;
-    const uint64_t units = ((count + 63) / 64) << std::min<uint32_t>(lg_units, 40);
+    // a unit is taken by a team of term_split waves
+    const uint64_t units = (((count + 63) / 64) << std::min<uint32_t>(lg_units, 40)) * std::max<uint32_t>(1, H.term_split);
     const uint64_t waves_per_block = threads / 64;
     const uint64_t want = (units + waves_per_block - 1) / waves_per_block;
     const uint64_t cap = (uint64_t)std::max(1, D.cus) * bpc;
@@ -263,7 +264,7 @@ int plan_single(DeviceState &D, const sim_program *P, uint64_t count, const sim_
         const ImgHeader &H = P->pk.hdr;
         const uint32_t kb = (uint32_t)inner_bits_for(H.W);
         const uint32_t lg_units = H.g >= kb ? H.g - kb : 0u;
-        const uint64_t units = ((count + 63) / 64) << std::min<uint32_t>(lg_units, 40);
+        const uint64_t units = (((count + 63) / 64) << std::min<uint32_t>(lg_units, 40)) * std::max<uint32_t>(1, H.term_split);
         if (units < 4 * (uint64_t)std::max(1, D.cus)) S->threads = 64;
     }
     int rc = eval_grid(D, P, count, S->threads, t, &S->blocks);

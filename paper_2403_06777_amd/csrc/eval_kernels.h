@@ -406,6 +406,78 @@ __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32
     }
 }
 
+// form_fields for one half of a 64-term block (hsel 0: steps 0..31, 1: steps 32..63): the
+// patterns' word hsel only, and the four field words of that half
+template <int C, bool DEG3>
+__device__ __forceinline__ void fm_group_half(CV8 *fe, uint32_t e0, uint32_t e1, uint32_t O, uint32_t hsel,
+                                              uint32_t &c0, uint32_t &c1, uint32_t &c2) {
+    auto one = [&](const u32x8 &E) {
+        const uint32_t h = E[0];
+        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, (h >> 16) & 0xFFu, 1u);
+        const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, h >> 24, 1u);
+        uint32_t P = ((hsel ? E[3] : E[2]) ^ m1) & ((hsel ? E[5] : E[4]) ^ m2);
+        if (DEG3) P &= (hsel ? E[7] : E[6]) ^ (uint32_t)__builtin_amdgcn_sbfe((int)O, E[1], 1u);
+        if (C & 1) {
+            const uint32_t t = c0 & P;
+            c0 ^= P;
+            const uint32_t u = c1 & t;
+            c1 ^= t;
+            c2 ^= u;
+        }
+        if (C & 2) {
+            const uint32_t t = c1 & P;
+            c1 ^= P;
+            c2 ^= t;
+        }
+        if (C & 4) c2 ^= P;
+    };
+    uint32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        u32x8 E[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) E[u] = fe[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) one(E[u]);
+    }
+    for (; e < e1; ++e) {
+        const u32x8 E1 = fe[e];
+        one(E1);
+    }
+}
+
+__device__ __forceinline__ void form_fields_half(const ImgHeader &H, CU32 *wd, uint32_t O, uint32_t hsel,
+                                                 uint32_t (&ft)[8]) {
+    uint32_t c0 = 0, c1 = 0, c2 = 0;
+    CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
+    CU32 *gb = wd + H.off_fmgrp;
+    fm_group_half<1, false>(fe, gb[0], gb[1], O, hsel, c0, c1, c2);
+    fm_group_half<2, false>(fe, gb[1], gb[2], O, hsel, c0, c1, c2);
+    fm_group_half<3, false>(fe, gb[2], gb[3], O, hsel, c0, c1, c2);
+    fm_group_half<4, false>(fe, gb[3], gb[4], O, hsel, c0, c1, c2);
+    fm_group_half<5, false>(fe, gb[4], gb[5], O, hsel, c0, c1, c2);
+    fm_group_half<6, false>(fe, gb[5], gb[6], O, hsel, c0, c1, c2);
+    fm_group_half<7, false>(fe, gb[6], gb[7], O, hsel, c0, c1, c2);
+    fm_group_half<1, true>(fe, gb[7], gb[8], O, hsel, c0, c1, c2);
+    fm_group_half<2, true>(fe, gb[8], gb[9], O, hsel, c0, c1, c2);
+    fm_group_half<3, true>(fe, gb[9], gb[10], O, hsel, c0, c1, c2);
+    fm_group_half<4, true>(fe, gb[10], gb[11], O, hsel, c0, c1, c2);
+    fm_group_half<5, true>(fe, gb[11], gb[12], O, hsel, c0, c1, c2);
+    fm_group_half<6, true>(fe, gb[12], gb[13], O, hsel, c0, c1, c2);
+    fm_group_half<7, true>(fe, gb[13], gb[14], O, hsel, c0, c1, c2);
+    uint32_t f[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        f[j] = spread8((c0 >> (8 * j)) & 0xFFu) | (spread8((c1 >> (8 * j)) & 0xFFu) << 1) |
+               (spread8((c2 >> (8 * j)) & 0xFFu) << 2);
+    if (hsel == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ft[j] = field_add(ft[j], f[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ft[4 + j] = field_add(ft[4 + j], f[j]);
+    }
+}
+
 // phase of the form monomials at one term whose forms' values are the bits of O (short walks)
 __device__ __forceinline__ int form_phase(const ImgHeader &H, CU32 *wd, uint32_t O) {
     CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
@@ -432,7 +504,7 @@ template <int W, bool MONO, int ACC, uint32_t SET, bool ZERO, bool CQ, bool ZT, 
 __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &S, CU32 *wd, const int64_t *tab,
                                             unsigned long long *cnt, uint64_t s, bool valid, uint32_t b0,
                                             uint32_t b1, uint32_t (&L)[W], int phi, uint64_t dal, uint32_t Sf,
-                                            WaveQueue *Q, Acc<ACC> &acc) {
+                                            WaveQueue *Q, Acc<ACC> &acc, uint32_t half = 0) {
     constexpr int KB = inner_bits_for(W);  // inner bits of a block
     constexpr int KS = 1 << KB;             // its terms
     constexpr int NF = KS / 8;              // words of its 4-bit phase fields
@@ -728,6 +800,42 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             // the block's last state: gray(KS - 1) has only the top inner bit set
 #pragma unroll
             for (int w = 0; w < W; ++w) L[w] ^= ck[KB - 1][w];
+        } else if (KB == 6 && half) {
+            // a team of two waves shares the walk: this one evaluates half of the block's terms
+            // (steps 0..31 or 32..63) with the form monomials' fields of that half only; the
+            // block's last state follows as usual.  (Programs without variable monomials.)
+            uint32_t L0[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) L0[w] = L[w];
+            uint32_t ft[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const uint32_t hsel = half - 1u;
+            if (MONO && H.n_fmono)
+                form_fields_half(H, wd, Sf ^ G ^ ((b & 1u) ? H.gcol_top : 0u), hsel, ft);
+            if (hsel == 0) {
+                add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + (int)(ft[0] & 7u), acc);
+#pragma unroll
+                for (int k = 1; k < 32; ++k) {
+                    const int j = __builtin_ctz(k);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) L[w] ^= ck[j][w];
+                    add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L,
+                                                     phi + (int)((ft[k >> 3] >> (4 * (k & 7))) & 7u), acc);
+                }
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) L[w] ^= ck[4 % KB][w] ^ ck[5 % KB][w];  // gray(32) = 48
+                add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + (int)(ft[4] & 7u), acc);
+#pragma unroll
+                for (int k = 33; k < 64; ++k) {
+                    const int j = __builtin_ctz(k);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) L[w] ^= ck[j % KB][w];
+                    add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L,
+                                                     phi + (int)((ft[(k >> 3) % NF] >> (4 * (k & 7))) & 7u), acc);
+                }
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) L[w] = L0[w] ^ ck[KB - 1][w];
         } else {
             // with form monomials, their absolute phase at each term joins the block's fields
             // (fv itself, relative to the first term, keeps carrying phi across blocks)
@@ -758,7 +866,7 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
 template <int W, bool MONO, int ACC, uint32_t SET, bool CQ>
 __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const int64_t *tab, unsigned long long *cnt,
                                           uint64_t s, bool valid, uint32_t b0, uint32_t b1, WaveQueue *Q,
-                                          Acc<ACC> &acc) {
+                                          Acc<ACC> &acc, uint32_t half = 0) {
     // the compacting walk needs only the vanishing masks (the queue reads the statistic
     // masks when it evaluates terms)
     Slots<W> S;
@@ -844,10 +952,10 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
         if (!H.has_zero) {
             if (b32)
                 walk_blocks<W, MONO, ACC, SET, false, false, false, B32_OK>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi,
-                                                                           dal, Sf, Q, acc);
+                                                                           dal, Sf, Q, acc, half);
             else
                 walk_blocks<W, MONO, ACC, SET, false, false, false>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi, dal, Sf,
-                                                                    Q, acc);
+                                                                    Q, acc, half);
         } else if (!kCompact<W>) {
             if (b32)
                 walk_blocks<W, MONO, ACC, SET, true, false, false, B32_OK>(H, S, wd, tab, cnt, s, true, b0, b1, L, phi,
@@ -1024,6 +1132,12 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
     const bool compact = kCompact<W> && H.has_zero && blocks;
     const uint32_t lg_nb = blocks ? H.g - inner_bits_for(W) : 0u;  // units per slice group = 2^lg_nb
     const uint64_t n_units = ((s_count + 63) >> 6) << lg_nb;
+    // teams of two waves sharing every unit, each evaluating half of a block's terms (header
+    // flag term_split, used when the launch holds whole teams): twice the waves for small grids
+    const uint32_t T = (H.term_split == 2 && blocks && !compact && (n_waves & 1) == 0) ? 2u : 1u;
+    const uint32_t half = T == 2 ? (uint32_t)(wave & 1) + 1u : 0u;
+    wave /= T;
+    n_waves /= T;
     const uint64_t q = uniform64(n_units / n_waves), r = uniform64(n_units % n_waves);
     const uint64_t u_begin = uniform64(wave * q + (wave < r ? wave : r));
     const uint64_t u_end = uniform64(u_begin + q + (wave < r ? 1 : 0));
@@ -1047,7 +1161,7 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
                                                    blocks ? b1 : 1u, &Q, acc);
             else if (valid)
                 run_slice<W, MONO, ACC, SET, false>(H, wd, s_tab, s_cnt, s_first + s, true, b0,
-                                                    blocks ? b1 : 1u, &Q, acc);
+                                                    blocks ? b1 : 1u, &Q, acc, half);
             u += b1 - b0;
         }
         if (ACC == ACC_CLASS && c + 1 < n_chunks) {

@@ -172,6 +172,8 @@ struct ImgHeader {
     uint32_t off_gcol;    // g words: the forms containing walk position i
     uint32_t gcol_top;    // gcol[KB - 1]: the top inner bit, set at the first term of odd blocks
     uint32_t block_flush128;  // int64 mode: each block's sums move to int128 after the block
+    uint32_t term_split;      // 2: two waves share each unit, each taking half of a 64-term block
+                              // (small programs with form monomials only); 1 otherwise
     uint32_t table_byte_off;  // int64 table: 4 coefficients per entry
     uint32_t table_n;         // entries (value classes + one zero entry)
     int32_t d_off;            // class of (d, r, e) = ((d + d_off) * 8 + r) * 2 + e

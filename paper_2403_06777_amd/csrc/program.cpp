@@ -733,6 +733,7 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
     // every variable monomial becomes a form monomial over coordinate forms (evaluated per block,
     // nothing per slice), and those of degree one linear terms on their coordinate forms.
     std::vector<IrLin> extra_lin;
+    bool fm_only = false;  // the variable monomials became form monomials
     {
         // (only without factors that can vanish: the walks that test them per block do not
         // evaluate form monomials)
@@ -754,6 +755,7 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
         for (const auto &m : w.mono)
             if (m.first.size() == 1) note(IrForm{0, (uint64_t)1 << m.first[0]});
         if (conv && (int)seen.size() <= kMaxMonoForms) {
+            fm_only = true;
             // (a degree-one monomial is a form monomial whose one form is taken twice)
             for (const auto &m : w.mono) {
                 IrFormMono fm{m.second, {}};
@@ -1422,6 +1424,9 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
     // forms' lambda as lo, hi words; lambda holds the block's 2^KB steps, KB <= 6); the forms:
     // 4 words each (slice mask lo, hi, constant, 0)
     H.block_flush128 = flush128 ? 1u : 0u;
+    // small programs whose monomials are all form monomials (no per-slice walk lists): two
+    // waves per unit, each evaluating half of every 64-term block
+    H.term_split = (fm_only && KB == 6 && g >= KB && !has_zero) ? 2u : 1u;
     H.n_fmono = (uint32_t)fmono.size();
     H.n_mforms = (uint32_t)mforms.size();
     H.gcol_top = g >= KB && KB > 0 ? gcol[KB - 1] : 0u;
@@ -1706,6 +1711,11 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
                             ((c & 4) ? 1 : 0) * KW;
             }
             setup += 2.0 * (w.pe - g);  // S: one masked column XOR per slice bit
+        }
+        if (blocks && H.term_split == 2) {
+            // both waves of a team extract the forms' bits; each takes one pattern word
+            for (size_t e = 0; e < fmono.size(); ++e) fm_block += (fm_idx[e][2] >= 0 ? 3 : 2);
+            fm_block += 2.0 * W;  // the second half's start state
         }
         if (blocks) walk += (double)(steps >> KB) * (fm_block + (flush128 ? 16.0 : 0.0));
         else if (!fmono.empty()) ops += 1 + 5.0 * fmono.size();

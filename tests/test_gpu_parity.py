@@ -428,3 +428,44 @@ def ProgramSpecZero():
     pr.nodes.append((f, 0, 4))
     pr.nodes.append((pr.add_form(0, 0b101), 1, 4))
     return pr.to_text()
+
+
+def _aligned_blocks(seed, p, fpb):
+    # blocks of 4 parameters whose factors 1 + w^(2 l) are 2 or 1 + i (no linear phases): the
+    # block sums do not cancel, so the whole sum exceeds 2^64 (int128 sums); relabelled by a
+    # random invertible affine map, which keeps the sum
+    from workloads.programs import ProgramSpec, _random_invertible_rows, _parity
+    rng = wl.SplitMix64(85, seed)
+    full, blocks = ProgramSpec(p), []
+    for off in range(0, p, 4):
+        blk = ProgramSpec(4)
+        for _ in range(fpb):
+            blk.nodes.append((blk.add_form(rng.randint(0, 1), rng.randint(1, 15)), 0, 2))
+        blocks.append(blk)
+        base = len(full.forms)
+        full.forms += [(c, m << off) for c, m in blk.forms]
+        full.nodes += [(base + f, a, b) for f, a, b in blk.nodes]
+    rows = _random_invertible_rows(rng, p)
+    shift = rng.randint(0, (1 << p) - 1)
+    forms = []
+    for c, m in full.forms:
+        mm = 0
+        for i in range(p):
+            if m >> i & 1:
+                mm ^= rows[i]
+        forms.append((c ^ _parity(m & shift), mm))
+    full.forms = forms
+    return full, blocks
+
+
+@pytest.mark.parametrize("p,fpb", [(40, 4), (44, 3)])
+def test_closed_forms_int128_stress(o2, p, fpb):
+    full, blocks = _aligned_blocks(p, p, fpb)
+    expect = zw.ONE
+    for blk in blocks:
+        expect = zw.mul(expect, o2.evaluate(blk.to_text(), threads=1)["raw"])
+    bits = max(abs(v) for v in expect).bit_length()
+    info = zx.sim_ir_info(full.to_text())
+    say("int128 stress", p, fpb, "log2|sum|", bits, "ops/term", info["ops_per_term"])
+    assert bits > 64 and info["n_params"] == p
+    assert gpu_value(full.to_text()) == zw.canonical(expect, 0)

@@ -162,14 +162,16 @@ def _parity(v: int) -> int:
 
 def block_separable_program(seed: int, p: int, block_size: int = 4, factors_per_block: int = 2,
                             lin_per_block: int = 1, mono_per_block: int = 0,
-                            pairs_per_block: int = 0, scramble: bool = True):
+                            pairs_per_block: int = 0, scramble: bool = True, no_vanishing: bool = False):
     """A program whose variables split into independent blocks of <= block_size, so its
     sum is the product of the block sums; then relabelled by x = A y XOR b.
 
     Returns (program, blocks): each block is a small ProgramSpec over its own variables.
     With ``scramble`` the relabelling is a random invertible affine map (allowed only when
     there are no variable monomials, since a monomial in x is not a monomial in y); with
-    monomials the relabelling is a random permutation of the variables plus a shift b."""
+    monomials the relabelling is a random permutation of the variables plus a shift b.
+    no_vanishing redraws node factors until neither of their two values is 1 + w^4 = 0 (so every
+    block sum is large: the int128 stress cases)."""
     if mono_per_block and scramble:
         raise ValueError("variable monomials only survive a permutation relabelling")
     rng = SplitMix64(STREAM_BLOCKS, seed * 7919 + p)
@@ -183,7 +185,10 @@ def block_separable_program(seed: int, p: int, block_size: int = 4, factors_per_
             const = 1 if rng.bernoulli(0.5) else 0
             mask = _random_mask(rng, size, 0.6) or 1
             f = blk.add_form(const, mask)
-            blk.nodes.append((f, rng.randint(0, 7), rng.randint(1, 7)))
+            a, b = rng.randint(0, 7), rng.randint(1, 7)
+            while no_vanishing and (a == 4 or (a + b) % 8 == 4):
+                a, b = rng.randint(0, 7), rng.randint(1, 7)
+            blk.nodes.append((f, a, b))
         for _ in range(pairs_per_block):
             f1 = blk.add_form(rng.randint(0, 1), _random_mask(rng, size, 0.6) or 1)
             f2 = blk.add_form(rng.randint(0, 1), _random_mask(rng, size, 0.6) or 1)
