@@ -382,13 +382,13 @@ def serve_section(stream, n_requests: int, p_cap: int) -> dict:
     mu = st.done / st.wall if st.wall > 0 else 1.0
     progress(f"serve: single-query service rate {mu:.1f}/s")
     rows = []
-    # the swept rates with a budget that holds every program, then 2x with a budget of 256 KiB
-    # (a few dozen resident programs): compiled programs wait for memory (held_for_memory)
+    # the swept rates with a budget that holds every program, then 2x and 4x with a budget of
+    # 64 KiB (a few resident programs): compiled programs wait for memory (held_for_memory)
     for mult, budget in ((0.25, 256 << 20), (0.5, 256 << 20), (1.0, 256 << 20), (2.0, 256 << 20),
-                         (4.0, 256 << 20), (2.0, 256 << 10)):
+                         (4.0, 256 << 20), (2.0, 64 << 10), (4.0, 64 << 10)):
         rate = mult * mu
         reqs = S.make_stream(pool, n_requests, rate=rate, seed=int(mult * 100))
-        srv = S.Server(backend, mem_budget=budget, max_active=256, tick_terms=1 << 27, compile_workers=8)
+        srv = S.Server(backend, mem_budget=budget, max_active=256, tick_terms=1 << 28, compile_workers=8)
         try:
             a = srv.run(reqs, realtime=True).summary()
         finally:

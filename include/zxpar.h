@@ -291,6 +291,20 @@ SIM_API int sim_serve_step(const sim_program *const *progs, const uint64_t *firs
                            const sim_zomega *carry, const uint8_t *last, size_t n, void *stream,
                            const sim_tuning *t, sim_zomega *out);
 
+/* The pipelined form of sim_serve_step: raw sums carried on the device and nothing waited for,
+ * so a serving loop can enqueue its next step while the previous one runs.  dev_carry holds
+ * n_carry_slots device accumulators of 72 bytes (caller-owned, 8-byte aligned); request i uses
+ * slot slots[i] (distinct within a step).  flags[i] bit 0: its first step (the slot is not
+ * read); bit 1: its last step.  Each request's partial sum over slices [first_slice[i],
+ * first_slice[i] + n_slices[i]) plus its carried sum goes back to its slot as a raw sum, or, on
+ * its last step, is finalised into dev_out[i] (caller-owned device memory, n x 72 bytes).  The
+ * layout of a step goes through one of a few library staging buffers, reused once the step that
+ * last used it has completed (the call waits on the host only then).  Steps on one stream run in
+ * order, so a slot's sum is read by its next step after the previous one wrote it. */
+SIM_API int sim_serve_enqueue(const sim_program *const *progs, const uint64_t *first_slice, const uint64_t *n_slices,
+                              const uint32_t *slots, const uint8_t *flags, size_t n, void *dev_carry,
+                              size_t n_carry_slots, void *stream, const sim_tuning *t, sim_zomega *dev_out);
+
 /* Amplitudes of an OUTCOMES program (query kind SIM_QUERY_OUTCOMES) for n output strings:
  * bits holds n rows of n_outer bytes (0/1), row k = y_0 .. y_{n_outer-1}; out[k] =
  * <y|C|0^n> in canonical form, bit-identical to compiling and evaluating the AMPLITUDE query

@@ -52,6 +52,7 @@ from .binding import (  # noqa: F401
     sim_raw_add,
     sim_sample,
     sim_serve_step,
+    sim_serve_enqueue,
     zomega_from_bytes,
 )
 

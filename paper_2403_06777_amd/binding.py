@@ -142,6 +142,10 @@ SIGNATURES = [
                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(sim_zomega),
                                       ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t, _P,
                                       ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
+    ("sim_serve_enqueue", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                                         ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t, _P, ctypes.c_size_t, _P,
+                                         ctypes.POINTER(sim_tuning), _P]),
     ("sim_eval_ranges_static", ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
                                               ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, _P,
                                               ctypes.POINTER(sim_tuning), ctypes.POINTER(sim_zomega)]),
@@ -449,6 +453,19 @@ def sim_serve_step(progs: Sequence[int], first_slices: Sequence[int], n_slices: 
     _check(lib().sim_serve_step(_prog_array(progs), firsts, counts, cz, lz, n, _stream(stream), _tuning(tuning),
                                 outs))
     return [_scalar(outs[i]) if last[i] else outs[i].coeffs() for i in range(n)]
+
+
+def sim_serve_enqueue(progs: Sequence[int], first_slices: Sequence[int], n_slices: Sequence[int],
+                      slots: Sequence[int], flags: Sequence[int], dev_carry: int, n_carry_slots: int, dev_out: int,
+                      stream=None, tuning: Optional[dict] = None):
+    """Enqueues one pipelined serving step (device-resident carried sums; see zxpar.h)."""
+    n = len(progs)
+    firsts = (ctypes.c_uint64 * max(1, n))(*first_slices)
+    counts = (ctypes.c_uint64 * max(1, n))(*n_slices)
+    sl = (ctypes.c_uint32 * max(1, n))(*slots)
+    fl = (ctypes.c_uint8 * max(1, n))(*flags)
+    _check(lib().sim_serve_enqueue(_prog_array(progs), firsts, counts, sl, fl, n, dev_carry, n_carry_slots,
+                                   _stream(stream), _tuning(tuning), dev_out))
 
 
 def sim_eval_ranges_static(progs: Sequence[int], first_slices: Sequence[int], n_slices: Sequence[int],

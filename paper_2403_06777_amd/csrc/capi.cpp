@@ -64,6 +64,15 @@ struct DeviceState {
     std::mutex mu;
     DevBuf ws;                    // the library's scratch region
     void *static_scratch = nullptr;  // this device's address of the fixed array (kStaticScratchBytes)
+    // pipelined serving steps (sim_serve_enqueue): a ring of device regions and pinned staging
+    // buffers, each reused only after the event of its previous step has completed
+    static constexpr int kRing = 4;
+    DevBuf ring_dev[kRing];
+    void *ring_host[kRing] = {nullptr, nullptr, nullptr, nullptr};
+    size_t ring_host_cap[kRing] = {0, 0, 0, 0};
+    hipEvent_t ring_ev[kRing] = {nullptr, nullptr, nullptr, nullptr};
+    bool ring_used[kRing] = {false, false, false, false};
+    unsigned ring_next = 0;
     void *host_result = nullptr;  // pinned
     size_t host_cap = 0;
     void *host_stage = nullptr;   // pinned staging of batch layouts
@@ -818,7 +827,8 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
 int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuning *t, hipStream_t stream,
                   const ImgHeader *d_hdrs, const uint64_t *d_imgs, const WorkItem *d_items,
                   Partial *d_parts, const uint32_t *d_firsts, const uint32_t *d_counts, const FinalArgs *d_args,
-                  DevResult *d_out, bool allow_fork = true, const Partial *d_carry = nullptr) {
+                  DevResult *d_out, bool allow_fork = true, const Partial *d_carry = nullptr,
+                  const uint32_t *d_slots = nullptr, const uint32_t *d_flags = nullptr, DevResult *d_slot_carry = nullptr) {
     const uint32_t threads = pick_threads(t);
     const size_t ng = L.groups.size();
     // kernel variants run concurrently: group k on auxiliary stream k % kAux, forked from and
@@ -848,7 +858,11 @@ int enqueue_batch(DeviceState &D, const BatchLayout &L, size_t n, const sim_tuni
             HIP_TRY(hipStreamWaitEvent(stream, D.ev_join[a], 0));
         }
     }
-    HIP_TRY(launch_finalize_batch(d_parts, d_firsts, d_counts, d_args, (uint32_t)n, d_out, stream, d_carry));
+    if (d_slots)
+        HIP_TRY(launch_serve_finalize(d_parts, d_firsts, d_counts, d_args, d_slots, d_flags, (uint32_t)n, d_slot_carry,
+                                      d_out, stream));
+    else
+        HIP_TRY(launch_finalize_batch(d_parts, d_firsts, d_counts, d_args, (uint32_t)n, d_out, stream, d_carry));
     return SIM_OK;
 }
 
@@ -1706,5 +1720,73 @@ extern "C" int sim_serve_step(const sim_program *const *ps, const uint64_t *firs
         if ((rc = to_zomega(r, &res[i]))) return rc;
     }
     for (size_t i = 0; i < n; ++i) out[i] = res[i];
+    return SIM_OK;
+}
+
+// ------------------------------------------------------------------ pipelined serving step
+
+extern "C" int sim_serve_enqueue(const sim_program *const *ps, const uint64_t *first_slice, const uint64_t *n_slices,
+                                 const uint32_t *slots, const uint8_t *flags, size_t n, void *dev_carry,
+                                 size_t n_carry_slots, void *stream, const sim_tuning *t, sim_zomega *dev_out) {
+    if (n && (!first_slice || !n_slices || !slots || !flags || !dev_carry || !dev_out))
+        return fail(SIM_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(dev_carry) % 8 || reinterpret_cast<uintptr_t>(dev_out) % 8)
+        return fail(SIM_EINVAL, "dev_carry and dev_out must be 8-byte aligned");
+    int dev, rc;
+    if ((rc = check_batch_args(ps, n, &dev))) return rc;
+    if ((rc = check_ranges(ps, n, first_slice, n_slices))) return rc;
+    for (size_t i = 0; i < n; ++i) {
+        if (slots[i] >= n_carry_slots) return fail(SIM_EINVAL, "carry slot out of range");
+        if (flags[i] > 3) return fail(SIM_EINVAL, "flags must be 0 .. 3");
+        for (size_t j = 0; j < i; ++j)
+            if (slots[j] == slots[i]) return fail(SIM_EINVAL, "two requests of one step share a carry slot");
+    }
+    if (!n) return SIM_OK;
+    HIP_TRY(hipSetDevice(dev));
+    DeviceState &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    if ((rc = settle(D))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int r = (int)(D.ring_next++ % DeviceState::kRing);
+    if (!D.ring_ev[r]) HIP_TRY(hipEventCreateWithFlags(&D.ring_ev[r], hipEventDisableTiming));
+    if (D.ring_used[r]) HIP_TRY(hipEventSynchronize(D.ring_ev[r]));  // its previous step is done with it
+    BatchLayout L;
+    if ((rc = build_layout(D, ps, n, first_slice, n_slices, true, t, &L))) return rc;
+    // programs without work (zero programs, empty ranges) still pass through the finaliser
+    const BatchPlan B = plan_batch(L, n, false);
+    const size_t o_slots = align16(B.stage);
+    const size_t o_flags = align16(o_slots + n * 4);
+    const size_t stage = align16(o_flags + n * 4);
+    const size_t o_parts = up256(stage);
+    const size_t total = o_parts + up256(std::max<size_t>(1, L.n_partials) * sizeof(Partial));
+    if ((rc = ensure(D.ring_dev[r], total))) return rc;
+    if (D.ring_host_cap[r] < stage) {
+        if (D.ring_host[r]) (void)hipHostFree(D.ring_host[r]);
+        D.ring_host[r] = nullptr;
+        D.ring_host_cap[r] = 0;
+        const size_t cap = std::max<size_t>(stage, 1 << 16);
+        hipError_t e = hipHostMalloc(&D.ring_host[r], cap, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+        D.ring_host_cap[r] = cap;
+    }
+    char *h = (char *)D.ring_host[r];
+    pack_stage(L, n, B, h);
+    uint32_t *hs = (uint32_t *)(h + o_slots), *hf = (uint32_t *)(h + o_flags);
+    for (size_t i = 0; i < n; ++i) {
+        hs[i] = slots[i];
+        hf[i] = flags[i];
+    }
+    Region R;
+    R.base = (char *)D.ring_dev[r].ptr;
+    R.cap = D.ring_dev[r].cap;
+    HIP_TRY(hipMemcpyAsync(R.base, h, stage, hipMemcpyHostToDevice, st));
+    LayoutPtrs LP = layout_ptrs(B, R, false);
+    LP.parts = (Partial *)(R.base + o_parts);
+    if ((rc = enqueue_batch(D, L, n, t, st, LP.hdrs, LP.imgs, LP.items, LP.parts, LP.firsts, LP.counts, LP.args,
+                            reinterpret_cast<DevResult *>(dev_out), true, nullptr, (const uint32_t *)(R.base + o_slots),
+                            (const uint32_t *)(R.base + o_flags), reinterpret_cast<DevResult *>(dev_carry))))
+        return rc;
+    HIP_TRY(hipEventRecord(D.ring_ev[r], st));
+    D.ring_used[r] = true;
     return SIM_OK;
 }

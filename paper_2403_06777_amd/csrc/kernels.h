@@ -60,6 +60,12 @@ hipError_t launch_finalize_batch(const Partial *partials, const uint32_t *d_item
 constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
 hipError_t static_scratch_address(void **ptr);
 
+// serving step finaliser: program k adds carry[slots[k]] (unless flags bit 0) to its partials and
+// writes the raw sum back there, or (flags bit 1) finalises it into d_out[k]
+hipError_t launch_serve_finalize(const Partial *partials, const uint32_t *d_item_first, const uint32_t *d_item_count,
+                                 const FinalArgs *d_args, const uint32_t *d_slots, const uint32_t *d_flags,
+                                 uint32_t n_progs, DevResult *d_carry, DevResult *d_out, hipStream_t stream);
+
 // resident blocks per compute unit of the single-program evaluation kernel of H
 hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
 

@@ -78,7 +78,35 @@ __global__ __launch_bounds__(kMaxThreads) void k_finalize_batch(const Partial *_
     finalize_range(partials, item_first[k], item_count[k], args[k], out + k, carry ? carry + k : nullptr);
 }
 
+// One serving step's finaliser: program k adds its partials to its carried raw sum (slot
+// slots[k] of carry, read unless flags bit 0 says its first step) and writes the result back to
+// that slot as a raw sum, or, when flags bit 1 says its last step, finalises it into out[k].
+__global__ __launch_bounds__(kMaxThreads) void k_serve_finalize(const Partial *__restrict__ partials,
+                                                                const uint32_t *__restrict__ item_first,
+                                                                const uint32_t *__restrict__ item_count,
+                                                                const FinalArgs *__restrict__ args,
+                                                                const uint32_t *__restrict__ slots,
+                                                                const uint32_t *__restrict__ flags,
+                                                                DevResult *carry, DevResult *__restrict__ out) {
+    const uint32_t k = blockIdx.x;
+    const uint32_t f = flags[k];
+    DevResult *slot = carry + slots[k];
+    FinalArgs a = args[k];
+    a.raw = (f & 2u) ? 0u : 1u;
+    finalize_range(partials, item_first[k], item_count[k], a, (f & 2u) ? out + k : slot,
+                   (f & 1u) ? nullptr : reinterpret_cast<const Partial *>(slot));
+}
+
 }  // namespace
+
+hipError_t launch_serve_finalize(const Partial *partials, const uint32_t *d_item_first, const uint32_t *d_item_count,
+                                 const FinalArgs *d_args, const uint32_t *d_slots, const uint32_t *d_flags,
+                                 uint32_t n_progs, DevResult *d_carry, DevResult *d_out, hipStream_t stream) {
+    if (n_progs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_serve_finalize, dim3(n_progs), dim3(kMaxThreads), 0, stream, partials, d_item_first,
+                       d_item_count, d_args, d_slots, d_flags, d_carry, d_out);
+    return hipGetLastError();
+}
 
 size_t dyn_lds_bytes(const ImgHeader &H) {
     const size_t base = H.acc == ACC_CLASS ? (size_t)H.zero_entry * H.q_limbs * 8 : (size_t)H.table_n * 32;

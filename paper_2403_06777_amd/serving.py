@@ -9,9 +9,10 @@ sum carried from its earlier ticks, and the requests whose last slices are in th
 finalised in the same step and answered.  Requests that arrive while others are on the GPU
 join the next tick: their work overlaps on the device with the requests already running.
 
-Shares are size-aware: every active request gets a floor share of the tick, and the rest of
-it goes to the requests with the least work left, whole (shortest remaining first), so small
-requests finish in the tick after their arrival while large ones keep moving.
+Shares are size-aware: small requests take their whole remainder in the next tick (they do
+not wait behind large ones), every request moves each tick, and the rest of the tick goes to
+the large requests oldest first, in large chunks.  Up to `pipeline_depth` ticks are in flight on
+the device, so the host prepares the next one while the device runs.
 
 Because partial sums over disjoint slices add exactly in Z[w], a result does not depend
 on how its slices were chunked or which other requests shared its launches: it is
@@ -80,6 +81,38 @@ class ZxBackend:
 
     def step(self, handles, firsts, counts, carries, last):
         return B.sim_serve_step(handles, firsts, counts, carries, last, self.stream, self.tuning)
+
+    # pipelined steps: carried sums in device slots, results copied back asynchronously
+    def open_pipeline(self, n_slots: int):
+        import torch
+        self._torch = torch
+        self._st = self.stream if self.stream is not None else torch.cuda.current_stream()
+        self._n_slots = n_slots
+        self._carry = torch.zeros(72 * n_slots + 256, dtype=torch.uint8, device="cuda")
+
+    def enqueue_step(self, handles, firsts, counts, slots, flags):
+        torch = self._torch
+        n = len(handles)
+        out = torch.empty(72 * n, dtype=torch.uint8, device="cuda")
+        base = self._carry.data_ptr()
+        base += (-base) % 8
+        B.sim_serve_enqueue(handles, firsts, counts, slots, flags, base, self._n_slots, out.data_ptr(), self._st,
+                            self.tuning)
+        host = torch.empty(72 * n, dtype=torch.uint8, pin_memory=True)
+        with torch.cuda.stream(self._st):
+            host.copy_(out, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self._st)
+        return (ev, host, out)
+
+    def step_done(self, ticket) -> bool:
+        return ticket[0].query()
+
+    def step_wait(self, ticket):
+        ticket[0].synchronize()
+
+    def step_result(self, ticket, k: int):
+        return B.zomega_from_bytes(ticket[1][72 * k:72 * (k + 1)].numpy().tobytes())
 
     def raw_add(self, a, b):
         return B.sim_raw_add(a, b)
@@ -180,14 +213,18 @@ class ProgramCache:
 
 
 class Server:
-    def __init__(self, backend, mem_budget: int = 64 << 20, max_active: int = 256, tick_terms: int = 1 << 27,
-                 compile_workers: int = 4, scratch_per_request: int = 4096, alone_terms: int = 1 << 30):
+    def __init__(self, backend, mem_budget: int = 64 << 20, max_active: int = 256, tick_terms: int = 1 << 28,
+                 compile_workers: int = 4, scratch_per_request: int = 4096, alone_terms: int = 1 << 30,
+                 small_terms: int = 1 << 24, lone_terms: int = 1 << 34):
         self.backend = backend
         self.cache = ProgramCache(backend, mem_budget)
         self.max_active = max_active
         self.tick_terms = tick_terms
-        # a request alone on the device up to this many terms runs as one launch of its own
+        self.small_terms = small_terms
+        # a request alone on the device takes up to alone_terms in one tick (the pipelined loop);
+        # a lone request of at most lone_terms with nothing in flight is one blocking launch
         self.alone_terms = alone_terms
+        self.lone_terms = lone_terms
         self.pool = cf.ThreadPoolExecutor(max_workers=compile_workers)
         self.scratch_per_request = scratch_per_request
 
@@ -198,7 +235,9 @@ class Server:
     def _compile(self, req: Request):
         return self.backend.compile(req)
 
-    def run(self, requests: List[Request], realtime: bool = True) -> ServeStats:
+    def run(self, requests: List[Request], realtime: bool = True, pipeline_depth: int = 2) -> ServeStats:
+        if pipeline_depth > 0 and hasattr(self.backend, "enqueue_step"):
+            return self._run_pipelined(requests, realtime, pipeline_depth)
         stats = ServeStats()
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         compiling: Dict[int, Tuple[Request, cf.Future]] = {}
@@ -305,7 +344,7 @@ class Server:
                     time.sleep(wait)
                 continue
             if (len(active) == 1 and not waiting and not compiling and not held and active[0].next_slice == 0
-                    and active[0].req.terms <= self.alone_terms):
+                    and active[0].req.terms <= self.lone_terms):
                 # a lone small request: one launch of its own, as fast as a dedicated queue
                 a = active[0]
                 a.req.result = self.backend.evaluate(a.entry.handle)
@@ -355,31 +394,193 @@ class Server:
         return stats
 
     def _shares(self, active: List[_Active]) -> List[int]:
-        """Slices of each active request in the next tick: a floor of a quarter of an equal
-        share each, then the rest of the tick's terms to the requests with the least work left,
-        each taking all of its remainder while the budget lasts (a request alone takes the larger
-        alone_terms budget)."""
+        """Slices of each active request in the next tick.  Small requests (at most small_terms
+        left) take their whole remainder, so they finish in the tick after their admission
+        instead of waiting behind large ones; every other request moves by at least one slice;
+        the rest of the tick's terms goes to the large requests in arrival order (oldest
+        first), so they finish in about the order a FIFO queue would give them, with large
+        chunks.  A request alone takes the larger alone_terms budget."""
         n = len(active)
         budget = self.alone_terms if n == 1 else self.tick_terms
 
         def per_slice(a):
             return max(1, (1 << a.entry.info["n_params"]) // a.entry.info["n_slices"])
 
-        def left(a):
-            return a.entry.info["n_slices"] - a.next_slice
-
-        floor = max(1, budget // (4 * n))
-        counts = [min(left(a), max(1, floor // per_slice(a))) for a in active]
-        spent = sum(c * per_slice(a) for a, c in zip(active, counts))
-        for k in sorted(range(n), key=lambda k: left(active[k]) * per_slice(active[k])):
+        left = [a.entry.info["n_slices"] - a.next_slice for a in active]
+        ps = [per_slice(a) for a in active]
+        counts = [0] * n
+        spent = 0
+        for k in sorted(range(n), key=lambda k: left[k] * ps[k]):
+            need = left[k] * ps[k]
+            if need > self.small_terms or spent + need > budget:
+                break
+            counts[k] = left[k]
+            spent += need
+        for k in range(n):
+            if counts[k] == 0 and left[k] > 0:
+                counts[k] = 1
+                spent += ps[k]
+        for k in sorted(range(n), key=lambda k: active[k].req.arrival):
             room = budget - spent
             if room <= 0:
                 break
-            a = active[k]
-            extra = min(left(a) - counts[k], room // per_slice(a))
+            extra = min(left[k] - counts[k], room // ps[k])
             counts[k] += extra
-            spent += extra * per_slice(a)
+            spent += extra * ps[k]
         return counts
+
+    def _run_pipelined(self, requests: List[Request], realtime: bool, depth: int) -> ServeStats:
+        """The serving loop with device-resident carried sums: up to `depth` steps are in flight
+        on the device, and the next one is enqueued while they run, so the device never waits for
+        the host between ticks; a request is answered when the step holding its last slices has
+        completed (its result copied back asynchronously)."""
+        stats = ServeStats()
+        be = self.backend
+        be.open_pipeline(self.max_active)
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        compiling: Dict[int, Tuple[Request, cf.Future]] = {}
+        held: "collections.deque[Tuple[Request, int, dict]]" = collections.deque()
+        waiting: "collections.deque[Tuple[Request, _Entry]]" = collections.deque()
+        active: List[_Active] = []
+        inflight: "collections.deque[Tuple[object, List[Tuple[_Active, int]]]]" = collections.deque()
+        free_slots = list(range(self.max_active - 1, -1, -1))
+        slot_of: Dict[int, int] = {}
+        inflight_keys: Dict[Tuple, cf.Future] = {}
+        freed = set()
+        start = time.perf_counter()
+        now = lambda: time.perf_counter() - start  # noqa: E731
+
+        def reject(req, msg):
+            req.status, req.error, req.t_done = "rejected", msg, now()
+            stats.rejected += 1
+
+        def place(req, handle, info) -> bool:
+            key = req.key()
+            ent = self.cache.get(key)
+            if ent is None:
+                need = int(info["image_bytes"]) + self.scratch_per_request
+                if need > self.cache.budget:
+                    if handle not in freed:
+                        be.free(handle)
+                        freed.add(handle)
+                    inflight_keys.pop(key, None)
+                    reject(req, "SIM_EBUSY: program exceeds the device-memory budget")
+                    return True
+                if not self.cache.make_room(need):
+                    return False
+                ent = _Entry(handle, info, need)
+                self.cache.put(key, ent)
+            inflight_keys.pop(key, None)
+            ent.users += 1
+            waiting.append((req, ent))
+            return True
+
+        while pending or compiling or held or waiting or active or inflight:
+            t = now()
+            while pending and (pending[0].arrival <= t or not realtime):
+                req = pending.popleft()
+                key = req.key()
+                ent = self.cache.get(key)
+                if ent is not None:
+                    stats.cache_hits += 1
+                    ent.users += 1
+                    waiting.append((req, ent))
+                    continue
+                fut = inflight_keys.get(key)
+                if fut is None:
+                    idle = not (active or waiting or compiling or held or inflight)
+                    if idle and not (pending and (pending[0].arrival <= t or not realtime)):
+                        fut = cf.Future()
+                        try:
+                            fut.set_result(self._compile(req))
+                        except B.SimError as e:
+                            fut.set_exception(e)
+                    else:
+                        fut = self.pool.submit(self._compile, req)
+                    inflight_keys[key] = fut
+                compiling[req.rid] = (req, fut)
+            for rid in list(compiling.keys()):
+                req, fut = compiling[rid]
+                if not fut.done():
+                    continue
+                del compiling[rid]
+                try:
+                    handle, info = fut.result()
+                except B.SimError as e:
+                    inflight_keys.pop(req.key(), None)
+                    reject(req, str(e))
+                    continue
+                if not place(req, handle, info):
+                    stats.held_for_memory += 1
+                    held.append((req, handle, info))
+            for _ in range(len(held)):
+                req, handle, info = held.popleft()
+                if not place(req, handle, info):
+                    held.append((req, handle, info))
+            # completed steps: answer the requests whose last slices they held
+            while inflight and be.step_done(inflight[0][0]):
+                ticket, fin = inflight.popleft()
+                t_done = now()
+                for a, k in fin:
+                    a.req.result = be.step_result(ticket, k)
+                    free_slots.append(slot_of.pop(a.req.rid))
+                    self._finish(a.req, a.entry, stats, t_done)
+            # admission to a slot (each active request owns a carry slot until it is answered)
+            while waiting and free_slots:
+                req, ent = waiting.popleft()
+                req.t_admit = now()
+                req.p = ent.info["n_params"]
+                req.terms = 1 << req.p
+                if ent.info["is_zero"]:
+                    req.result = be.finalize(ent.handle, (0, 0, 0, 0))
+                    self._finish(req, ent, stats, now())
+                    continue
+                slot_of[req.rid] = free_slots.pop()
+                active.append(_Active(req, ent))
+            if (len(active) == 1 and not inflight and not waiting and not compiling and not held
+                    and active[0].next_slice == 0 and active[0].req.terms <= self.lone_terms):
+                # a lone small request: one launch of its own
+                a = active[0]
+                a.req.result = be.evaluate(a.entry.handle)
+                stats.ticks += 1
+                free_slots.append(slot_of.pop(a.req.rid))
+                self._finish(a.req, a.entry, stats, now())
+                active = []
+                continue
+            if active and len(inflight) < depth:
+                counts = self._shares(active)
+                handles = [a.entry.handle for a in active]
+                firsts = [a.next_slice for a in active]
+                slots = [slot_of[a.req.rid] for a in active]
+                flags, fin, still = [], [], []
+                for k, (a, c) in enumerate(zip(active, counts)):
+                    last = a.next_slice + c >= a.entry.info["n_slices"]
+                    flags.append((1 if a.next_slice == 0 else 0) | (2 if last else 0))
+                    a.next_slice += c
+                    (fin if last else still).append((a, k) if last else a)
+                ticket = be.enqueue_step(handles, firsts, counts, slots, flags)
+                stats.ticks += 1
+                inflight.append((ticket, fin))
+                active = still
+                continue
+            if inflight:
+                # nothing else to enqueue: wait for the oldest step unless the host has work soon
+                if not (compiling or (pending and realtime and pending[0].arrival - now() < 2e-4)):
+                    be.step_wait(inflight[0][0])
+                else:
+                    time.sleep(0.00005)
+                continue
+            wait = 0.05
+            if pending and realtime:
+                wait = min(wait, max(0.0, pending[0].arrival - now()))
+            if compiling:
+                cf.wait([f for _, f in compiling.values()], timeout=wait, return_when=cf.FIRST_COMPLETED)
+            elif held:
+                time.sleep(0.0002)
+            elif pending and realtime and not waiting and wait > 0:
+                time.sleep(wait)
+        stats.wall = now()
+        return stats
 
     def _finish(self, req: Request, ent: _Entry, stats: ServeStats, t: float):
         ent.users -= 1

@@ -35,6 +35,39 @@ def test_serve_step_carries_and_finalises(o2):
             zx.sim_program_free(h)
 
 
+def test_pipelined_steps_carry_on_the_device(o2):
+    # three steps enqueued back to back without waiting (device-resident carried sums in slots
+    # 5 and 2 of 8), a third program finished in one step; results equal the single evaluations
+    import torch
+    texts = [wl.kernel_sized_program(5, p=18, n_factors=30, n_monomials=60).to_text(),
+             wl.random_program(6, 14, n_nodes=12, n_pairs=1, n_lin=4, n_mono=20, scalar_range=2).to_text(),
+             wl.kernel_sized_program(7, p=12, n_factors=20, n_monomials=30).to_text()]
+    hs = [zx.sim_program_from_ir(t) for t in texts]
+    try:
+        want = [zx.sim_eval_amplitude(h) for h in hs]
+        ns = [zx.sim_program_info(h)["n_slices"] for h in hs[:2]]
+        cuts = [[0, n // 3, n // 2, n] for n in ns]
+        carry = torch.zeros(8 * 72, dtype=torch.uint8, device="cuda")
+        outs = [torch.zeros(3 * 72, dtype=torch.uint8, device="cuda") for _ in range(3)]
+        s = torch.cuda.current_stream()
+        for k in range(3):
+            progs = hs[:2] + ([hs[2]] if k == 1 else [])
+            firsts = [c[k] for c in cuts] + ([0] if k == 1 else [])
+            counts = [c[k + 1] - c[k] for c in cuts] + ([zx.sim_program_info(hs[2])["n_slices"]] if k == 1 else [])
+            flags = [(1 if k == 0 else 0) | (2 if k == 2 else 0)] * 2 + ([3] if k == 1 else [])
+            zx.sim_serve_enqueue(progs, firsts, counts, [5, 2] + ([0] if k == 1 else []), flags, carry.data_ptr(), 8,
+                                 outs[k].data_ptr(), s)
+        torch.cuda.synchronize()
+        last = zx.zomegas_from_bytes(outs[2].cpu().numpy().tobytes(), 2)
+        assert last == want[:2]
+        assert zx.zomegas_from_bytes(outs[1].cpu().numpy().tobytes(), 3)[2] == want[2]
+        with pytest.raises(zx.SimError):  # one slot twice in a step
+            zx.sim_serve_enqueue(hs[:2], [0, 0], [1, 1], [3, 3], [1, 1], carry.data_ptr(), 8, outs[0].data_ptr(), s)
+    finally:
+        for h in hs:
+            zx.sim_program_free(h)
+
+
 def test_served_results_equal_the_oracle(o2):
     # every served request whose compiled program has at most 22 parameters, against the
     # oracle's evaluation of the same compiled program (its IR text)

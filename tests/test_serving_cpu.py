@@ -171,7 +171,7 @@ def test_small_requests_overtake_a_large_one():
     sizes = {0: 20}
     be = StepBackend(p_of=lambda req: sizes.get(req.rid, 10))
     srv = S.Server(be, mem_budget=1 << 30, max_active=8, tick_terms=1 << 14, compile_workers=1,
-                   alone_terms=1 << 14)
+                   alone_terms=1 << 14, lone_terms=1 << 14)
     reqs = _reqs(6)
     st = srv.run(reqs, realtime=False)
     assert st.done == 6
@@ -183,3 +183,60 @@ def test_small_requests_overtake_a_large_one():
             else:
                 assert c > 0  # the large one moves in every tick it is active
     assert len(big_ticks) >= (1 << 20) // (1 << 14)
+
+
+class PipeBackend(FakeBackend):
+    """the pipelined interface: carried sums live in slots 'on the device', a step completes a
+    few polls after it was enqueued, results are read per finished request"""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.carry = None
+        self.tickets = []
+        self.max_inflight = 0
+
+    def open_pipeline(self, n_slots):
+        self.carry = [None] * n_slots
+
+    def enqueue_step(self, handles, firsts, counts, slots, flags):
+        assert len(set(slots)) == len(slots)
+        out = {}
+        for k, (h, f, c, s, fl) in enumerate(zip(handles, firsts, counts, slots, flags)):
+            n = self.live[h]["n_slices"]
+            assert 0 <= f and f + c <= n and bool(fl & 2) == (f + c == n) and bool(fl & 1) == (f == 0)
+            prev = (0, 0, 0, 0) if fl & 1 else self.carry[s]
+            assert prev is not None
+            raw = tuple(x + y for x, y in zip(prev, (sum(range(f, f + c)), c, 0, 0)))
+            if fl & 2:
+                out[k] = (raw, 0)
+                self.carry[s] = None
+            else:
+                self.carry[s] = raw
+        t = {"polls": 0, "out": out}
+        self.tickets.append(t)
+        live = sum(1 for x in self.tickets if x["polls"] < 2)
+        self.max_inflight = max(self.max_inflight, live)
+        return t
+
+    def step_done(self, t):
+        t["polls"] += 1
+        return t["polls"] >= 2
+
+    def step_wait(self, t):
+        t["polls"] = 2
+
+    def step_result(self, t, k):
+        return t["out"][k]
+
+
+def test_pipelined_loop_gives_solo_results():
+    be = PipeBackend(p_of=lambda req: 9 + req.rid % 9)
+    srv = S.Server(be, mem_budget=1 << 30, max_active=6, tick_terms=1 << 11, compile_workers=2)
+    reqs = _reqs(60)
+    st = srv.run(reqs, realtime=False, pipeline_depth=3)
+    assert st.done == 60 and st.rejected == 0
+    for r in reqs:
+        n = 1 << (r.p - min(r.p, 4))
+        assert r.result == ((n * (n - 1) // 2, n, 0, 0), 0), r.rid
+    assert be.max_inflight >= 2  # steps overlapped
+    assert all(x is None for x in be.carry)  # every slot released
