@@ -343,11 +343,12 @@ SIM_API int sim_sample(const sim_program *const *progs, size_t K, size_t n, cons
 
 /* Marginal by summing (Fig. 3 left): prog is an OUTCOMES program (k = n_outer query
  * parameters); pattern holds k bytes, 0 or 1 fixing y_i and 2 leaving it free.  out = the sum
- * of |<y|C|0^n>|^2 over the 2^m strings y that match (m = number of free outcomes, at most
- * 20), exactly (products and sum in Z[sqrt2], no rounding), canonical.  The 2^m amplitudes
- * are one batch (the kernels of sim_eval_outcomes); the squares and the sum are taken on the
- * host.  Blocks until done.  SIM_EINVAL on bad arguments, SIM_ERANGE if m > 20 or the exact
- * sum exceeds int128 coefficients. */
+ * of |<y|C|0^n>|^2 over the 2^m strings y that match (m = number of free outcomes, at most 32),
+ * exactly, canonical.  The amplitudes are evaluated in batches of up to 2^16 strings (the
+ * kernels of sim_eval_outcomes) and stay on the device, where their squares (in Z[sqrt2]:
+ * |z|^2 = a + b sqrt2) are added to two 384-bit integer sums; only those come back.  Blocks
+ * until done.  SIM_EINVAL on bad arguments, SIM_ERANGE if m > 32, an amplitude leaves the
+ * 384-bit sums, or the exact sum exceeds int128 coefficients. */
 SIM_API int sim_marginal_sum(const sim_program *prog, const uint8_t *pattern, void *stream,
                              const sim_tuning *t, sim_zomega *out);
 

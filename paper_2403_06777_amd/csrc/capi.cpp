@@ -63,6 +63,7 @@ struct DeviceState {
     int cus = 0;
     std::mutex mu;
     DevBuf ws;                    // the library's scratch region
+    DevBuf msum;                  // sim_marginal_sum: its 384-bit sums and their partials
     void *static_scratch = nullptr;  // this device's address of the fixed array (kStaticScratchBytes)
     // pipelined serving steps (sim_serve_enqueue): a ring of device regions and pinned staging
     // buffers, each reused only after the event of its previous step has completed
@@ -88,6 +89,8 @@ struct DeviceState {
 };
 
 constexpr int kAux = 4;
+// free outcomes a marginal by summing may have (2^m amplitudes, in chunks of 2^16)
+constexpr size_t kMaxMarginalFree = 32;
 
 constexpr int kMaxDevices = 64;
 DeviceState g_dev[kMaxDevices];
@@ -1188,19 +1191,6 @@ int sim_sample(const sim_program *const *progs, size_t K, size_t n, const uint64
 
 namespace {
 
-// |z|^2 = z conj(z) = (c0^2 + c1^2 + c2^2 + c3^2) + (c0 c1 + c1 c2 + c2 c3 - c3 c0) sqrt2: the
-// products z_i z_j w^{i-j} pair up as w + w^-1 = sqrt2, w^3 + w^-3 = -sqrt2, w^2 + w^-2 = 0
-zreal::Real norm2(const Zw &z, int32_t e) {
-    using namespace zreal;
-    BigInt c[4];
-    for (int i = 0; i < 4; ++i) c[i] = BigInt::of(z.c[i]);
-    Real r;
-    r.a = add(add(mul(c[0], c[0]), mul(c[1], c[1])), add(mul(c[2], c[2]), mul(c[3], c[3])));
-    r.b = add(add(mul(c[0], c[1]), mul(c[1], c[2])), add(mul(c[2], c[3]), neg(mul(c[3], c[0]))));
-    r.e = 2 * e;
-    return r;
-}
-
 // canonical (a + b sqrt2) sqrt2^e as a Z[w] element (a, b, 0, -b); false if it exceeds int128
 bool canonical_of(zreal::Real r, Zw *z, int32_t *e) {
     using namespace zreal;
@@ -1259,40 +1249,92 @@ int sim_marginal_sum(const sim_program *P, const uint8_t *pattern, void *stream,
         else return fail(SIM_EINVAL, "pattern bytes must be 0, 1 or 2");
     }
     const size_t m = free_pos.size();
-    if (m > 20) return fail(SIM_ERANGE, "at most 20 summed outcomes");
-    // one slice range per string that matches the pattern (the outcomes are the top bits)
-    const uint32_t low = (uint32_t)(P->pk.hdr.pe - P->pk.hdr.g) - (uint32_t)k;
-    const size_t n = (size_t)1 << m;
-    std::vector<const sim_program *> ps(n, P);
-    std::vector<uint64_t> first(n), count(n, (uint64_t)1 << low);
-    for (size_t r = 0; r < n; ++r) {
-        uint64_t y = fixed;
-        for (size_t j = 0; j < m; ++j) y |= (uint64_t)((r >> j) & 1) << free_pos[j];
-        first[r] = y << low;
+    if (m > kMaxMarginalFree)
+        return fail(SIM_ERANGE, "at most " + std::to_string(kMaxMarginalFree) + " summed outcomes");
+    if (P->pk.zero) {
+        zero_result(out, false);
+        return SIM_OK;
     }
-    std::vector<sim_zomega> amps(n);
-    int rc = run_batch(ps.data(), n, first.data(), count.data(), false, stream, t, amps.data());
+    DeviceState *D;
+    int rc = enter_device(P, &D);
     if (rc) return rc;
-    // the exact sum of |A|^2, at the lowest power of sqrt2 met so far
-    zreal::Real acc;
-    bool any = false;
-    for (size_t r = 0; r < n; ++r) {
-        if (zw_is_zero(zw_of(amps[r]))) continue;
-        zreal::Real v = norm2(zw_of(amps[r]), amps[r].sqrt2_exp);
-        if (!any) {
-            acc = v;
-            any = true;
-            continue;
-        }
-        const int32_t E = std::min(acc.e, v.e);
-        acc = zreal::lower_to(acc, E);
-        v = zreal::lower_to(v, E);
-        acc.a = zreal::add(acc.a, v.a);
-        acc.b = zreal::add(acc.b, v.b);
+    std::lock_guard<std::mutex> lk(D->mu);
+    if ((rc = settle(*D))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // one slice range per string that matches the pattern (the outcomes are the top bits), in
+    // chunks of at most 2^16 strings: each chunk's amplitudes stay on the device, where their
+    // squares are added to two 384-bit sums (the accumulator lives in its own small buffer)
+    const uint32_t low = (uint32_t)(P->pk.hdr.pe - P->pk.hdr.g) - (uint32_t)k;
+    const uint64_t n = (uint64_t)1 << m;
+    const uint64_t chunk = std::min<uint64_t>(n, (uint64_t)1 << 16);
+    const uint32_t n_blocks = (uint32_t)std::min<uint64_t>(256, (chunk + kMaxThreads - 1) / kMaxThreads);
+    const size_t acc_bytes = 2 * 6 * 8, part_off = 256;
+    if ((rc = ensure(D->msum, part_off + (size_t)n_blocks * acc_bytes))) return rc;
+    char *mbase = (char *)D->msum.ptr;
+    {
+        const std::vector<uint8_t> zeros(part_off, 0);
+        HIP_TRY(hipMemcpyAsync(mbase, zeros.data(), part_off, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
     }
+    std::vector<const sim_program *> ps(chunk, P);
+    std::vector<uint64_t> first(chunk), count(chunk, (uint64_t)1 << low);
+    for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
+        const size_t nc = (size_t)std::min<uint64_t>(chunk, n - c0);
+        for (size_t r = 0; r < nc; ++r) {
+            uint64_t y = fixed;
+            const uint64_t idx = c0 + r;
+            for (size_t j = 0; j < m; ++j) y |= ((idx >> j) & 1) << free_pos[j];
+            first[r] = y << low;
+        }
+        BatchLayout L;
+        if ((rc = build_layout(*D, ps.data(), nc, first.data(), count.data(), false, t, &L))) return rc;
+        const BatchPlan B = plan_batch(L, nc, true);
+        Region R;
+        if ((rc = lib_region(*D, B.total, &R))) return rc;
+        if ((rc = upload_stage(*D, L, nc, B, R, true, st, nullptr))) return rc;
+        const LayoutPtrs LP = layout_ptrs(B, R, true);
+        if (!L.live.empty()) {
+            if ((rc = enqueue_batch(*D, L, nc, t, st, LP.hdrs, LP.imgs, LP.items, LP.parts, LP.firsts, LP.counts,
+                                    LP.args, LP.res)))
+                return rc;
+            HIP_TRY(launch_norm2_sum(LP.res, (uint32_t)nc, P->pk.e, (uint64_t *)(mbase + part_off), n_blocks,
+                                     (uint64_t *)mbase, (uint32_t *)(mbase + acc_bytes), st));
+        }
+        // the staging buffers are reused by the next chunk
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    uint64_t host[2 * 6 + 2];
+    HIP_TRY(hipMemcpy(host, mbase, sizeof host, hipMemcpyDeviceToHost));
+    if (((const uint32_t *)(host + 12))[0] & 1u)
+        return fail(SIM_ERANGE, "an amplitude of the marginal leaves the 384-bit sums");
+    auto big_of = [](const uint64_t *w) {  // 384-bit two's complement -> BigInt
+        uint64_t v[6];
+        for (int i = 0; i < 6; ++i) v[i] = w[i];
+        BigInt r;
+        r.neg = (v[5] >> 63) != 0;
+        if (r.neg) {
+            uint64_t carry = 1;
+            for (int i = 0; i < 6; ++i) {
+                const uint64_t x = ~v[i] + carry;
+                carry = (carry && x == 0) ? 1u : 0u;
+                v[i] = x;
+            }
+        }
+        for (int i = 0; i < 6; ++i) {
+            r.m.push_back((uint32_t)v[i]);
+            r.m.push_back((uint32_t)(v[i] >> 32));
+        }
+        r.trim();
+        return r;
+    };
+    zreal::Real acc;
+    acc.a = big_of(host);
+    acc.b = big_of(host + 6);
+    acc.e = 2 * P->pk.e;
     Zw z = zw_zero();
     int32_t e = 0;
-    if (any && !canonical_of(acc, &z, &e)) return fail(SIM_ERANGE, "the marginal exceeds int128");
+    if ((!acc.a.zero() || !acc.b.zero()) && !canonical_of(acc, &z, &e))
+        return fail(SIM_ERANGE, "the marginal exceeds int128");
     *out = zomega_of(z, e);
     return SIM_OK;
 }

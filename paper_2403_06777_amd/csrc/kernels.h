@@ -66,6 +66,13 @@ hipError_t launch_serve_finalize(const Partial *partials, const uint32_t *d_item
                                  const FinalArgs *d_args, const uint32_t *d_slots, const uint32_t *d_flags,
                                  uint32_t n_progs, DevResult *d_carry, DevResult *d_out, hipStream_t stream);
 
+// marginals by summing: d_acc (2 x 6 uint64: the 384-bit two's complement sums a, b) += the sum
+// over the n results of |A|^2 = (a + b sqrt2) 2^e relative to 2^e_ref, through n_blocks partials
+// (2 x 6 uint64 each) in d_part; *d_flags bit 0 is set if an exponent is below e_ref or too far
+// above it (more than 120)
+hipError_t launch_norm2_sum(const DevResult *d_res, uint32_t n, int32_t e_ref, uint64_t *d_part, uint32_t n_blocks,
+                            uint64_t *d_acc, uint32_t *d_flags, hipStream_t stream);
+
 // resident blocks per compute unit of the single-program evaluation kernel of H
 hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
 

@@ -188,21 +188,24 @@ def test_summing_equals_doubling():
 
 
 def test_marginal_sum_arguments_are_checked():
-    n = 22
+    n = 34
     text = f"qubits {n}\n" + "".join(f"h {q}\n" for q in range(n)) + "t 0\nh 0\n"
     h = zx.sim_compile(text, zx.outcomes_query(n))
     c, _ = wl.tiny_circuit(0)
     plain = zx.sim_compile(wl.circuit_text(c), zx.amplitude_query("0" * 6))
     try:
         with pytest.raises(zx.SimError) as ei:
-            zx.sim_marginal_sum(h, "*" * n)
-        assert ei.value.code == -2 and "20 summed" in str(ei.value)
+            zx.sim_marginal_sum(h, "*" * 33 + "0")
+        assert ei.value.code == -2 and "32 summed" in str(ei.value)
         with pytest.raises(zx.SimError) as ei:
             zx.sim_marginal_sum(plain, "*" * 6)
         assert ei.value.code == -1
-        # 20 free outcomes is the limit.  Qubit 0 is in HTH|0> = ((1 + w)|0> + (1 - w)|1>) / 2,
-        # the others in |+>: P(y_0 = 0, y_21 = 1) = (2 + sqrt2) / 8 = (1 + sqrt2) sqrt2^-5
-        assert zx.sim_marginal_sum(h, "0" + "*" * 20 + "1") == ((1, 1, 0, -1), -5)
+        # Qubit 0 is in HTH|0> = ((1 + w)|0> + (1 - w)|1>) / 2, the others in |+>:
+        # P(y_0 = 0, y_23..32 = 0, y_33 = 1) = (2 + sqrt2) / 4 * 2^-11 = (1 + sqrt2) sqrt2^-25,
+        # summed over 2^22 strings (64 batches of 2^16 amplitudes, squares added on the device);
+        # with qubit 0 free and 16 qubits fixed it is 2^-16
+        assert zx.sim_marginal_sum(h, "0" + "*" * 22 + "0" * 10 + "1") == ((1, 1, 0, -1), -25)
+        assert zx.sim_marginal_sum(h, "*" * 18 + "1" * 16) == ((1, 0, 0, 0), -32)
     finally:
         zx.sim_program_free(h)
         zx.sim_program_free(plain)
