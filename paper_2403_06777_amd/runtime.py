@@ -1,8 +1,9 @@
 """Batch runtime: autotuned launch shapes and replayable batch plans.
 
-A batch of compiled programs is evaluated by one persistent launch per kernel variant; the
-launch sequence is captured once into a hipGraph by the library (sim_batch_plan_create) and
-replayed.  The autotuner times a few launch shapes (threads per workgroup, resident
+A batch of compiled programs is cut into work items of about 2^chunk_log2 terms (slice ranges
+of one program); each kernel variant takes its items in one launch, one workgroup per item, and
+programs of 2^26 terms or more get resident-grid launches of their own.  The launch sequence is
+captured once into a hipGraph by the library (sim_batch_plan_create) and replayed.  The autotuner times a few launch shapes (threads per workgroup, resident
 workgroups per CU, terms per work item) on the actual batch and caches the winner under a
 key that summarises the batch (parameter-count histogram and form widths).
 """
