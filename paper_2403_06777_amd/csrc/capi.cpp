@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -28,6 +29,10 @@ struct sim_program {
     IrProgram ir;
     PackedProgram pk;
     void *dimg = nullptr;
+    // the image goes up asynchronously (the device's upload stream); launches wait for this
+    // event once, the first time the program is used
+    hipEvent_t up_ev = nullptr;
+    mutable std::atomic<bool> uploaded{false};
     double compile_seconds = 0.0;
     uint32_t t_count = 0;
     uint32_t n_constraints = 0;
@@ -65,6 +70,9 @@ struct DeviceState {
     DevBuf ws;                    // the library's scratch region
     DevBuf msum;                  // sim_marginal_sum: its 384-bit sums and their partials
     void *static_scratch = nullptr;  // this device's address of the fixed array (kStaticScratchBytes)
+    // program images are copied on a stream of their own (non-blocking, default priority), so
+    // creating a program never waits behind evaluations already enqueued on other streams
+    hipStream_t upload = nullptr;
     // pipelined serving steps (sim_serve_enqueue): a ring of device regions and pinned staging
     // buffers, each reused only after the event of its previous step has completed
     static constexpr int kRing = 4;
@@ -152,6 +160,7 @@ int init_device(int dev) {
     void *sp = nullptr;
     HIP_TRY(static_scratch_address(&sp));
     D.static_scratch = sp;
+    HIP_TRY(hipStreamCreateWithFlags(&D.upload, hipStreamNonBlocking));
     D.ready = true;
     return SIM_OK;
 }
@@ -171,6 +180,11 @@ FinalArgs final_args(const PackedProgram &pk, bool raw) {
     a.e = pk.e;
     a.raw = raw ? 1u : 0u;
     a.zero = pk.zero ? 1u : 0u;
+    // +-w^k (one coefficient +-1, the others 0): w^k or w^(k + 4)
+    int nz = 0, at = 0;
+    for (int k = 0; k < 4; ++k)
+        if (pk.c0.c[k] != 0) ++nz, at = k;
+    if (nz == 1 && (pk.c0.c[at] == 1 || pk.c0.c[at] == -1)) a.unit = (uint32_t)(at + (pk.c0.c[at] < 0 ? 4 : 0)) + 1u;
     return a;
 }
 
@@ -295,6 +309,8 @@ struct EventPair {
     }
 };
 
+int await_upload(const sim_program *P);
+
 // Blocking evaluation of one slice range in region R (laid out by S): kernel, finaliser, copy of
 // the 72-byte result to host memory (`pinned` staging of the library, or a pageable copy) and a
 // wait on the stream.  Device lock held.
@@ -302,6 +318,8 @@ int eval_single(const sim_program *P, uint64_t first, uint64_t count, bool raw, 
                 void *pinned, hipStream_t stream, sim_zomega *out, float *kernel_ms = nullptr) {
     Partial *parts = (Partial *)R.base;
     DevResult *dres = (DevResult *)(R.base + S.o_res);
+    int rc = await_upload(P);
+    if (rc) return rc;
     EventPair ev;
     if (kernel_ms) {
         HIP_TRY(hipEventCreate(&ev.a));
@@ -340,13 +358,28 @@ int finish_program(std::unique_ptr<sim_program> &P, sim_program **out, bool elim
     P->device = dev;
     hipError_t e = hipMalloc(&P->dimg, P->pk.blob.size());
     if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
-    e = hipMemcpy(P->dimg, P->pk.blob.data(), P->pk.blob.size(), hipMemcpyHostToDevice);
+    // the host blob stays alive with the program, so the copy may still be in flight on return
+    const hipStream_t up = g_dev[dev].upload;
+    e = hipEventCreateWithFlags(&P->up_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->dimg, P->pk.blob.data(), P->pk.blob.size(), hipMemcpyHostToDevice, up);
+    if (e == hipSuccess) e = hipEventRecord(P->up_ev, up);
     if (e != hipSuccess) {
+        (void)hipStreamSynchronize(up);
+        if (P->up_ev) (void)hipEventDestroy(P->up_ev);
         (void)hipFree(P->dimg);
         P->dimg = nullptr;
-        return fail(SIM_EDEVICE, std::string("hipMemcpy failed: ") + hipGetErrorString(e));
+        return fail(SIM_EDEVICE, std::string("program upload failed: ") + hipGetErrorString(e));
     }
     *out = P.release();
+    return SIM_OK;
+}
+
+// the program's image is on the device: waits (host) for its upload the first time only.  A
+// host wait rather than a stream wait keeps every launch path capturable.
+int await_upload(const sim_program *P) {
+    if (P->uploaded.load(std::memory_order_acquire)) return SIM_OK;
+    HIP_TRY(hipEventSynchronize(P->up_ev));
+    P->uploaded.store(true, std::memory_order_release);
     return SIM_OK;
 }
 
@@ -598,6 +631,7 @@ int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, v
     if ((rc = plan_single(*D, P, P->pk.n_slices, nullptr, &S))) return rc;
     // growing the scratch frees the old buffer: lib_region waits for enqueued work first
     if ((rc = lib_region(*D, S.o_res, &R))) return rc;
+    if ((rc = await_upload(P))) return rc;
     if (D->pending && D->pending_stream != st) HIP_TRY(hipStreamWaitEvent(st, D->ev_pending, 0));
     Partial *parts = (Partial *)R.base;
     if (ev_before) HIP_TRY(hipEventRecord((hipEvent_t)ev_before, st));
@@ -680,6 +714,10 @@ void sim_program_free(sim_program *P) {
         int cur = 0;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(P->device);
+        if (P->up_ev) {
+            (void)hipEventSynchronize(P->up_ev);
+            (void)hipEventDestroy(P->up_ev);
+        }
         (void)hipFree(P->dimg);
         (void)hipSetDevice(cur);
     }
@@ -737,6 +775,7 @@ int build_layout(DeviceState &D, const sim_program *const *ps, size_t n, const u
     for (size_t i = 0; i < n; ++i) {
         const sim_program *P = ps[i];
         L->hdrs[i] = P->pk.hdr;
+        if (int rc = await_upload(P)) return rc;
         L->imgs[i] = (uint64_t)(uintptr_t)P->dimg;
         L->args[i] = final_args(P->pk, raw);
         uint64_t cnt = n_slices ? n_slices[i] : P->pk.n_slices;

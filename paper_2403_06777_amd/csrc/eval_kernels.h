@@ -406,64 +406,80 @@ __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32
     }
 }
 
-// form_fields for one half of a 64-term block (hsel 0: steps 0..31, 1: steps 32..63): the
-// patterns' word hsel only, and the four field words of that half
+// form_fields for one half of a 64-term block (steps 0..31 or 32..63), from that half's table
+// (ht: two-form entries from word 0, three-form entries from word off3): the patterns' one
+// word of the half, and the four field words of that half.  gb holds the 15 group bounds.
 template <int C, bool DEG3>
-__device__ __forceinline__ void fm_group_half(CV8 *fe, uint32_t e0, uint32_t e1, uint32_t O, uint32_t hsel,
-                                              uint32_t &c0, uint32_t &c1, uint32_t &c2) {
-    auto one = [&](const u32x8 &E) {
-        const uint32_t h = E[0];
-        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, (h >> 16) & 0xFFu, 1u);
-        const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, h >> 24, 1u);
-        uint32_t P = ((hsel ? E[3] : E[2]) ^ m1) & ((hsel ? E[5] : E[4]) ^ m2);
-        if (DEG3) P &= (hsel ? E[7] : E[6]) ^ (uint32_t)__builtin_amdgcn_sbfe((int)O, E[1], 1u);
+__device__ __forceinline__ void fmh_group(CU32 *t, uint32_t e0, uint32_t e1, uint32_t O, uint32_t &c0,
+                                          uint32_t &c1, uint32_t &c2) {
+    auto one = [&](uint32_t j1, uint32_t j2, uint32_t j3, uint32_t l1, uint32_t l2, uint32_t l3) {
+        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, j1, 1u);
+        const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, j2, 1u);
+        uint32_t P = (l1 ^ m1) & (l2 ^ m2);
+        if (DEG3) P &= l3 ^ (uint32_t)__builtin_amdgcn_sbfe((int)O, j3, 1u);
         if (C & 1) {
-            const uint32_t t = c0 & P;
+            const uint32_t a = c0 & P;
             c0 ^= P;
-            const uint32_t u = c1 & t;
-            c1 ^= t;
+            const uint32_t u = c1 & a;
+            c1 ^= a;
             c2 ^= u;
         }
         if (C & 2) {
-            const uint32_t t = c1 & P;
+            const uint32_t a = c1 & P;
             c1 ^= P;
-            c2 ^= t;
+            c2 ^= a;
         }
         if (C & 4) c2 ^= P;
     };
-    uint32_t e = e0;
-    for (; e + 4 <= e1; e += 4) {
-        u32x8 E[4];
+    if (DEG3) {
+        CV8 *p = reinterpret_cast<CV8 *>(t) + e0;
+        CV8 *const end = reinterpret_cast<CV8 *>(t) + e1;
+        for (; p + 4 <= end; p += 4) {
+            u32x8 E[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) E[u] = fe[e + u];
+            for (int u = 0; u < 4; ++u) E[u] = p[u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) one(E[u]);
-    }
-    for (; e < e1; ++e) {
-        const u32x8 E1 = fe[e];
-        one(E1);
+            for (int u = 0; u < 4; ++u) one(E[u][0], E[u][1], E[u][2], E[u][3], E[u][4], E[u][5]);
+        }
+        for (; p < end; ++p) {
+            const u32x8 E1 = *p;
+            one(E1[0], E1[1], E1[2], E1[3], E1[4], E1[5]);
+        }
+    } else {
+        CV4 *p = reinterpret_cast<CV4 *>(t) + e0;
+        CV4 *const end = reinterpret_cast<CV4 *>(t) + e1;
+        for (; p + 8 <= end; p += 8) {
+            u32x4 E[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) E[u] = p[u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) one(E[u][0], E[u][1], 0u, E[u][2], E[u][3], 0u);
+        }
+        for (; p < end; ++p) {
+            const u32x4 E1 = *p;
+            one(E1[0], E1[1], 0u, E1[2], E1[3], 0u);
+        }
     }
 }
 
-__device__ __forceinline__ void form_fields_half(const ImgHeader &H, CU32 *wd, uint32_t O, uint32_t hsel,
-                                                 uint32_t (&ft)[8]) {
+__device__ __forceinline__ void form_fields_half(CU32 *ht, uint32_t off3, const uint32_t (&gb)[15], uint32_t O,
+                                                 uint32_t hsel, uint32_t (&ft)[8]) {
     uint32_t c0 = 0, c1 = 0, c2 = 0;
-    CV8 *fe = reinterpret_cast<CV8 *>(wd + H.off_fmono);
-    CU32 *gb = wd + H.off_fmgrp;
-    fm_group_half<1, false>(fe, gb[0], gb[1], O, hsel, c0, c1, c2);
-    fm_group_half<2, false>(fe, gb[1], gb[2], O, hsel, c0, c1, c2);
-    fm_group_half<3, false>(fe, gb[2], gb[3], O, hsel, c0, c1, c2);
-    fm_group_half<4, false>(fe, gb[3], gb[4], O, hsel, c0, c1, c2);
-    fm_group_half<5, false>(fe, gb[4], gb[5], O, hsel, c0, c1, c2);
-    fm_group_half<6, false>(fe, gb[5], gb[6], O, hsel, c0, c1, c2);
-    fm_group_half<7, false>(fe, gb[6], gb[7], O, hsel, c0, c1, c2);
-    fm_group_half<1, true>(fe, gb[7], gb[8], O, hsel, c0, c1, c2);
-    fm_group_half<2, true>(fe, gb[8], gb[9], O, hsel, c0, c1, c2);
-    fm_group_half<3, true>(fe, gb[9], gb[10], O, hsel, c0, c1, c2);
-    fm_group_half<4, true>(fe, gb[10], gb[11], O, hsel, c0, c1, c2);
-    fm_group_half<5, true>(fe, gb[11], gb[12], O, hsel, c0, c1, c2);
-    fm_group_half<6, true>(fe, gb[12], gb[13], O, hsel, c0, c1, c2);
-    fm_group_half<7, true>(fe, gb[13], gb[14], O, hsel, c0, c1, c2);
+    CU32 *t3 = ht + off3 - 8 * gb[7];  // three-form entry e at t3 + 8 e
+    fmh_group<1, false>(ht, gb[0], gb[1], O, c0, c1, c2);
+    fmh_group<2, false>(ht, gb[1], gb[2], O, c0, c1, c2);
+    fmh_group<3, false>(ht, gb[2], gb[3], O, c0, c1, c2);
+    fmh_group<4, false>(ht, gb[3], gb[4], O, c0, c1, c2);
+    fmh_group<5, false>(ht, gb[4], gb[5], O, c0, c1, c2);
+    fmh_group<6, false>(ht, gb[5], gb[6], O, c0, c1, c2);
+    fmh_group<7, false>(ht, gb[6], gb[7], O, c0, c1, c2);
+    fmh_group<1, true>(t3, gb[7], gb[8], O, c0, c1, c2);
+    fmh_group<2, true>(t3, gb[8], gb[9], O, c0, c1, c2);
+    fmh_group<3, true>(t3, gb[9], gb[10], O, c0, c1, c2);
+    fmh_group<4, true>(t3, gb[10], gb[11], O, c0, c1, c2);
+    fmh_group<5, true>(t3, gb[11], gb[12], O, c0, c1, c2);
+    fmh_group<6, true>(t3, gb[12], gb[13], O, c0, c1, c2);
+    fmh_group<7, true>(t3, gb[13], gb[14], O, c0, c1, c2);
     uint32_t f[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -555,9 +571,18 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     uint32_t gray = (b0 ^ (b0 >> 1)) << KB;  // walk bits at or above KB
     // the outer walk parts of the form monomials' forms at the current walk state (uniform)
     uint32_t G = 0;
+    // the form monomials' 15 group bounds, read once (teams of two waves)
+    uint32_t gbv[15];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) gbv[k] = 0;
     if (MONO && H.n_fmono) {
         CU32 *gc = wd + H.off_gcol;
         for (uint32_t bits = gray; bits; bits &= bits - 1u) G ^= gc[__builtin_ctz(bits)];
+        if (KB == 6 && half) {
+            CU32 *gb = wd + H.off_fmgrp;
+#pragma unroll
+            for (int k = 0; k < 15; ++k) gbv[k] = gb[k];
+        }
     }
     if (MONO && b0) {
         // inner-and-outer monomials already switched on at the start state
@@ -810,7 +835,8 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             uint32_t ft[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             const uint32_t hsel = half - 1u;
             if (MONO && H.n_fmono)
-                form_fields_half(H, wd, Sf ^ G ^ ((b & 1u) ? H.gcol_top : 0u), hsel, ft);
+                form_fields_half(wd + H.off_fmh + hsel * H.fmh_stride, H.fmh_off3, gbv,
+                                 Sf ^ G ^ ((b & 1u) ? H.gcol_top : 0u), hsel, ft);
             if (hsel == 0) {
                 add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + (int)(ft[0] & 7u), acc);
 #pragma unroll

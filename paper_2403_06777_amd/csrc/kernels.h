@@ -12,7 +12,7 @@ struct FinalArgs {
     int32_t e;
     uint32_t raw;   // 1: write the raw sum (no constant, no canonical form)
     uint32_t zero;  // 1: the program is identically zero
-    uint32_t pad;
+    uint32_t unit;  // r + 1 when the constant is exactly w^r (a rotation, no products); 0 otherwise
 };
 
 // device result, laid out exactly like sim_zomega

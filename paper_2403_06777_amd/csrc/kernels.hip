@@ -46,9 +46,30 @@ __device__ void finalize_range(const Partial *partials, uint32_t first, uint32_t
     } else if (A.zero) {
         r = zw_zero();
     } else {
-        Zw c0;
-        for (int k = 0; k < 4; ++k) c0.c[k] = load_i128(A.c0 + 2 * k);
-        if (!zw_mul_checked(c0, sum, &r)) {
+        bool ok;
+        if (A.unit) {
+            // times w^u: u mod 4 negacyclic rotations (w^4 = -1), negated once more when u >= 4
+            const int u = (int)A.unit - 1;
+            const bool neg_all = u >= 4;
+            const int q = u & 3;
+            const i128 lo = (i128)((unsigned __int128)1 << 127);  // the one value without a negation
+            ok = true;
+            for (int k = 0; k < 4; ++k) {
+                const int src = k - q;
+                i128 v = src >= 0 ? sum.c[src] : sum.c[src + 4];
+                const bool neg = (src < 0) != neg_all;
+                if (neg) {
+                    ok = ok && v != lo;
+                    v = -v;
+                }
+                r.c[k] = v;
+            }
+        } else {
+            Zw c0;
+            for (int k = 0; k < 4; ++k) c0.c[k] = load_i128(A.c0 + 2 * k);
+            ok = zw_mul_checked(c0, sum, &r);
+        }
+        if (!ok) {
             flags |= RESULT_FLAG_OVERFLOW;
             r = zw_zero();
         }

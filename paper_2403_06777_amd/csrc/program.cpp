@@ -1469,6 +1469,40 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
             }
         img.push_back(at);
     }
+    // teams of two waves: per half (steps 32h .. 32h + 31 of a block) a table of the entries
+    // with that half's pattern words only and the form indices as whole words (no field
+    // extraction or selection on the scalar unit): two-form entries of 4 words (j1, j2,
+    // lambda1, lambda2), then, 8-aligned, three-form entries of 8 words (j1, j2, j3, lambda1,
+    // lambda2, lambda3, 0, 0), in the main table's order
+    H.off_fmh = H.fmh_stride = H.fmh_off3 = 0;
+    if (H.term_split == 2 && !fmono.empty()) {
+        while (img.size() % 8) img.push_back(0);
+        const uint32_t n2 = img[H.off_fmgrp + 7], n = (uint32_t)fmono.size();
+        H.fmh_off3 = (4 * n2 + 7) / 8 * 8;
+        H.fmh_stride = H.fmh_off3 + 8 * (n - n2);
+        H.off_fmh = (uint32_t)img.size();
+        for (int h = 0; h < 2; ++h) {
+            const size_t base = img.size();
+            img.resize(base + H.fmh_stride, 0u);
+            for (uint32_t e = 0; e < n; ++e) {
+                const uint32_t *src = img.data() + H.off_fmono + 8 * e;
+                const uint32_t j1 = (src[0] >> 16) & 0xFFu, j2 = src[0] >> 24, j3 = src[1];
+                const bool three = e >= n2;
+                uint32_t *dst = img.data() + base + (three ? H.fmh_off3 + 8 * (e - n2) : 4 * e);
+                dst[0] = j1;
+                dst[1] = j2;
+                if (three) {
+                    dst[2] = j3;
+                    dst[3] = src[2 + h];
+                    dst[4] = src[4 + h];
+                    dst[5] = src[6 + h];
+                } else {
+                    dst[2] = src[2 + h];
+                    dst[3] = src[4 + h];
+                }
+            }
+        }
+    }
     H.off_mforms = (uint32_t)img.size();
     for (const auto &f : mforms) {
         const uint64_t hm = g >= 64 ? 0 : f.mask >> g;
