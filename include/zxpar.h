@@ -318,10 +318,11 @@ SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *
  * waiting: the device writes the canonical value to dev_out (memory the caller owns and the
  * device can write, one sim_zomega, 8-byte aligned) when the stream gets there; flags bit
  * SIM_ZOMEGA_OVERFLOW marks an invalid value.  ev_before and ev_after, if not NULL, are
- * hipEvent_t recorded on stream right before and after the evaluation kernel (not the
- * finaliser), for timing.  Calls on one device share its scratch: an enqueued evaluation is
- * ordered before any later call on the device, on any stream (later enqueues on another
- * stream wait for it on the device, other calls on the host).  For pipelines of many
+ * hipEvent_t created with timing that take the start and end time of the evaluation kernel
+ * (not the finaliser) from its own dispatch, with no event packets of their own on the
+ * stream.  Calls on one device share its scratch: an enqueued evaluation is ordered before
+ * any later call on the device, on any stream (the later call's stream waits for it on the
+ * device, or the host waits when the call grows the scratch).  For pipelines of many
  * evaluations without a host round trip between them. */
 SIM_API int sim_enqueue_amplitude(const sim_program *prog, void *stream, void *ev_before, void *ev_after,
                                   sim_zomega *dev_out);

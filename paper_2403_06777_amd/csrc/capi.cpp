@@ -180,11 +180,7 @@ FinalArgs final_args(const PackedProgram &pk, bool raw) {
     a.e = pk.e;
     a.raw = raw ? 1u : 0u;
     a.zero = pk.zero ? 1u : 0u;
-    // +-w^k (one coefficient +-1, the others 0): w^k or w^(k + 4)
-    int nz = 0, at = 0;
-    for (int k = 0; k < 4; ++k)
-        if (pk.c0.c[k] != 0) ++nz, at = k;
-    if (nz == 1 && (pk.c0.c[at] == 1 || pk.c0.c[at] == -1)) a.unit = (uint32_t)(at + (pk.c0.c[at] < 0 ? 4 : 0)) + 1u;
+    a.unit = zw_unit_code(pk.c0);
     return a;
 }
 
@@ -253,11 +249,15 @@ struct Region {
 
 // the library's own scratch, grown to at least `need` bytes (work enqueued without waiting
 // still uses it, so that is waited for before the buffer is replaced); device lock held
-int lib_region(DeviceState &D, size_t need, Region *R) {
+// The library's scratch for work on stream st: grown only after enqueued work that uses it has
+// finished (host wait); otherwise st is ordered after such work when that was on another stream.
+int lib_region(DeviceState &D, size_t need, Region *R, hipStream_t st) {
     if (D.ws.cap < need) {
         int rc = settle(D);
         if (rc) return rc;
         if ((rc = ensure(D.ws, need))) return rc;
+    } else if (D.pending && D.pending_stream != st) {
+        HIP_TRY(hipStreamWaitEvent(st, D.ev_pending, 0));
     }
     R->base = (char *)D.ws.ptr;
     R->cap = D.ws.cap;
@@ -324,10 +324,8 @@ int eval_single(const sim_program *P, uint64_t first, uint64_t count, bool raw, 
     if (kernel_ms) {
         HIP_TRY(hipEventCreate(&ev.a));
         HIP_TRY(hipEventCreate(&ev.b));
-        HIP_TRY(hipEventRecord(ev.a, stream));
     }
-    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, first, count, parts, S.blocks, S.threads, stream));
-    if (kernel_ms) HIP_TRY(hipEventRecord(ev.b, stream));
+    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, first, count, parts, S.blocks, S.threads, stream, ev.a, ev.b));
     HIP_TRY(launch_finalize(parts, S.blocks, final_args(P->pk, raw), dres, stream));
     DevResult r;
     HIP_TRY(hipMemcpyAsync(pinned ? pinned : (void *)&r, dres, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
@@ -344,7 +342,7 @@ int eval_range_locked(DeviceState &D, const sim_program *P, uint64_t first, uint
     Region R;
     int rc;
     if ((rc = plan_single(D, P, count, t, &S))) return rc;
-    if ((rc = lib_region(D, S.total, &R))) return rc;
+    if ((rc = lib_region(D, S.total, &R, stream))) return rc;
     if ((rc = ensure_host(D, sizeof(DevResult)))) return rc;
     return eval_single(P, first, count, raw, S, R, D.host_result, stream, out, kernel_ms);
 }
@@ -630,13 +628,11 @@ int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, v
     Region R;
     if ((rc = plan_single(*D, P, P->pk.n_slices, nullptr, &S))) return rc;
     // growing the scratch frees the old buffer: lib_region waits for enqueued work first
-    if ((rc = lib_region(*D, S.o_res, &R))) return rc;
+    if ((rc = lib_region(*D, S.o_res, &R, st))) return rc;
     if ((rc = await_upload(P))) return rc;
-    if (D->pending && D->pending_stream != st) HIP_TRY(hipStreamWaitEvent(st, D->ev_pending, 0));
     Partial *parts = (Partial *)R.base;
-    if (ev_before) HIP_TRY(hipEventRecord((hipEvent_t)ev_before, st));
-    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, 0, P->pk.n_slices, parts, S.blocks, S.threads, st));
-    if (ev_after) HIP_TRY(hipEventRecord((hipEvent_t)ev_after, st));
+    HIP_TRY(launch_eval(P->pk.hdr, P->dimg, 0, P->pk.n_slices, parts, S.blocks, S.threads, st,
+                        (hipEvent_t)ev_before, (hipEvent_t)ev_after));
     HIP_TRY(launch_finalize(parts, S.blocks, final_args(P->pk, false), reinterpret_cast<DevResult *>(dev_out), st));
     HIP_TRY(hipEventRecord(D->ev_pending, st));
     D->pending = true;
@@ -691,7 +687,7 @@ int sim_finalize(const sim_program *P, const sim_zomega *raw, void *stream, sim_
     hipStream_t st = (hipStream_t)stream;
     Region R;
     const size_t o_res = up256(sizeof(Partial));
-    if ((rc = lib_region(*D, o_res + up256(sizeof(DevResult)), &R))) return rc;
+    if ((rc = lib_region(*D, o_res + up256(sizeof(DevResult)), &R, st))) return rc;
     if ((rc = ensure_host(*D, sizeof(DevResult)))) return rc;
     Partial part;
     for (int k = 0; k < 4; ++k) {
@@ -1028,7 +1024,7 @@ int run_batch_locked(DeviceState &D, const sim_program *const *ps, size_t n, con
     Region R;
     const bool lib = given == nullptr;
     if (lib) {
-        if ((rc = lib_region(D, B.total, &R))) return rc;
+        if ((rc = lib_region(D, B.total, &R, st))) return rc;
         if ((rc = ensure_host(D, std::max<size_t>(1, n) * sizeof(DevResult)))) return rc;
     } else {
         if (given->cap < B.total)
@@ -1329,7 +1325,7 @@ int sim_marginal_sum(const sim_program *P, const uint8_t *pattern, void *stream,
         if ((rc = build_layout(*D, ps.data(), nc, first.data(), count.data(), false, t, &L))) return rc;
         const BatchPlan B = plan_batch(L, nc, true);
         Region R;
-        if ((rc = lib_region(*D, B.total, &R))) return rc;
+        if ((rc = lib_region(*D, B.total, &R, st))) return rc;
         if ((rc = upload_stage(*D, L, nc, B, R, true, st, nullptr))) return rc;
         const LayoutPtrs LP = layout_ptrs(B, R, true);
         if (!L.live.empty()) {
@@ -1410,7 +1406,7 @@ int sim_finalize_batch(const sim_program *const *ps, const sim_zomega *raws, siz
     L.n_partials = n;
     const BatchPlan B = plan_batch(L, n, true);
     Region R;
-    if ((rc = lib_region(D, B.total, &R))) return rc;
+    if ((rc = lib_region(D, B.total, &R, st))) return rc;
     if ((rc = ensure_host(D, n * sizeof(DevResult)))) return rc;
     if ((rc = upload_stage(D, L, n, B, R, true, st, nullptr))) return rc;
     const LayoutPtrs LP = layout_ptrs(B, R, true);
@@ -1774,7 +1770,7 @@ extern "C" int sim_serve_step(const sim_program *const *ps, const uint64_t *firs
     // the carried sums follow the results in the same region
     const size_t o_carry = B.total;
     Region R;
-    if ((rc = lib_region(D, o_carry + up256(n * sizeof(Partial)), &R))) return rc;
+    if ((rc = lib_region(D, o_carry + up256(n * sizeof(Partial)), &R, st))) return rc;
     if ((rc = ensure_host(D, n * sizeof(DevResult)))) return rc;
     if ((rc = upload_stage(D, L, n, B, R, true, st, nullptr))) return rc;
     std::vector<Partial> cp(n);

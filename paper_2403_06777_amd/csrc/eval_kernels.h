@@ -21,6 +21,7 @@
 
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "image.h"
@@ -1253,13 +1254,21 @@ hipError_t set_lds(K kern, size_t lds) {
 
 template <int W, bool MONO, int ACC, uint32_t SET>
 hipError_t launch_eval_t(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                         Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
+                         Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream,
+                         hipEvent_t ev_start, hipEvent_t ev_stop) {
     const size_t lds = dyn_lds_bytes(H);
     auto kern = k_eval<W, MONO, ACC, SET>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, H, reinterpret_cast<const uint8_t *>(dimg),
-                       s_begin, s_count, chunk_units_for(H, threads), partials);
+    if (ev_start || ev_stop) {
+        // timed by the dispatch itself: the events take the kernel's start and end
+        hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, ev_start, ev_stop, 0u, H,
+                              reinterpret_cast<const uint8_t *>(dimg), s_begin, s_count,
+                              chunk_units_for(H, threads), partials);
+    } else {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, stream, H, reinterpret_cast<const uint8_t *>(dimg),
+                           s_begin, s_count, chunk_units_for(H, threads), partials);
+    }
     return hipGetLastError();
 }
 
@@ -1314,9 +1323,10 @@ hipError_t launch_batch_t(const ImgHeader &H0, const ImgHeader *d_hdrs, const ui
 
 template <int W, bool MONO>
 hipError_t launch_eval_wm(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
+                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream,
+                          hipEvent_t ev_start, hipEvent_t ev_stop) {
 #define CALL_EVAL(w, m, a, set) \
-    launch_eval_t<w, m, a, set>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
+    launch_eval_t<w, m, a, set>(H, dimg, s_begin, s_count, partials, blocks, threads, stream, ev_start, ev_stop)
     const bool N0_ = H.node_word0 != 0;
     DISPATCH_WM(W, MONO, H.acc, H.slot_menu, CALL_EVAL);
 #undef CALL_EVAL
@@ -1353,7 +1363,8 @@ hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const u
 #define INSTANTIATE_EVAL_WM(w, m)                                                                     \
     template hipError_t occupancy_wm<w, m>(const ImgHeader &, uint32_t, int *);                       \
     template hipError_t launch_eval_wm<w, m>(const ImgHeader &, const void *, uint64_t, uint64_t,     \
-                                             Partial *, uint32_t, uint32_t, hipStream_t);             \
+                                             Partial *, uint32_t, uint32_t, hipStream_t, hipEvent_t,  \
+                                             hipEvent_t);                                             \
     template hipError_t launch_batch_wm<w, m>(const ImgHeader &, const ImgHeader *, const uint64_t *, \
                                               const WorkItem *, uint32_t, Partial *, uint32_t, uint32_t, \
                                               hipStream_t);

@@ -37,8 +37,11 @@ size_t dyn_lds_bytes(const ImgHeader &H);
 // 2^32 terms of at most 2^31 each to a counter between flushes)
 uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads);
 
+// ev_start / ev_stop (optional, timing events): set by the kernel's own dispatch at its start and
+// end (no separate event packets on the stream)
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                       Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
+                       Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream,
+                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 hipError_t launch_finalize(const Partial *partials, uint32_t n, const FinalArgs &args, DevResult *out,
                            hipStream_t stream);
@@ -82,7 +85,8 @@ template <int W, bool MONO>
 hipError_t occupancy_wm(const ImgHeader &H, uint32_t threads, int *blocks_per_cu);
 template <int W, bool MONO>
 hipError_t launch_eval_wm(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream);
+                          Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream,
+                          hipEvent_t ev_start, hipEvent_t ev_stop);
 template <int W, bool MONO>
 hipError_t launch_batch_wm(const ImgHeader &H0, const ImgHeader *d_hdrs, const uint64_t *d_imgs,
                            const WorkItem *d_items, uint32_t n_items, Partial *partials, uint32_t threads,

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 
+#include "final.h"
 #include "image.h"
 #include "kernels.h"
 #include "zw.h"
@@ -38,50 +39,7 @@ __device__ void finalize_range(const Partial *partials, uint32_t first, uint32_t
     if (threadIdx.x != 0) return;
     Zw sum = zw_zero();
     for (int k = 0; k < 4; ++k) sum.c[k] = s_sum[0][k];
-    uint32_t flags = 0;
-    int32_t e = 0;
-    Zw r = sum;
-    if (A.raw) {
-        flags |= RESULT_FLAG_RAW;
-    } else if (A.zero) {
-        r = zw_zero();
-    } else {
-        bool ok;
-        if (A.unit) {
-            // times w^u: u mod 4 negacyclic rotations (w^4 = -1), negated once more when u >= 4
-            const int u = (int)A.unit - 1;
-            const bool neg_all = u >= 4;
-            const int q = u & 3;
-            const i128 lo = (i128)((unsigned __int128)1 << 127);  // the one value without a negation
-            ok = true;
-            for (int k = 0; k < 4; ++k) {
-                const int src = k - q;
-                i128 v = src >= 0 ? sum.c[src] : sum.c[src + 4];
-                const bool neg = (src < 0) != neg_all;
-                if (neg) {
-                    ok = ok && v != lo;
-                    v = -v;
-                }
-                r.c[k] = v;
-            }
-        } else {
-            Zw c0;
-            for (int k = 0; k < 4; ++k) c0.c[k] = load_i128(A.c0 + 2 * k);
-            ok = zw_mul_checked(c0, sum, &r);
-        }
-        if (!ok) {
-            flags |= RESULT_FLAG_OVERFLOW;
-            r = zw_zero();
-        }
-        e = A.e;
-        zw_canonicalise(&r, &e);
-    }
-    for (int k = 0; k < 4; ++k) {
-        out->w[2 * k] = (uint64_t)r.c[k];
-        out->w[2 * k + 1] = (uint64_t)((unsigned __int128)r.c[k] >> 64);
-    }
-    out->e = e;
-    out->flags = flags;
+    finish_sum(sum, A, out);
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_finalize(const Partial *__restrict__ partials, uint32_t n,
@@ -332,11 +290,13 @@ hipError_t eval_occupancy(const ImgHeader &H, uint32_t threads, int *blocks_per_
 }
 
 hipError_t launch_eval(const ImgHeader &H, const void *dimg, uint64_t s_begin, uint64_t s_count,
-                       Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream) {
+                       Partial *partials, uint32_t blocks, uint32_t threads, hipStream_t stream,
+                       hipEvent_t ev_start, hipEvent_t ev_stop) {
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64 || blocks == 0)
         return hipErrorInvalidValue;
     if (dyn_lds_bytes(H) > MAX_TABLE_BYTES) return hipErrorInvalidValue;
-#define CALL_EVAL(w, m) launch_eval_wm<w, m>(H, dimg, s_begin, s_count, partials, blocks, threads, stream)
+#define CALL_EVAL(w, m) \
+    launch_eval_wm<w, m>(H, dimg, s_begin, s_count, partials, blocks, threads, stream, ev_start, ev_stop)
     SWITCH_WM(H, CALL_EVAL);
 #undef CALL_EVAL
 }

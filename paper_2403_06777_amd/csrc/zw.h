@@ -47,6 +47,15 @@ ZW_HD inline Zw zw_rot(Zw z, int k) {
     return z;
 }
 
+// r + 1 when z = w^r exactly (one coefficient +-1, the others 0), else 0
+ZW_HD inline uint32_t zw_unit_code(const Zw &z) {
+    int nz = 0, at = 0;
+    for (int k = 0; k < 4; ++k)
+        if (z.c[k] != 0) ++nz, at = k;
+    if (nz != 1 || (z.c[at] != 1 && z.c[at] != -1)) return 0;
+    return (uint32_t)(at + (z.c[at] < 0 ? 4 : 0)) + 1u;
+}
+
 ZW_HD inline Zw zw_add(const Zw &a, const Zw &b) {
     return zw_make(a.c[0] + b.c[0], a.c[1] + b.c[1], a.c[2] + b.c[2], a.c[3] + b.c[3]);
 }
