@@ -410,63 +410,85 @@ __device__ __forceinline__ void form_fields(const ImgHeader &H, CU32 *wd, uint32
 // form_fields for one half of a 64-term block (steps 0..31 or 32..63), from that half's table
 // (ht: two-form entries from word 0, three-form entries from word off3): the patterns' one
 // word of the half, and the four field words of that half.  gb holds the 15 group bounds.
+//
+// A group (one coefficient C) first counts, per step, how many of its monomials are 1 there
+// (mod 8, three bit planes t) with carry-save adders over four patterns at a time, so the
+// patterns of a batch are independent and the planes take few dependent operations; C * t is
+// then added to the block's planes c once per group.
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) { return (a & b) | (a & c) | (b & c); }
+
+// (c0, c1, c2) += (u0, u1, u2) mod 8, bit-sliced
+__device__ __forceinline__ void planes_add(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t u0, uint32_t u1,
+                                           uint32_t u2) {
+    const uint32_t k1 = c0 & u0;
+    c0 ^= u0;
+    const uint32_t k2 = maj3(c1, u1, k1);
+    c1 ^= u1 ^ k1;
+    c2 ^= u2 ^ k2;
+}
+
+template <int C>
+__device__ __forceinline__ void planes_add_times(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t t0, uint32_t t1,
+                                                 uint32_t t2) {
+    // C * t mod 8 from t, 2t = (0, t0, t1) and 4t = (0, 0, t0)
+    if (C & 1) planes_add(c0, c1, c2, t0, t1, t2);
+    if (C & 2) planes_add(c0, c1, c2, 0u, t0, t1);
+    if (C & 4) c2 ^= t0;
+}
+
 template <int C, bool DEG3>
-__device__ __forceinline__ void fmh_group(CU32 *t, uint32_t e0, uint32_t e1, uint32_t O, uint32_t &c0,
+__device__ __forceinline__ void fmh_group(const uint4 *t, uint32_t e0, uint32_t e1, uint32_t O, uint32_t &c0,
                                           uint32_t &c1, uint32_t &c2) {
-    auto one = [&](uint32_t j1, uint32_t j2, uint32_t j3, uint32_t l1, uint32_t l2, uint32_t l3) {
+    if (e0 >= e1) return;
+    uint32_t t0 = 0, t1 = 0, t2 = 0;
+    auto pat = [&](uint32_t j1, uint32_t j2, uint32_t j3, uint32_t l1, uint32_t l2, uint32_t l3) {
         const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)O, j1, 1u);
         const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)O, j2, 1u);
         uint32_t P = (l1 ^ m1) & (l2 ^ m2);
         if (DEG3) P &= l3 ^ (uint32_t)__builtin_amdgcn_sbfe((int)O, j3, 1u);
-        if (C & 1) {
-            const uint32_t a = c0 & P;
-            c0 ^= P;
-            const uint32_t u = c1 & a;
-            c1 ^= a;
-            c2 ^= u;
-        }
-        if (C & 2) {
-            const uint32_t a = c1 & P;
-            c1 ^= P;
-            c2 ^= a;
-        }
-        if (C & 4) c2 ^= P;
+        return P;
     };
+    auto add4 = [&](uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+        const uint32_t s1 = t0 ^ a ^ b, k1 = maj3(t0, a, b);
+        t0 = s1 ^ c ^ d;
+        const uint32_t k2 = maj3(s1, c, d);
+        t2 ^= maj3(t1, k1, k2);
+        t1 ^= k1 ^ k2;
+    };
+    // the groups are whole batches (padded with null entries), read from LDS with the same
+    // address in every lane (broadcast reads, returned in order)
     if (DEG3) {
-        CV8 *p = reinterpret_cast<CV8 *>(t) + e0;
-        CV8 *const end = reinterpret_cast<CV8 *>(t) + e1;
-        for (; p + 4 <= end; p += 4) {
-            u32x8 E[4];
+        for (uint32_t e = e0; e < e1; e += 4) {
+            uint4 A[4], B[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) E[u] = p[u];
+            for (int u = 0; u < 4; ++u) {
+                A[u] = t[2 * (e + u)];
+                B[u] = t[2 * (e + u) + 1];
+            }
+            uint32_t P[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) one(E[u][0], E[u][1], E[u][2], E[u][3], E[u][4], E[u][5]);
-        }
-        for (; p < end; ++p) {
-            const u32x8 E1 = *p;
-            one(E1[0], E1[1], E1[2], E1[3], E1[4], E1[5]);
+            for (int u = 0; u < 4; ++u) P[u] = pat(A[u].x, A[u].y, A[u].z, A[u].w, B[u].x, B[u].y);
+            add4(P[0], P[1], P[2], P[3]);
         }
     } else {
-        CV4 *p = reinterpret_cast<CV4 *>(t) + e0;
-        CV4 *const end = reinterpret_cast<CV4 *>(t) + e1;
-        for (; p + 8 <= end; p += 8) {
-            u32x4 E[8];
+        for (uint32_t e = e0; e < e1; e += 8) {
+            uint4 E[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) E[u] = p[u];
+            for (int u = 0; u < 8; ++u) E[u] = t[e + u];
+            uint32_t P[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) one(E[u][0], E[u][1], 0u, E[u][2], E[u][3], 0u);
-        }
-        for (; p < end; ++p) {
-            const u32x4 E1 = *p;
-            one(E1[0], E1[1], 0u, E1[2], E1[3], 0u);
+            for (int u = 0; u < 8; ++u) P[u] = pat(E[u].x, E[u].y, 0u, E[u].z, E[u].w, 0u);
+            add4(P[0], P[1], P[2], P[3]);
+            add4(P[4], P[5], P[6], P[7]);
         }
     }
+    planes_add_times<C>(c0, c1, c2, t0, t1, t2);
 }
 
-__device__ __forceinline__ void form_fields_half(CU32 *ht, uint32_t off3, const uint32_t (&gb)[15], uint32_t O,
+__device__ __forceinline__ void form_fields_half(const uint4 *ht, uint32_t off3, const uint32_t (&gb)[16], uint32_t O,
                                                  uint32_t hsel, uint32_t (&ft)[8]) {
     uint32_t c0 = 0, c1 = 0, c2 = 0;
-    CU32 *t3 = ht + off3 - 8 * gb[7];  // three-form entry e at t3 + 8 e
+    const uint4 *t3 = ht + off3 / 4;  // three-form entries
     fmh_group<1, false>(ht, gb[0], gb[1], O, c0, c1, c2);
     fmh_group<2, false>(ht, gb[1], gb[2], O, c0, c1, c2);
     fmh_group<3, false>(ht, gb[2], gb[3], O, c0, c1, c2);
@@ -474,13 +496,13 @@ __device__ __forceinline__ void form_fields_half(CU32 *ht, uint32_t off3, const 
     fmh_group<5, false>(ht, gb[4], gb[5], O, c0, c1, c2);
     fmh_group<6, false>(ht, gb[5], gb[6], O, c0, c1, c2);
     fmh_group<7, false>(ht, gb[6], gb[7], O, c0, c1, c2);
-    fmh_group<1, true>(t3, gb[7], gb[8], O, c0, c1, c2);
-    fmh_group<2, true>(t3, gb[8], gb[9], O, c0, c1, c2);
-    fmh_group<3, true>(t3, gb[9], gb[10], O, c0, c1, c2);
-    fmh_group<4, true>(t3, gb[10], gb[11], O, c0, c1, c2);
-    fmh_group<5, true>(t3, gb[11], gb[12], O, c0, c1, c2);
-    fmh_group<6, true>(t3, gb[12], gb[13], O, c0, c1, c2);
-    fmh_group<7, true>(t3, gb[13], gb[14], O, c0, c1, c2);
+    fmh_group<1, true>(t3, gb[8], gb[9], O, c0, c1, c2);
+    fmh_group<2, true>(t3, gb[9], gb[10], O, c0, c1, c2);
+    fmh_group<3, true>(t3, gb[10], gb[11], O, c0, c1, c2);
+    fmh_group<4, true>(t3, gb[11], gb[12], O, c0, c1, c2);
+    fmh_group<5, true>(t3, gb[12], gb[13], O, c0, c1, c2);
+    fmh_group<6, true>(t3, gb[13], gb[14], O, c0, c1, c2);
+    fmh_group<7, true>(t3, gb[14], gb[15], O, c0, c1, c2);
     uint32_t f[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -572,17 +594,17 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
     uint32_t gray = (b0 ^ (b0 >> 1)) << KB;  // walk bits at or above KB
     // the outer walk parts of the form monomials' forms at the current walk state (uniform)
     uint32_t G = 0;
-    // the form monomials' 15 group bounds, read once (teams of two waves)
-    uint32_t gbv[15];
+    // the form monomials' padded group bounds of the half tables, read once (teams of two waves)
+    uint32_t gbv[16];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) gbv[k] = 0;
+    for (int k = 0; k < 16; ++k) gbv[k] = 0;
     if (MONO && H.n_fmono) {
         CU32 *gc = wd + H.off_gcol;
         for (uint32_t bits = gray; bits; bits &= bits - 1u) G ^= gc[__builtin_ctz(bits)];
         if (KB == 6 && half) {
-            CU32 *gb = wd + H.off_fmgrp;
+            CU32 *gb = wd + H.off_fmh;
 #pragma unroll
-            for (int k = 0; k < 15; ++k) gbv[k] = gb[k];
+            for (int k = 0; k < 16; ++k) gbv[k] = gb[k];
         }
     }
     if (MONO && b0) {
@@ -836,7 +858,9 @@ __device__ __forceinline__ void walk_blocks(const ImgHeader &H, const Slots<W> &
             uint32_t ft[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             const uint32_t hsel = half - 1u;
             if (MONO && H.n_fmono)
-                form_fields_half(wd + H.off_fmh + hsel * H.fmh_stride, H.fmh_off3, gbv,
+                form_fields_half(reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(tab) + H.fmh_lds) +
+                                     (16 + hsel * H.fmh_stride) / 4,
+                                 H.fmh_off3, gbv,
                                  Sf ^ G ^ ((b & 1u) ? H.gcol_top : 0u), hsel, ft);
             if (hsel == 0) {
                 add_term<W, ACC, SET, false, B32>(H, S, tab, cnt, L, phi + (int)(ft[0] & 7u), acc);
@@ -929,7 +953,8 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
             phi += ((s & hm) == hm) ? (int)mh[0] : 0;
         }
         CU32 *aidx = wd + H.off_aidx;
-        for (uint32_t i = 0; i < H.g; ++i) {
+        const uint32_t n_al = aidx[H.g];  // entries of all positions (none: skip the walk)
+        for (uint32_t i = 0; i < (n_al ? H.g : 0u); ++i) {
             int f = 0;
             CU32 *ae = wd + H.off_al + 3 * aidx[i];
             #pragma unroll 4
@@ -1129,6 +1154,13 @@ __device__ __forceinline__ void prepare_lds(const ImgHeader &H, const int64_t *_
         uint32_t *d = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_tab) + H.ztab_lds);
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = words[H.off_ztab + i];
     }
+    if (H.off_fmh) {
+        // the form monomials' half tables (16-byte aligned at both ends)
+        const uint32_t n4 = (16 + 2 * H.fmh_stride) / 4;
+        uint4 *d = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(s_tab) + H.fmh_lds);
+        const uint4 *src = reinterpret_cast<const uint4 *>(words + H.off_fmh);
+        for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x) d[i] = src[i];
+    }
     __syncthreads();
 }
 
@@ -1165,12 +1197,15 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
     const uint32_t half = T == 2 ? (uint32_t)(wave & 1) + 1u : 0u;
     wave /= T;
     n_waves /= T;
-    const uint64_t q = uniform64(n_units / n_waves), r = uniform64(n_units % n_waves);
+    // (32-bit division when the operands fit: the 64-bit one is a long instruction sequence)
+    const bool narrow = (n_units >> 32) == 0 && (n_waves >> 32) == 0;
+    const uint64_t q = uniform64(narrow ? (uint64_t)((uint32_t)n_units / (uint32_t)n_waves) : n_units / n_waves);
+    const uint64_t r = uniform64(n_units - q * n_waves);
     const uint64_t u_begin = uniform64(wave * q + (wave < r ? wave : r));
     const uint64_t u_end = uniform64(u_begin + q + (wave < r ? 1 : 0));
     const uint64_t most = q + (r ? 1 : 0);  // largest run of any wave
     const uint64_t chunk = ACC == ACC_CLASS && chunk_units ? chunk_units : (most ? most : 1);
-    const uint64_t n_chunks = uniform64((most + chunk - 1) / chunk);
+    const uint64_t n_chunks = chunk == most ? (most ? 1u : 0u) : uniform64((most + chunk - 1) / chunk);
     const uint32_t lane = threadIdx.x & 63u;
     for (uint64_t c = 0; c < n_chunks; ++c) {
         const uint64_t c0 = u_begin + c * chunk;

@@ -166,10 +166,13 @@ struct ImgHeader {
     uint32_t n_mforms;
     uint32_t off_fmgrp;   // 15 words: entries [grp[k], grp[k + 1]) have 2 (k < 7) or 3 forms and
                           // coefficient k % 7 + 1 (the entries are sorted so)
-    uint32_t off_fmh;     // term_split 2: two half tables (steps 0..31, 32..63), fmh_stride
-    uint32_t fmh_stride;  //   words apart: entries [0, grp[7]) of 4 words (j1, j2, lambda1,
-    uint32_t fmh_off3;    //   lambda2: that half's pattern word), then at fmh_off3 the entries
-                          //   from grp[7] on, 8 words each (j1, j2, j3, lambda1..3, 0, 0)
+    uint32_t off_fmh;     // term_split 2: 16 words of group bounds (two-form groups d2[0..7],
+    uint32_t fmh_stride;  //   three-form groups d3[0..7], each group padded with null entries
+    uint32_t fmh_off3;    //   to 8 or 4 entries), then two half tables (steps 0..31, 32..63)
+                          //   fmh_stride words apart: two-form entries of 4 words (j1, j2,
+                          //   lambda1, lambda2: that half's pattern word), then at fmh_off3
+                          //   three-form entries of 8 words (j1, j2, j3, lambda1..3, 0, 0);
+    uint32_t fmh_lds;     //   all copied to dynamic LDS at byte offset fmh_lds
     uint32_t off_mforms;  // 4 words each: slice mask lo, hi, constant, 0
     uint32_t off_scol;    // pe - g words: the forms containing slice bit j (S = fm_s0 ^ the
     uint32_t fm_s0;       //   columns of the set slice bits)

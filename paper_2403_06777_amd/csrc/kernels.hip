@@ -253,11 +253,14 @@ hipError_t launch_serve_finalize(const Partial *partials, const uint32_t *d_item
 
 size_t dyn_lds_bytes(const ImgHeader &H) {
     const size_t base = H.acc == ACC_CLASS ? (size_t)H.zero_entry * H.q_limbs * 8 : (size_t)H.table_n * 32;
-    const size_t end = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4 : base;
-    if (!H.ztab_bits) return end;
-    const int kb = inner_bits_for(H.W);
-    const size_t zwords = 4 * (size_t)ztab_slots_for(kb) + ((size_t)1 << kb) * H.W;
-    return std::max(end, (size_t)H.ztab_lds + zwords * 4);
+    size_t end = H.ntab_n ? (size_t)H.ntab_lds + (size_t)H.ntab_n * 4 : base;
+    if (H.ztab_bits) {
+        const int kb = inner_bits_for(H.W);
+        const size_t zwords = 4 * (size_t)ztab_slots_for(kb) + ((size_t)1 << kb) * H.W;
+        end = std::max(end, (size_t)H.ztab_lds + zwords * 4);
+    }
+    if (H.off_fmh) end = std::max(end, (size_t)H.fmh_lds + (16 + 2 * (size_t)H.fmh_stride) * 4);
+    return end;
 }
 
 uint64_t chunk_units_for(const ImgHeader &H, uint32_t threads) {

@@ -1471,35 +1471,60 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
     }
     // teams of two waves: per half (steps 32h .. 32h + 31 of a block) a table of the entries
     // with that half's pattern words only and the form indices as whole words (no field
-    // extraction or selection on the scalar unit): two-form entries of 4 words (j1, j2,
-    // lambda1, lambda2), then, 8-aligned, three-form entries of 8 words (j1, j2, j3, lambda1,
-    // lambda2, lambda3, 0, 0), in the main table's order
+    // extraction or selection on the scalar unit).  Each group is padded with null entries
+    // (pattern m & ~m = 0) to whole batches of the kernel's loop (8 two-form entries, 4
+    // three-form entries), so that no group ends in single loads.  At off_fmh: 16 words of
+    // padded bounds (two-form groups 0..6 in d2[0..7], three-form groups in d3[0..7]), then
+    // the two half tables fmh_stride words apart: two-form entries of 4 words (j1, j2, lambda1,
+    // lambda2), then at fmh_off3 three-form entries of 8 words (j1, j2, j3, lambda1..3, 0, 0).
     H.off_fmh = H.fmh_stride = H.fmh_off3 = 0;
     if (H.term_split == 2 && !fmono.empty()) {
         while (img.size() % 8) img.push_back(0);
-        const uint32_t n2 = img[H.off_fmgrp + 7], n = (uint32_t)fmono.size();
-        H.fmh_off3 = (4 * n2 + 7) / 8 * 8;
-        H.fmh_stride = H.fmh_off3 + 8 * (n - n2);
+        const uint32_t *grp = img.data() + H.off_fmgrp;
+        uint32_t d2[8], d3[8];
+        std::vector<int> src2, src3;  // entry of the main table, -1 for a null entry
+        d2[0] = d3[0] = 0;
+        for (int k = 0; k < 7; ++k) {
+            for (uint32_t e = grp[k]; e < grp[k + 1]; ++e) src2.push_back((int)e);
+            while (src2.size() % 8) src2.push_back(-1);
+            d2[k + 1] = (uint32_t)src2.size();
+            for (uint32_t e = grp[7 + k]; e < grp[8 + k]; ++e) src3.push_back((int)e);
+            while (src3.size() % 4) src3.push_back(-1);
+            d3[k + 1] = (uint32_t)src3.size();
+        }
         H.off_fmh = (uint32_t)img.size();
+        img.insert(img.end(), d2, d2 + 8);
+        img.insert(img.end(), d3, d3 + 8);
+        H.fmh_off3 = 4 * (uint32_t)src2.size();  // a multiple of 32 words
+        H.fmh_stride = H.fmh_off3 + 8 * (uint32_t)src3.size();
         for (int h = 0; h < 2; ++h) {
             const size_t base = img.size();
             img.resize(base + H.fmh_stride, 0u);
-            for (uint32_t e = 0; e < n; ++e) {
-                const uint32_t *src = img.data() + H.off_fmono + 8 * e;
-                const uint32_t j1 = (src[0] >> 16) & 0xFFu, j2 = src[0] >> 24, j3 = src[1];
-                const bool three = e >= n2;
-                uint32_t *dst = img.data() + base + (three ? H.fmh_off3 + 8 * (e - n2) : 4 * e);
-                dst[0] = j1;
-                dst[1] = j2;
-                if (three) {
-                    dst[2] = j3;
-                    dst[3] = src[2 + h];
-                    dst[4] = src[4 + h];
-                    dst[5] = src[6 + h];
-                } else {
-                    dst[2] = src[2 + h];
-                    dst[3] = src[4 + h];
+            for (size_t i = 0; i < src2.size(); ++i) {
+                uint32_t *dst = img.data() + base + 4 * i;
+                if (src2[i] < 0) {
+                    dst[3] = 0xFFFFFFFFu;  // j1 = j2 = 0, lambda1 = 0, lambda2 = ~0
+                    continue;
                 }
+                const uint32_t *src = img.data() + H.off_fmono + 8 * src2[i];
+                dst[0] = (src[0] >> 16) & 0xFFu;
+                dst[1] = src[0] >> 24;
+                dst[2] = src[2 + h];
+                dst[3] = src[4 + h];
+            }
+            for (size_t i = 0; i < src3.size(); ++i) {
+                uint32_t *dst = img.data() + base + H.fmh_off3 + 8 * i;
+                if (src3[i] < 0) {
+                    dst[4] = 0xFFFFFFFFu;  // j1 = j2 = j3 = 0, lambda2 = ~0, the others 0
+                    continue;
+                }
+                const uint32_t *src = img.data() + H.off_fmono + 8 * src3[i];
+                dst[0] = (src[0] >> 16) & 0xFFu;
+                dst[1] = src[0] >> 24;
+                dst[2] = src[1];
+                dst[3] = src[2 + h];
+                dst[4] = src[4 + h];
+                dst[5] = src[6 + h];
             }
         }
     }
@@ -1621,6 +1646,12 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
                 img.insert(img.end(), zt.begin(), zt.end());
                 img.insert(img.end(), pstep.begin(), pstep.end());
             }
+        }
+        // the half tables of the form monomials (two-wave teams) follow every other LDS table
+        H.fmh_lds = 0;
+        if (H.off_fmh) {
+            const size_t end_z = H.ztab_bits ? (size_t)H.ztab_lds + (4 * (size_t)zslots + (size_t)KS * W) * 4 : end_lds;
+            H.fmh_lds = (uint32_t)((end_z + 15) & ~(size_t)15);
         }
     }
     std::vector<int64_t> table((size_t)H.table_n * 4, 0);
