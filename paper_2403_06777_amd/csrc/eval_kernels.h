@@ -1033,27 +1033,40 @@ __device__ __forceinline__ void run_slice(const ImgHeader &H, CU32 *wd, const in
     }
 }
 
-__device__ __forceinline__ i128 shfl_xor_i128(i128 v, int mask) {
+// v moved across lanes by one DPP pattern (four 32-bit moves); lanes the pattern does not
+// write, or whose source is out of range, get 0
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ i128 dpp_i128(i128 v) {
     const unsigned __int128 u = (unsigned __int128)v;
-    uint32_t p0 = (uint32_t)u, p1 = (uint32_t)(u >> 32), p2 = (uint32_t)(u >> 64), p3 = (uint32_t)(u >> 96);
-    p0 = (uint32_t)__shfl_xor((int)p0, mask);
-    p1 = (uint32_t)__shfl_xor((int)p1, mask);
-    p2 = (uint32_t)__shfl_xor((int)p2, mask);
-    p3 = (uint32_t)__shfl_xor((int)p3, mask);
-    const unsigned __int128 r = (unsigned __int128)p0 | ((unsigned __int128)p1 << 32) |
-                                ((unsigned __int128)p2 << 64) | ((unsigned __int128)p3 << 96);
-    return (i128)r;
+    const uint32_t p0 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, BANKS, true);
+    const uint32_t p1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, BANKS, true);
+    const uint32_t p2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 64), CTRL, ROWS, BANKS, true);
+    const uint32_t p3 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 96), CTRL, ROWS, BANKS, true);
+    return (i128)((unsigned __int128)p0 | ((unsigned __int128)p1 << 32) | ((unsigned __int128)p2 << 64) |
+                  ((unsigned __int128)p3 << 96));
 }
 
-// sum of acc over the block (wave shuffles, then LDS in wave order), written by thread 0.
-// Integer addition is associative, so the result does not depend on the order.
+// sum of v over the wave, in lane 63: windows of 4, 8 and 16 lanes within each row of 16
+// (row shifts), then the rows' sums through the row broadcasts of lanes 15 and 31
+__device__ __forceinline__ i128 wave_sum_to_lane63(i128 v) {
+    i128 a = v + dpp_i128<0x111, 0xf, 0xf>(v);   // row_shr:1
+    a += dpp_i128<0x112, 0xf, 0xf>(v);           // row_shr:2
+    a += dpp_i128<0x113, 0xf, 0xf>(v);           // row_shr:3
+    a += dpp_i128<0x114, 0xf, 0xe>(a);           // row_shr:4, lanes 4..15 of a row
+    a += dpp_i128<0x118, 0xf, 0xc>(a);           // row_shr:8, lanes 8..15
+    a += dpp_i128<0x142, 0xa, 0xf>(a);           // row_bcast:15 into rows 1 and 3
+    a += dpp_i128<0x143, 0xc, 0xf>(a);           // row_bcast:31 into rows 2 and 3
+    return a;
+}
+
+// sum of acc over the block (per wave by cross-lane moves, then LDS in wave order), written by
+// thread 0.  Integer addition is associative, so the result does not depend on the order.
 __device__ __forceinline__ void block_reduce_store(i128 (&acc)[4], Partial *out) {
     __shared__ i128 s_red[kMaxThreads / 64][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int off = 32; off > 0; off >>= 1) acc[k] += shfl_xor_i128(acc[k], off);
+    for (int k = 0; k < 4; ++k) acc[k] = wave_sum_to_lane63(acc[k]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s_red[wave][k] = acc[k];
     }
@@ -1195,8 +1208,8 @@ __device__ __forceinline__ void run_range(const ImgHeader &H, const uint8_t *img
     // flag term_split, used when the launch holds whole teams): twice the waves for small grids
     const uint32_t T = (H.term_split == 2 && blocks && !compact && (n_waves & 1) == 0) ? 2u : 1u;
     const uint32_t half = T == 2 ? (uint32_t)(wave & 1) + 1u : 0u;
-    wave /= T;
-    n_waves /= T;
+    wave >>= T - 1u;  // T is 1 or 2: a shift, not a 64-bit division
+    n_waves >>= T - 1u;
     // (32-bit division when the operands fit: the 64-bit one is a long instruction sequence)
     const bool narrow = (n_units >> 32) == 0 && (n_waves >> 32) == 0;
     const uint64_t q = uniform64(narrow ? (uint64_t)((uint32_t)n_units / (uint32_t)n_waves) : n_units / n_waves);
