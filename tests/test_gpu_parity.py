@@ -376,6 +376,27 @@ def test_block_sums_at_the_int32_bound(o2, n_nodes):
     assert gpu_value(text) == oracle_value(o2, text)
 
 
+@pytest.mark.parametrize("n_nodes", [24, 25])
+def test_block_sums_reach_the_int32_bound(o2, n_nodes):
+    # every node factor 1 + w^l on the one top parameter (a slice bit): in a slice with it 0 each
+    # of a 64-term block's terms is exactly 2^n times a phase that is the same across the block
+    # (linear terms on slice bits only, which also make two form words), so with 24 factors a
+    # block sums to 2^30 in a coordinate, the most that 32-bit block sums take; with 25 (2^31,
+    # which int32 cannot hold) the header leaves them off
+    p = 14
+    prog = wl.ProgramSpec(p)
+    f = prog.add_form(0, 1 << (p - 1))
+    for _ in range(n_nodes):
+        prog.nodes.append((f, 0, 1))
+    for m in range(1, 13):
+        prog.lin.append((2 * (m % 4) + 1, prog.add_form(0, (1 << (p - 1)) | (m << (p - 6)))))
+    text = prog.to_text()
+    info = zx.sim_ir_info(text)
+    assert info["n_forms"] > 32 and info["walk_bits"] <= p - 6
+    say("int32 block sums at 2^30 / 2^31", n_nodes)
+    assert gpu_value(text) == oracle_value(o2, text)
+
+
 @pytest.mark.parametrize("case", ["random", "node", "opposite", "constant"])
 def test_weight4_phase_parts_combined(o2, case):
     # the weight-4 parts of the linear phase terms as one form: beside node tables of 1 to 10
