@@ -24,6 +24,8 @@ ZxBackend is the real one over the C-ABI.
 
 import collections
 import concurrent.futures as cf
+import contextlib
+import gc
 import hashlib
 import time
 from dataclasses import dataclass, field
@@ -212,6 +214,21 @@ class ProgramCache:
         self.used = 0
 
 
+@contextlib.contextmanager
+def _collector_paused():
+    """Pauses Python's cyclic garbage collector for the duration of a serving loop (both
+    servers below): its full passes walk every object of the process and can stall a loop for
+    tens of milliseconds, which shows up as tail latency.  The loops create no reference cycles
+    that need it; it is restored (and runs as usual) afterwards."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
 class Server:
     def __init__(self, backend, mem_budget: int = 64 << 20, max_active: int = 256, tick_terms: int = 1 << 28,
                  compile_workers: int = 4, scratch_per_request: int = 4096, alone_terms: int = 1 << 30,
@@ -236,8 +253,13 @@ class Server:
         return self.backend.compile(req)
 
     def run(self, requests: List[Request], realtime: bool = True, pipeline_depth: int = 2) -> ServeStats:
-        if pipeline_depth > 0 and hasattr(self.backend, "enqueue_step"):
-            return self._run_pipelined(requests, realtime, pipeline_depth)
+        with _collector_paused():
+            if pipeline_depth > 0 and hasattr(self.backend, "enqueue_step"):
+                return self._run_pipelined(requests, realtime, pipeline_depth)
+            return self._run_ticks(requests, realtime)
+
+    def _run_ticks(self, requests: List[Request], realtime: bool) -> ServeStats:
+        """The serving loop with one blocking device step per tick (backends without enqueue)."""
         stats = ServeStats()
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         compiling: Dict[int, Tuple[Request, cf.Future]] = {}
@@ -594,6 +616,11 @@ class Server:
 def run_fifo(backend, requests: List[Request], realtime: bool = True, cache_budget: int = 64 << 20) -> ServeStats:
     """Baseline: one request at a time in arrival order, compiled (with the same resident
     program cache) and evaluated by one launch of its own."""
+    with _collector_paused():
+        return _run_fifo(backend, requests, realtime, cache_budget)
+
+
+def _run_fifo(backend, requests: List[Request], realtime: bool, cache_budget: int) -> ServeStats:
     stats = ServeStats()
     cache = ProgramCache(backend, cache_budget)
     start = time.perf_counter()
