@@ -247,10 +247,9 @@ struct Region {
     size_t cap = 0;
 };
 
-// the library's own scratch, grown to at least `need` bytes (work enqueued without waiting
-// still uses it, so that is waited for before the buffer is replaced); device lock held
-// The library's scratch for work on stream st: grown only after enqueued work that uses it has
-// finished (host wait); otherwise st is ordered after such work when that was on another stream.
+// The library's scratch for work on stream st, at least `need` bytes (device lock held): grown
+// only after enqueued work that uses it has finished (host wait); otherwise st is ordered after
+// such work when that was on another stream.
 int lib_region(DeviceState &D, size_t need, Region *R, hipStream_t st) {
     if (D.ws.cap < need) {
         int rc = settle(D);
