@@ -66,6 +66,8 @@ IMG_HD constexpr int slot_words(uint32_t set, int slot, int W) {
 // words, 16 for wider ones (whose unrolled block keeps 2^KB columns of W words in registers).
 // Programs with fewer walk bits use the plain step loop.
 constexpr int kMaxInnerBits = 6;
+// the most dynamic LDS (value table and the other tables) a program's kernels may take
+constexpr unsigned kMaxDynLdsBytes = 64 * 1024;
 // slots of the table of surviving steps (4 words each: key, 64-bit step mask, 0), for blocks of
 // 2^KB steps: enough that a collision-free multiplier is found quickly for 2^KB keys
 #ifdef __HIPCC__

@@ -26,7 +26,7 @@ struct DevResult {
 #define RESULT_FLAG_OVERFLOW 2u
 
 // largest dynamic LDS a value table may take
-#define MAX_TABLE_BYTES (64 * 1024)
+#define MAX_TABLE_BYTES kMaxDynLdsBytes
 
 // largest block of the evaluation and finalise kernels
 constexpr int kMaxThreads = 256;

@@ -1647,11 +1647,19 @@ int pack_program(const IrProgram &ir_given, int max_walk_bits, PackedProgram *ou
                 img.insert(img.end(), pstep.begin(), pstep.end());
             }
         }
-        // the half tables of the form monomials (two-wave teams) follow every other LDS table
+        // the half tables of the form monomials (two-wave teams) follow every other LDS table;
+        // when they would not fit the kernels' dynamic LDS, the program is evaluated whole
+        // blocks per wave instead (the form monomials read from the image)
         H.fmh_lds = 0;
         if (H.off_fmh) {
             const size_t end_z = H.ztab_bits ? (size_t)H.ztab_lds + (4 * (size_t)zslots + (size_t)KS * W) * 4 : end_lds;
-            H.fmh_lds = (uint32_t)((end_z + 15) & ~(size_t)15);
+            const size_t at = (end_z + 15) & ~(size_t)15;
+            if (at + (16 + 2 * (size_t)H.fmh_stride) * 4 <= kMaxDynLdsBytes) {
+                H.fmh_lds = (uint32_t)at;
+            } else {
+                H.term_split = 1;
+                H.off_fmh = H.fmh_stride = H.fmh_off3 = 0;
+            }
         }
     }
     std::vector<int64_t> table((size_t)H.table_n * 4, 0);
