@@ -143,6 +143,11 @@ typedef struct {
     uint32_t n_form_monomials; /* phase monomials that the elimination turned into products of
                                  two or three affine forms */
     uint32_t n_mono_forms;    /* distinct forms of those products (at most 32) */
+    uint32_t block_sum32;     /* 1: each 2^KB-term block's terms are added in 32 bits first (the
+                                 node factors bound a block's sum below 2^31), then in 64 */
+    uint32_t team_waves;      /* waves that share each block of the walk: 2 for small programs
+                                 whose monomials are all form monomials (their per-half tables
+                                 in LDS), else 1 */
 } sim_info;
 
 /* launch shape of the evaluation kernels; zero fields take the library's choice */

@@ -80,7 +80,8 @@ class sim_info(ctypes.Structure):
                 ("ops_per_term", ctypes.c_double), ("nonzero_fraction", ctypes.c_double),
                 ("n_outer", ctypes.c_uint32), ("vanish_table_bits", ctypes.c_uint32),
                 ("n_params_given", ctypes.c_uint32), ("n_eliminated", ctypes.c_uint32),
-                ("n_form_monomials", ctypes.c_uint32), ("n_mono_forms", ctypes.c_uint32)]
+                ("n_form_monomials", ctypes.c_uint32), ("n_mono_forms", ctypes.c_uint32),
+                ("block_sum32", ctypes.c_uint32), ("team_waves", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -473,6 +473,8 @@ void fill_info(const PackedProgram &pk, double compile_seconds, uint32_t t_count
     out->n_eliminated = (uint32_t)pk.eliminated;
     out->n_form_monomials = (uint32_t)pk.n_fmono;
     out->n_mono_forms = (uint32_t)pk.n_mforms;
+    out->block_sum32 = pk.hdr.block_sum32;
+    out->team_waves = std::max<uint32_t>(1, pk.hdr.term_split);
 }
 }  // namespace
 

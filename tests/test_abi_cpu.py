@@ -70,6 +70,9 @@ def test_ir_info_kernel_sized():
     info = zx.sim_ir_info(prog.to_text())  # the 11 vanishing factors solved for
     assert info["n_params"] == 21 and info["n_factors"] == 53
     assert info["n_slices"] << info["walk_bits"] == 1 << 21
+    # 147 form monomials, all of them in LDS: two-wave teams; 53 factors allow no 32-bit sums
+    assert info["n_form_monomials"] == 147 and info["team_waves"] == 2
+    assert info["block_sum32"] == 0
 
 
 @pytest.mark.parametrize("text,frag", [

@@ -61,15 +61,16 @@ def test_form_monomials_on_wider_form_vectors(o2, factors, n_lin):
     assert gpu_value(text) == o2.evaluate(text)["canonical"]
 
 
-@pytest.mark.parametrize("seed", [3, 4])
-def test_many_form_monomials_beyond_the_lds_tables(o2, seed):
-    # about 900 form monomials: their per-half tables outgrow the kernels' LDS, so the program
-    # is evaluated whole blocks per wave with the monomials read from the image (and, below
-    # that size, the teams read them from LDS)
+@pytest.mark.parametrize("seed,team", [(3, 1), (4, 2)])
+def test_many_form_monomials_beyond_the_lds_tables(o2, seed, team):
+    # about 900 form monomials: at seed 3 (940 of them) their per-half tables outgrow the
+    # kernels' LDS, so the program is evaluated whole blocks per wave with the monomials read
+    # from the image; at seed 4 (835) the tables still fit and two-wave teams read them from LDS
     text = wl.kernel_sized_program(seed, p=19, n_factors=44, n_monomials=6000).to_text()
     info = zx.sim_ir_info(text)
     say("many form monomials", seed, info["n_form_monomials"], info["image_bytes"])
     assert info["n_form_monomials"] > 800 and info["walk_bits"] >= 6
+    assert info["team_waves"] == team
     assert gpu_value(text) == o2.evaluate(text)["canonical"]
 
 

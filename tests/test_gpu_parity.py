@@ -393,6 +393,7 @@ def test_block_sums_reach_the_int32_bound(o2, n_nodes):
     text = prog.to_text()
     info = zx.sim_ir_info(text)
     assert info["n_forms"] > 32 and info["walk_bits"] <= p - 6
+    assert info["block_sum32"] == (1 if n_nodes == 24 else 0)
     say("int32 block sums at 2^30 / 2^31", n_nodes)
     assert gpu_value(text) == oracle_value(o2, text)
 
