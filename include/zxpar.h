@@ -326,9 +326,12 @@ SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *
  * hipEvent_t created with timing that take the start and end time of the evaluation kernel
  * (not the finaliser) from its own dispatch, with no event packets of their own on the
  * stream.  Calls on one device share its scratch: an enqueued evaluation is ordered before
- * any later call on the device, on any stream (the later call's stream waits for it on the
- * device, or the host waits when the call grows the scratch).  For pipelines of many
- * evaluations without a host round trip between them. */
+ * any later call on the device.  A later call on the same stream follows it in stream order; a
+ * later call on another stream, or one that grows the scratch, first waits on the host until
+ * the device is idle (so no event is recorded per evaluation, and the stream may be destroyed
+ * after the call).  To capture enqueued evaluations into a graph, make one call on the
+ * capture stream before the capture begins.  For pipelines of many evaluations without a host
+ * round trip between them. */
 SIM_API int sim_enqueue_amplitude(const sim_program *prog, void *stream, void *ev_before, void *ev_after,
                                   sim_zomega *dev_out);
 

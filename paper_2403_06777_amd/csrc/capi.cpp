@@ -89,9 +89,10 @@ struct DeviceState {
     bool aux_ready = false;       // auxiliary streams (default priority) for concurrent batch groups
     hipStream_t aux[4];
     hipEvent_t ev_fork, ev_join[4];
-    // evaluations enqueued without waiting (sim_enqueue_amplitude) still use the scratch above
-    // until ev_pending has been reached on pending_stream
-    hipEvent_t ev_pending = nullptr;
+    // evaluations enqueued without waiting (sim_enqueue_amplitude) may still use the scratch
+    // above; the last of them went to pending_stream.  No event marks them: a recorded event
+    // costs the GPU about as much as a tenth of a small evaluation, and a stream handle kept
+    // for a later record could have been destroyed by then.
     hipStream_t pending_stream = nullptr;
     bool pending = false;
 };
@@ -104,11 +105,13 @@ constexpr int kMaxDevices = 64;
 DeviceState g_dev[kMaxDevices];
 std::mutex g_init_mu;
 
-// waits on the host for enqueued work that still uses the device's scratch (caller holds D.mu)
+// waits on the host for enqueued work that may still use the device's scratch (caller holds
+// D.mu): the whole device, since the stream it went to need not exist any more
 int settle(DeviceState &D) {
     if (!D.pending) return SIM_OK;
     D.pending = false;
-    HIP_TRY(hipEventSynchronize(D.ev_pending));
+    HIP_TRY(hipSetDevice((int)(&D - g_dev)));
+    HIP_TRY(hipDeviceSynchronize());
     return SIM_OK;
 }
 
@@ -247,16 +250,14 @@ struct Region {
     size_t cap = 0;
 };
 
-// The library's scratch for work on stream st, at least `need` bytes (device lock held): grown
-// only after enqueued work that uses it has finished (host wait); otherwise st is ordered after
-// such work when that was on another stream.
+// The library's scratch for work on stream st, at least `need` bytes (device lock held).
+// Enqueued work that may still use it is waited for on the host when the scratch grows, or when
+// that work went to another stream; on the same stream, stream order suffices.
 int lib_region(DeviceState &D, size_t need, Region *R, hipStream_t st) {
-    if (D.ws.cap < need) {
+    if (D.ws.cap < need || (D.pending && D.pending_stream != st)) {
         int rc = settle(D);
         if (rc) return rc;
         if ((rc = ensure(D.ws, need))) return rc;
-    } else if (D.pending && D.pending_stream != st) {
-        HIP_TRY(hipStreamWaitEvent(st, D.ev_pending, 0));
     }
     R->base = (char *)D.ws.ptr;
     R->cap = D.ws.cap;
@@ -616,10 +617,9 @@ int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, v
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(D->mu);
     hipStream_t st = (hipStream_t)stream;
-    if (!D->ev_pending) HIP_TRY(hipEventCreateWithFlags(&D->ev_pending, hipEventDisableTiming));
     if (P->pk.zero) {
         static const sim_zomega zero = {};
-        if (D->pending && D->pending_stream != st) HIP_TRY(hipStreamWaitEvent(st, D->ev_pending, 0));
+        if (D->pending && D->pending_stream != st && (rc = settle(*D))) return rc;
         if (ev_before) HIP_TRY(hipEventRecord((hipEvent_t)ev_before, st));
         if (ev_after) HIP_TRY(hipEventRecord((hipEvent_t)ev_after, st));
         HIP_TRY(hipMemcpyAsync(dev_out, &zero, sizeof zero, hipMemcpyHostToDevice, st));
@@ -635,7 +635,6 @@ int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, v
     HIP_TRY(launch_eval(P->pk.hdr, P->dimg, 0, P->pk.n_slices, parts, S.blocks, S.threads, st,
                         (hipEvent_t)ev_before, (hipEvent_t)ev_after));
     HIP_TRY(launch_finalize(parts, S.blocks, final_args(P->pk, false), reinterpret_cast<DevResult *>(dev_out), st));
-    HIP_TRY(hipEventRecord(D->ev_pending, st));
     D->pending = true;
     D->pending_stream = st;
     return SIM_OK;
