@@ -219,3 +219,24 @@ def test_block_sums_in_32_bits_stop_at_the_bound():
     assert a["n_forms"] > 32 and b["n_forms"] > 32 and a["n_forms"] <= 64 and b["n_forms"] <= 64
     # (the one more high parameter adds 4 / 256 to the per-slice set-up)
     assert b["ops_per_term"] - a["ops_per_term"] == pytest.approx(8 - 12 / 64 + 4 / 256, abs=1e-9)
+
+
+@pytest.mark.parametrize("n_nodes", [24, 25])
+def test_int32_block_sums_would_wrap_past_the_bound(o2, n_nodes):
+    # the block-sum bound program: a 64-term block of the low parameters sums to exactly
+    # 2^(n+6) in one coordinate (oracle), which int32 holds at n = 24 and not at n = 25, where
+    # 32-bit addition of the block's terms wraps to -2^31; the header enables 32-bit block sums
+    # exactly where they cannot wrap
+    import numpy as np
+    text = wl.block_bound_program(n_nodes).to_text()
+    block = o2.evaluate(text, first=0, count=64, terms=True)
+    assert block["raw"] == (1 << (n_nodes + 6), 0, 0, 0)
+    assert sorted(block["terms"]) == list(range(64))
+    lanes = np.array([block["terms"][t][0] for t in range(64)], dtype=np.int64)
+    assert (lanes == 1 << n_nodes).all()
+    wrapped = int(lanes.astype(np.int32).sum(dtype=np.int32))
+    fits = n_nodes + 6 <= 30
+    assert (wrapped == 1 << (n_nodes + 6)) == fits
+    if not fits:
+        assert wrapped == -(1 << 31)
+    assert zx.sim_ir_info(text)["block_sum32"] == (1 if fits else 0)

@@ -384,13 +384,7 @@ def test_block_sums_reach_the_int32_bound(o2, n_nodes):
     # block sums to 2^30 in a coordinate, the most that 32-bit block sums take; with 25 (2^31,
     # which int32 cannot hold) the header leaves them off
     p = 14
-    prog = wl.ProgramSpec(p)
-    f = prog.add_form(0, 1 << (p - 1))
-    for _ in range(n_nodes):
-        prog.nodes.append((f, 0, 1))
-    for m in range(1, 13):
-        prog.lin.append((2 * (m % 4) + 1, prog.add_form(0, (1 << (p - 1)) | (m << (p - 6)))))
-    text = prog.to_text()
+    text = wl.block_bound_program(n_nodes, p).to_text()
     info = zx.sim_ir_info(text)
     assert info["n_forms"] > 32 and info["walk_bits"] <= p - 6
     assert info["block_sum32"] == (1 if n_nodes == 24 else 0)

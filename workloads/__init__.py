@@ -25,6 +25,7 @@ from .programs import (
     block_separable_program,
     appendix_d_terms,
     weight4_phase_program,
+    block_bound_program,
 )
 
 __all__ = [
@@ -43,4 +44,5 @@ __all__ = [
     "block_separable_program",
     "appendix_d_terms",
     "weight4_phase_program",
+    "block_bound_program",
 ]

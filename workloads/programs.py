@@ -274,6 +274,21 @@ def appendix_d_terms() -> List[ProgramSpec]:
     return terms
 
 
+def block_bound_program(n_nodes: int, p: int = 14) -> ProgramSpec:
+    """n_nodes node factors 1 + w^l on the top parameter, and 12 linear terms on forms of the
+    top parameter and parameters p-6 .. p-3 (parameters below p-6 enter no form).  Where the
+    top parameter is 0, every term is 2^n_nodes times a phase that depends only on parameters
+    p-6 .. p-3, so any 64 consecutive assignments of the low parameters sum to 2^(n_nodes+6)
+    times that phase."""
+    prog = ProgramSpec(p)
+    f = prog.add_form(0, 1 << (p - 1))
+    for _ in range(n_nodes):
+        prog.nodes.append((f, 0, 1))
+    for m in range(1, 13):
+        prog.lin.append((2 * (m % 4) + 1, prog.add_form(0, (1 << (p - 1)) | (m << (p - 6)))))
+    return prog
+
+
 def weight4_phase_program(seed: int, p: int, n_nodes: int, case: str) -> ProgramSpec:
     """Programs whose linear phase terms carry weight-4 parts (coefficients 4..7) in the ways
     they can combine: `random` (many terms with coefficients 1..7, half of them on forms
