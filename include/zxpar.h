@@ -330,8 +330,11 @@ SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *
  * later call on another stream, or one that grows the scratch, first waits on the host until
  * the device is idle (so no event is recorded per evaluation, and the stream may be destroyed
  * after the call).  To capture enqueued evaluations into a graph, make one call on the
- * capture stream before the capture begins.  For pipelines of many evaluations without a host
- * round trip between them. */
+ * capture stream before the capture begins, for the program needing the most scratch; a
+ * captured evaluation keeps the scratch address of the capture, so replay the graph only
+ * while no later call has grown the device's scratch (calls on programs no larger than the
+ * captured ones do not; sim_enqueue_batch with caller-owned scratch has no such condition).
+ * For pipelines of many evaluations without a host round trip between them. */
 SIM_API int sim_enqueue_amplitude(const sim_program *prog, void *stream, void *ev_before, void *ev_after,
                                   sim_zomega *dev_out);
 

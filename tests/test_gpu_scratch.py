@@ -143,6 +143,40 @@ def test_enqueued_batch_replays_from_a_captured_graph(programs):
     zx.sim_batch_forget(buf.data_ptr())
 
 
+def test_enqueued_amplitudes_replay_from_a_captured_graph(programs):
+    # the documented recipe: after evaluations enqueued on another stream, one call on the
+    # capture stream (which waits for them), then the capture; every replay, with synchronous
+    # library calls between replays, writes the synchronous values
+    import torch
+    hs, want = programs
+    n = len(hs)
+    out = torch.zeros(72 * n, dtype=torch.uint8, device="cuda")
+    s0, s = torch.cuda.Stream(), torch.cuda.Stream()
+    for k, h in enumerate(hs):
+        zx.sim_enqueue_amplitude(h, out.data_ptr() + 72 * k, s0)
+    zx.sim_enqueue_amplitude(hs[0], out.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert zx.zomegas_from_bytes(out.cpu().numpy().tobytes(), n) == want
+    # the capture holds the programs with a value (a zero program's result is a host copy)
+    keep = [k for k in range(n) if not zx.sim_program_info(hs[k])["is_zero"]]
+    hs, want, n = [hs[k] for k in keep], [want[k] for k in keep], len(keep)
+    assert n >= 5
+    g = torch.cuda.CUDAGraph()
+    out.zero_()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        for k, h in enumerate(hs):
+            zx.sim_enqueue_amplitude(h, out.data_ptr() + 72 * k, s)
+    for rep in range(4):
+        say("amplitude graph replay", rep)
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert zx.zomegas_from_bytes(out.cpu().numpy().tobytes(), n) == want
+        assert zx.sim_eval_amplitude(hs[rep % n]) == want[rep % n]
+    del g
+
+
 def test_enqueue_needs_a_prepared_region(programs):
     import torch
     hs, want = programs
