@@ -327,14 +327,13 @@ SIM_API int sim_eval_outcomes(const sim_program *prog, size_t n, const uint8_t *
  * (not the finaliser) from its own dispatch, with no event packets of their own on the
  * stream.  Calls on one device share its scratch: an enqueued evaluation is ordered before
  * any later call on the device.  A later call on the same stream follows it in stream order; a
- * later call on another stream, or one that grows the scratch, first waits on the host until
- * the device is idle (so no event is recorded per evaluation, and the stream may be destroyed
- * after the call).  To capture enqueued evaluations into a graph, make one call on the
- * capture stream before the capture begins, for the program needing the most scratch; a
- * captured evaluation keeps the scratch address of the capture, so replay the graph only
- * while no later call has grown the device's scratch (calls on programs no larger than the
- * captured ones do not; sim_enqueue_batch with caller-owned scratch has no such condition).
- * For pipelines of many evaluations without a host round trip between them. */
+ * later call on another stream first waits on the host until the device is idle (so no event
+ * is recorded per evaluation, and the stream may be destroyed after the call).  To capture
+ * enqueued evaluations into a graph, make one call on the capture stream before the capture
+ * begins, for the program needing the most scratch (the capture cannot allocate).  Scratch
+ * buffers the library outgrows are kept until the process ends, so a captured graph stays
+ * valid whatever is evaluated later.  For pipelines of many evaluations without a host round
+ * trip between them. */
 SIM_API int sim_enqueue_amplitude(const sim_program *prog, void *stream, void *ev_before, void *ev_after,
                                   sim_zomega *dev_out);
 

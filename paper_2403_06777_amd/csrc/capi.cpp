@@ -68,6 +68,7 @@ struct DeviceState {
     int cus = 0;
     std::mutex mu;
     DevBuf ws;                    // the library's scratch region
+    std::vector<void *> ws_old;   // scratch buffers it outgrew: kept until the process ends
     DevBuf msum;                  // sim_marginal_sum: its 384-bit sums and their partials
     void *static_scratch = nullptr;  // this device's address of the fixed array (kStaticScratchBytes)
     // program images are copied on a stream of their own (non-blocking, default priority), so
@@ -251,13 +252,23 @@ struct Region {
 };
 
 // The library's scratch for work on stream st, at least `need` bytes (device lock held).
-// Enqueued work that may still use it is waited for on the host when the scratch grows, or when
-// that work went to another stream; on the same stream, stream order suffices.
+// Enqueued work on another stream that may still use it is waited for on the host; on the same
+// stream, stream order suffices.  A scratch that is too small is replaced by one at least
+// twice its size, and the old buffer is kept, never freed: enqueued work and captured graphs
+// that hold its address stay valid, and growing needs no wait.
 int lib_region(DeviceState &D, size_t need, Region *R, hipStream_t st) {
-    if (D.ws.cap < need || (D.pending && D.pending_stream != st)) {
+    if (D.pending && D.pending_stream != st) {
         int rc = settle(D);
         if (rc) return rc;
-        if ((rc = ensure(D.ws, need))) return rc;
+    }
+    if (D.ws.cap < need) {
+        void *p = nullptr;
+        const size_t cap = std::max<size_t>({need, 2 * D.ws.cap, 4096});
+        hipError_t e = hipMalloc(&p, cap);
+        if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        if (D.ws.ptr) D.ws_old.push_back(D.ws.ptr);
+        D.ws.ptr = p;
+        D.ws.cap = cap;
     }
     R->base = (char *)D.ws.ptr;
     R->cap = D.ws.cap;
@@ -628,7 +639,6 @@ int sim_enqueue_amplitude(const sim_program *P, void *stream, void *ev_before, v
     SinglePlan S;
     Region R;
     if ((rc = plan_single(*D, P, P->pk.n_slices, nullptr, &S))) return rc;
-    // growing the scratch frees the old buffer: lib_region waits for enqueued work first
     if ((rc = lib_region(*D, S.o_res, &R, st))) return rc;
     if ((rc = await_upload(P))) return rc;
     Partial *parts = (Partial *)R.base;
